@@ -1,0 +1,164 @@
+/*
+ * nlfem.h -- C ABI of the MI355X (gfx950) library that assembles the 3D P1
+ * finite-element system of the volume-constrained nonlocal Poisson problem
+ * with a constant kernel on the horizon ball, using the "fullcaps" ball
+ * approximation, and solves it by conjugate gradients.
+ *
+ * Paper: G. Chen, Y. Ma, J. Zhang, "High performance implementation of 3D FEM
+ * for nonlocal Poisson problem with different ball approximation strategies".
+ *
+ * Conventions for every entry point:
+ *   - All functions return nlfem_status; nothing throws across the ABI.
+ *   - After a failure, nlfem_last_error(ctx) holds a message (owned by the
+ *     context, valid until the next call on that context).
+ *   - "device" pointers are HIP device memory on the context's device;
+ *     "host" pointers are ordinary CPU memory.  Which one a pointer is, is
+ *     stated per argument (mesh arrays: by nlfem_mesh.mem_kind).
+ *   - The library never frees caller memory.  Plans own their internal
+ *     device buffers and free them in nlfem_plan_destroy.
+ *   - Work is issued on the context's stream; entry points that return sizes
+ *     or scalars to the host synchronise that stream.
+ */
+#ifndef NLFEM_H
+#define NLFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nlfem_ctx nlfem_ctx;
+typedef struct nlfem_plan nlfem_plan;
+
+typedef enum {
+    NLFEM_OK = 0,
+    NLFEM_E_INVALID_ARG = 1,   /* null required pointer, delta <= 0, N < 1, negative size     */
+    NLFEM_E_MESH = 2,          /* index out of range, zero-volume tet, free vertex in a T_OmegaI tet */
+    NLFEM_E_OOM = 3,           /* allocation failed or would exceed the context's HBM budget  */
+    NLFEM_E_DEVICE = 4,        /* a HIP runtime call failed                                  */
+    NLFEM_E_NOT_CONVERGED = 5, /* CG hit max_iter; x and the residual are still written     */
+    NLFEM_E_UNSUPPORTED = 6    /* a size beyond what this build handles (message says which) */
+} nlfem_status;
+
+typedef enum {
+    NLFEM_FP64 = 0,       /* every step in IEEE double                                        */
+    NLFEM_FP32_LOCAL = 1  /* per-pair inner integrals (subtet rule + Monte Carlo sums) in float;
+                             classification, sample acceptance and all global sums in double */
+} nlfem_precision;
+
+/* Tetrahedral mesh of Omega u Omega_I (Sec. 3.1: coinciding triangulations of
+ * Omega and Omega_I; P1 nodes on the boundary of Omega and in Omega_I carry the
+ * volume constraint, Sec. 3.2).                                              */
+typedef struct {
+    int64_t n_vertices, n_tets;
+    const double *coords;        /* [n_vertices][3] vertex coordinates                               */
+    const int32_t *tets;         /* [n_tets][4] 0-based vertex ids, either orientation                */
+    const uint8_t *vertex_free;  /* [n_vertices] 1 = unknown (node in open Omega), 0 = constrained    */
+    const uint8_t *tet_region;   /* optional [n_tets]: 1 = T_Omega, 0 = T_OmegaI; NULL = T_Omega iff
+                                    the tet has a free vertex                                        */
+    int32_t mem_kind;            /* 0: the arrays above are host memory; 1: device memory             */
+} nlfem_mesh;
+
+/* Method parameters (Sec. 2.1 kernel gamma = psi * indicator of B_delta(x);
+ * Sec. 4.3 fullcaps with N Monte Carlo samples per cut (point, element) pair). */
+typedef struct {
+    double delta;                /* horizon > 0                                                       */
+    double psi;                  /* kernel constant; the operator is L u = 2 int_B (u(y)-u(x)) psi dy */
+    int32_t mc_samples;          /* N >= 1 uniform samples per cut pair (exact sums for N <= 2048)    */
+    uint64_t seed;               /* Philox4x32-10 key                                                 */
+    int32_t precision;           /* nlfem_precision                                                   */
+    const uint8_t *outer_mask;   /* optional [n_tets], same memory kind as the mesh: 1 = use this tet
+                                    as an outer element (subset runs); NULL = all T_Omega tets        */
+} nlfem_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes caps the device
+ * memory the library may hold at once (0 = no cap).                          */
+nlfem_status nlfem_create(nlfem_ctx **ctx, int device, void *hip_stream, size_t hbm_budget_bytes);
+nlfem_status nlfem_destroy(nlfem_ctx *ctx);
+const char *nlfem_last_error(const nlfem_ctx *ctx);
+/* Device memory currently held by the context (plans and cached scratch).   */
+nlfem_status nlfem_memory_in_use(const nlfem_ctx *ctx, size_t *bytes);
+/* Releases cached scratch blocks the context keeps for reuse.               */
+nlfem_status nlfem_trim(nlfem_ctx *ctx);
+
+/* The library's own copies of the 4-point rule constants alpha, beta
+ * (Sec. 4.3: degree-2, 4 points, equal weights), for checks.                */
+void nlfem_rule_constants(double *alpha, double *beta);
+
+/* ---- symbolic phase ------------------------------------------------------ */
+
+/* Validates the mesh, builds the device mesh layout and a uniform-grid cell
+ * list, classifies every (outer quadrature point, tet) pair against the open
+ * ball exactly in FP64 (IN / CUT(n_in) / OUT; Def. "simplex's dividing
+ * strategy"), and builds the CSR pattern of the free rows and the sorted-key
+ * reduction plan.  Mesh and mask are read during the call only.             */
+nlfem_status nlfem_plan_create(nlfem_ctx *ctx, const nlfem_mesh *mesh, const nlfem_params *params,
+                               nlfem_plan **plan);
+
+/* Sizes for the caller's output buffers (host scalars).
+ * pair_counts[5] = number of (point, element) pairs that are IN, CUT(0),
+ * CUT(1), CUT(2), CUT(3).  workspace_bytes = device memory held by the plan. */
+nlfem_status nlfem_plan_info(const nlfem_plan *plan, int64_t *n_free, int64_t *nnz_ff,
+                             int64_t *nnz_fc, int64_t pair_counts[5], size_t *workspace_bytes);
+
+/* ---- numeric phase ------------------------------------------------------- */
+
+/* Assembles A_ff (free x free, free-renumbered), A_fc (free rows x constrained
+ * columns, original vertex ids) and b = F_h - A_fc g  (eq. modified_linear:
+ * A_h of eq. Ah over the fullcaps ball, F_h of eq. Fh with the nodal volume
+ * constraint).  Free vertices are numbered in increasing vertex id; rows and
+ * columns are sorted ascending.  All arrays are DEVICE memory owned by the
+ * caller and sized from nlfem_plan_info:
+ *   f_qp [n_tets][4] f at the 4 outer points of each tet (NULL = 0)
+ *   g_nodal [n_vertices] constraint values (only constrained ones read; NULL = 0)
+ *   ff_row_ptr [n_free+1], ff_col [nnz_ff], ff_val [nnz_ff]
+ *   fc_row_ptr [n_free+1], fc_col [nnz_fc], fc_val [nnz_fc]   (all three NULL to skip)
+ *   rhs [n_free], free_to_vertex [n_free] (NULL to skip).
+ * Deterministic: the same inputs give bitwise the same outputs.             */
+nlfem_status nlfem_assemble(nlfem_plan *plan, const double *f_qp, const double *g_nodal,
+                            int64_t *ff_row_ptr, int32_t *ff_col, double *ff_val,
+                            int64_t *fc_row_ptr, int32_t *fc_col, double *fc_val, double *rhs,
+                            int32_t *free_to_vertex);
+
+/* Unpreconditioned FP64 conjugate gradients on a CSR matrix (DEVICE arrays),
+ * x holds x0 on entry and the solution on exit.  Stops when
+ * ||r||_2 <= rtol ||b||_2 or after max_iter iterations (host scalars out).  */
+nlfem_status nlfem_cg(nlfem_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                      const double *val, const double *b, double *x, double rtol, int32_t max_iter,
+                      int32_t *iters, double *rel_residual);
+
+nlfem_status nlfem_plan_destroy(nlfem_plan *plan);
+
+/* ---- introspection for tests ---------------------------------------------
+ * Per-pair records for the outer points q in [q_begin, q_end) where q = 4 n + k
+ * indexes the k-th outer point of mesh tet n.  Each record (HOST memory) is
+ * nlfem_pair_record; pairs with class OUT are not listed.  *n_written gets the
+ * number of records; if out_cap is too small, NLFEM_E_INVALID_ARG is returned
+ * and *n_written holds the count needed.                                    */
+typedef struct {
+    int32_t q;            /* outer point id 4 n + k                                        */
+    int32_t m;            /* inner tet id                                                  */
+    int32_t cls;          /* 1 IN, 2 + n_in CUT(n_in)                                      */
+    int32_t pad;
+    double S[15];         /* moments of lambda^m over E_m n B_{delta,h}(p_q):
+                             S0, S1[0..3], S2 upper triangle 00,01,02,03,11,12,13,22,23,33 */
+} nlfem_pair_record;
+
+nlfem_status nlfem_debug_pairs(nlfem_plan *plan, int64_t q_begin, int64_t q_end,
+                               nlfem_pair_record *out, int64_t out_cap, int64_t *n_written);
+
+/* Device kernel timing of the last nlfem_assemble / nlfem_plan_create on the
+ * plan, measured with HIP events on the context's stream (milliseconds):
+ * times[0] plan total, [1] classify, [2] pattern+sort, [3] integrate,
+ * [4] reduction (G + segmented sums + rhs), [5] assemble total.             */
+nlfem_status nlfem_plan_timings(const nlfem_plan *plan, double times[6]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLFEM_H */

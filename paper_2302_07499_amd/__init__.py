@@ -1,0 +1,319 @@
+"""Python binding of libnlfem (include/nlfem.h): argument marshalling only.
+
+Every step of assembly and solve runs in the HIP library; PyTorch provides
+device memory and the stream.  Importing this module loads the in-tree
+libnlfem.so and raises if it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlfem.so")
+
+NLFEM_OK = 0
+NLFEM_E_INVALID_ARG = 1
+NLFEM_E_MESH = 2
+NLFEM_E_OOM = 3
+NLFEM_E_DEVICE = 4
+NLFEM_E_NOT_CONVERGED = 5
+NLFEM_E_UNSUPPORTED = 6
+NLFEM_FP64 = 0
+NLFEM_FP32_LOCAL = 1
+
+STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_MESH", 3: "E_OOM", 4: "E_DEVICE",
+                5: "E_NOT_CONVERGED", 6: "E_UNSUPPORTED"}
+
+
+class nlfem_mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_tets", C.c_int64), ("coords", C.c_void_p),
+                ("tets", C.c_void_p), ("vertex_free", C.c_void_p), ("tet_region", C.c_void_p),
+                ("mem_kind", C.c_int32)]
+
+
+class nlfem_params(C.Structure):
+    _fields_ = [("delta", C.c_double), ("psi", C.c_double), ("mc_samples", C.c_int32),
+                ("seed", C.c_uint64), ("precision", C.c_int32), ("outer_mask", C.c_void_p)]
+
+
+class nlfem_pair_record(C.Structure):
+    _fields_ = [("q", C.c_int32), ("m", C.c_int32), ("cls", C.c_int32), ("pad", C.c_int32),
+                ("S", C.c_double * 15)]
+
+
+EXPORTS = ["nlfem_create", "nlfem_destroy", "nlfem_last_error", "nlfem_memory_in_use", "nlfem_trim",
+           "nlfem_rule_constants", "nlfem_plan_create", "nlfem_plan_info", "nlfem_assemble", "nlfem_cg",
+           "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings"]
+
+_lib = None
+
+
+def load():
+    """Loads libnlfem.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: build it with paper_2302_07499_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i64 = C.c_int64
+    L.nlfem_create.argtypes = [C.POINTER(P), C.c_int, P, C.c_size_t]
+    L.nlfem_destroy.argtypes = [P]
+    L.nlfem_last_error.argtypes = [P]
+    L.nlfem_last_error.restype = C.c_char_p
+    L.nlfem_memory_in_use.argtypes = [P, C.POINTER(C.c_size_t)]
+    L.nlfem_trim.argtypes = [P]
+    L.nlfem_rule_constants.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.nlfem_rule_constants.restype = None
+    L.nlfem_plan_create.argtypes = [P, C.POINTER(nlfem_mesh), C.POINTER(nlfem_params), C.POINTER(P)]
+    L.nlfem_plan_info.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                                  C.POINTER(C.c_size_t)]
+    L.nlfem_assemble.argtypes = [P] * 12
+    L.nlfem_cg.argtypes = [P, i64, P, P, P, P, P, C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                           C.POINTER(C.c_double)]
+    L.nlfem_plan_destroy.argtypes = [P]
+    L.nlfem_debug_pairs.argtypes = [P, i64, i64, P, i64, C.POINTER(i64)]
+    L.nlfem_plan_timings.argtypes = [P, C.POINTER(C.c_double)]
+    for name in EXPORTS:
+        if name != "nlfem_rule_constants" and name != "nlfem_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class NlfemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st, ctx=None):
+    if st != NLFEM_OK:
+        msg = load().nlfem_last_error(ctx).decode() if ctx else ""
+        raise NlfemError(st, msg)
+
+
+# ---- thin wrappers with the C names ------------------------------------------
+
+def nlfem_create(device: int = 0, stream=None, hbm_budget_bytes: int = 0):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    ctx = C.c_void_p()
+    _check(load().nlfem_create(C.byref(ctx), device, C.c_void_p(h), hbm_budget_bytes))
+    return ctx
+
+
+def nlfem_destroy(ctx):
+    _check(load().nlfem_destroy(ctx))
+
+
+def nlfem_last_error(ctx) -> str:
+    return load().nlfem_last_error(ctx).decode()
+
+
+def nlfem_memory_in_use(ctx) -> int:
+    b = C.c_size_t()
+    _check(load().nlfem_memory_in_use(ctx, C.byref(b)), ctx)
+    return b.value
+
+
+def nlfem_trim(ctx):
+    _check(load().nlfem_trim(ctx), ctx)
+
+
+def nlfem_rule_constants():
+    a, b = C.c_double(), C.c_double()
+    load().nlfem_rule_constants(C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def nlfem_plan_create(ctx, mesh: nlfem_mesh, params: nlfem_params):
+    plan = C.c_void_p()
+    _check(load().nlfem_plan_create(ctx, C.byref(mesh), C.byref(params), C.byref(plan)), ctx)
+    return plan
+
+
+def nlfem_plan_info(plan):
+    nf, nff, nfc = C.c_int64(), C.c_int64(), C.c_int64()
+    pc = (C.c_int64 * 5)()
+    ws = C.c_size_t()
+    _check(load().nlfem_plan_info(plan, C.byref(nf), C.byref(nff), C.byref(nfc), pc, C.byref(ws)))
+    return {"n_free": nf.value, "nnz_ff": nff.value, "nnz_fc": nfc.value, "pair_counts": list(pc),
+            "workspace_bytes": ws.value}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def nlfem_assemble(plan, f_qp, g_nodal, ff_row_ptr, ff_col, ff_val, fc_row_ptr, fc_col, fc_val, rhs,
+                   free_to_vertex, ctx=None):
+    st = load().nlfem_assemble(plan, _ptr(f_qp), _ptr(g_nodal), _ptr(ff_row_ptr), _ptr(ff_col), _ptr(ff_val),
+                               _ptr(fc_row_ptr), _ptr(fc_col), _ptr(fc_val), _ptr(rhs), _ptr(free_to_vertex))
+    _check(st, ctx)
+
+
+def nlfem_cg(ctx, n, row_ptr, col, val, b, x, rtol=1e-10, max_iter=None):
+    it, rr = C.c_int32(), C.c_double()
+    st = load().nlfem_cg(ctx, n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(b), _ptr(x), rtol,
+                         n if max_iter is None else max_iter, C.byref(it), C.byref(rr))
+    if st not in (NLFEM_OK, NLFEM_E_NOT_CONVERGED):
+        _check(st, ctx)
+    return it.value, rr.value, st == NLFEM_OK
+
+
+def nlfem_plan_destroy(plan):
+    _check(load().nlfem_plan_destroy(plan))
+
+
+def nlfem_debug_pairs(plan, q_begin, q_end, ctx=None):
+    n = C.c_int64()
+    st = load().nlfem_debug_pairs(plan, q_begin, q_end, None, 0, C.byref(n))
+    if st not in (NLFEM_OK, NLFEM_E_INVALID_ARG):
+        _check(st, ctx)
+    cnt = n.value
+    buf = (nlfem_pair_record * max(cnt, 1))()
+    _check(load().nlfem_debug_pairs(plan, q_begin, q_end, C.cast(buf, C.c_void_p), cnt, C.byref(n)), ctx)
+    rec = np.ctypeslib.as_array(buf)[:cnt]
+    return {"q": rec["q"].copy(), "m": rec["m"].copy(), "cls": rec["cls"].copy(), "S": rec["S"].copy()}
+
+
+def nlfem_plan_timings(plan):
+    t = (C.c_double * 6)()
+    _check(load().nlfem_plan_timings(plan, t))
+    return list(t)
+
+
+# ---- convenience: one problem on the GPU -------------------------------------
+
+@dataclass
+class System:
+    n_free: int
+    ff_row_ptr: object
+    ff_col: object
+    ff_val: object
+    fc_row_ptr: object
+    fc_col: object
+    fc_val: object
+    rhs: object
+    free_to_vertex: object
+    info: dict
+
+
+class Device:
+    """A context bound to a torch device and its current stream."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.dev = torch.device("cuda", device)
+        self.ctx = nlfem_create(device, torch.cuda.current_stream(device), hbm_budget_bytes)
+
+    def close(self):
+        if self.ctx is not None:
+            nlfem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def to_dev(self, a, dtype):
+        return self.torch.as_tensor(np.ascontiguousarray(a)).to(self.dev, dtype=dtype)
+
+    def mesh(self, coords, tets, vertex_free, tet_region=None):
+        t = self.torch
+        keep = {"coords": self.to_dev(coords, t.float64), "tets": self.to_dev(tets, t.int32),
+                "vfree": self.to_dev(vertex_free, t.uint8),
+                "region": None if tet_region is None else self.to_dev(tet_region, t.uint8)}
+        m = nlfem_mesh(int(keep["coords"].shape[0]), int(keep["tets"].shape[0]), keep["coords"].data_ptr(),
+                       keep["tets"].data_ptr(), keep["vfree"].data_ptr(),
+                       None if keep["region"] is None else keep["region"].data_ptr(), 1)
+        return m, keep
+
+    def plan(self, coords, tets, vertex_free, delta, psi, mc_samples, seed, precision="fp64", tet_region=None,
+             outer_mask=None):
+        m, keep = self.mesh(coords, tets, vertex_free, tet_region)
+        om = None if outer_mask is None else self.to_dev(outer_mask, self.torch.uint8)
+        prm = nlfem_params(float(delta), float(psi), int(mc_samples), int(seed),
+                           NLFEM_FP32_LOCAL if precision == "fp32" else NLFEM_FP64,
+                           None if om is None else om.data_ptr())
+        plan = nlfem_plan_create(self.ctx, m, prm)
+        return Plan(self, plan)
+
+    def plan_problem(self, pb, outer_mask=None):
+        mm = pb.mesh
+        return self.plan(mm.coords, mm.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
+                         precision=pb.precision, outer_mask=outer_mask)
+
+
+class Plan:
+    def __init__(self, dev: Device, handle):
+        self.dev = dev
+        self.handle = handle
+        self.info = nlfem_plan_info(handle)
+
+    def destroy(self):
+        if self.handle is not None:
+            nlfem_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def alloc_system(self) -> System:
+        t = self.dev.torch
+        d = self.dev.dev
+        nf, nff, nfc = self.info["n_free"], self.info["nnz_ff"], self.info["nnz_fc"]
+        return System(nf, t.empty(nf + 1, dtype=t.int64, device=d), t.empty(max(nff, 1), dtype=t.int32, device=d),
+                      t.empty(max(nff, 1), dtype=t.float64, device=d), t.empty(nf + 1, dtype=t.int64, device=d),
+                      t.empty(max(nfc, 1), dtype=t.int32, device=d), t.empty(max(nfc, 1), dtype=t.float64, device=d),
+                      t.empty(max(nf, 1), dtype=t.float64, device=d), t.empty(max(nf, 1), dtype=t.int32, device=d),
+                      dict(self.info))
+
+    def assemble(self, f_qp=None, g_nodal=None, out: System | None = None) -> System:
+        t = self.dev.torch
+        sysm = out if out is not None else self.alloc_system()
+        fq = None if f_qp is None else (f_qp if isinstance(f_qp, t.Tensor) else self.dev.to_dev(f_qp, t.float64))
+        gn = None if g_nodal is None else (g_nodal if isinstance(g_nodal, t.Tensor)
+                                           else self.dev.to_dev(g_nodal, t.float64))
+        nlfem_assemble(self.handle, fq, gn, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.fc_row_ptr,
+                       sysm.fc_col, sysm.fc_val, sysm.rhs, sysm.free_to_vertex, ctx=self.dev.ctx)
+        sysm._keep = (fq, gn)
+        return sysm
+
+    def solve(self, sysm: System, rtol=1e-10, max_iter=None):
+        t = self.dev.torch
+        x = t.zeros(max(sysm.n_free, 1), dtype=t.float64, device=self.dev.dev)
+        it, rr, ok = nlfem_cg(self.dev.ctx, sysm.n_free, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.rhs, x,
+                              rtol, max_iter)
+        return x[:sysm.n_free], it, rr, ok
+
+    def timings(self):
+        return nlfem_plan_timings(self.handle)
+
+    def debug_pairs(self, q_begin, q_end):
+        return nlfem_debug_pairs(self.handle, q_begin, q_end, ctx=self.dev.ctx)
+
+
+def system_to_numpy(s: System) -> dict:
+    nf = s.n_free
+    nff, nfc = s.info["nnz_ff"], s.info["nnz_fc"]
+    return {"n_free": nf, "ff_row_ptr": s.ff_row_ptr.cpu().numpy(), "ff_col": s.ff_col[:nff].cpu().numpy(),
+            "ff_val": s.ff_val[:nff].cpu().numpy(), "fc_row_ptr": s.fc_row_ptr.cpu().numpy(),
+            "fc_col": s.fc_col[:nfc].cpu().numpy(), "fc_val": s.fc_val[:nfc].cpu().numpy(),
+            "rhs": s.rhs[:nf].cpu().numpy(), "free_to_vertex": s.free_to_vertex[:nf].cpu().numpy(),
+            "pair_counts": np.array(s.info["pair_counts"], dtype=np.int64)}

@@ -1,0 +1,767 @@
+// Host runtime behind the C ABI of include/nlfem.h: contexts with a caching
+// device allocator and an HBM budget, the symbolic plan (mesh layout, cell
+// list, classification, local vertex sets, sorted-key reduction plan, CSR
+// pattern), the numeric assembly and the CG solver loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nlfem.h"
+#include "common.hpp"
+
+using namespace nlfem;
+
+struct nlfem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;  // 0 = unlimited
+    size_t live = 0, cached = 0;
+    std::multimap<size_t, void*> cache;
+    std::unordered_map<void*, size_t> sizes;
+    std::string err;
+    size_t lds_max = 65536;
+    double* pinned = nullptr;  // host scratch for readbacks
+    int64_t* pinned_i = nullptr;
+};
+
+namespace {
+
+struct Status {
+    nlfem_status code = NLFEM_OK;
+};
+
+nlfem_status fail(nlfem_ctx* c, nlfem_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+size_t round_up(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void release_cache(nlfem_ctx* c) {
+    for (auto& kv : c->cache) hipFree(kv.second);
+    c->cache.clear();
+    c->cached = 0;
+}
+
+// returns nullptr on failure (c->err set)
+void* dalloc(nlfem_ctx* c, size_t bytes) {
+    bytes = round_up(bytes ? bytes : 1);
+    auto it = c->cache.lower_bound(bytes);
+    if (it != c->cache.end() && it->first <= 2 * bytes) {
+        void* p = it->second;
+        size_t sz = it->first;
+        c->cache.erase(it);
+        c->cached -= sz;
+        c->live += sz;
+        c->sizes[p] = sz;
+        return p;
+    }
+    if (c->budget && c->live + c->cached + bytes > c->budget) release_cache(c);
+    if (c->budget && c->live + bytes > c->budget) {
+        c->err = "HBM budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
+                 std::to_string(c->live) + " in use, budget " + std::to_string(c->budget);
+        return nullptr;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        hipGetLastError();
+        release_cache(c);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            hipGetLastError();
+            c->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+            return nullptr;
+        }
+    }
+    c->live += bytes;
+    c->sizes[p] = bytes;
+    return p;
+}
+
+void dfree(nlfem_ctx* c, void* p) {
+    if (!p) return;
+    auto it = c->sizes.find(p);
+    if (it == c->sizes.end()) return;
+    size_t sz = it->second;
+    c->sizes.erase(it);
+    c->live -= sz;
+    c->cache.emplace(sz, p);
+    c->cached += sz;
+}
+
+int bits_for(uint64_t x) {  // number of bits needed to represent values in [0, x]
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
+}
+
+int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct nlfem_plan {
+    nlfem_ctx* ctx = nullptr;
+    std::vector<void*> owned;
+    // sizes
+    int64_t V = 0, K = 0, n_free = 0, n_outer = 0, P = 0, n_rec = 0, n_rec_c = 0, n_slots = 0;
+    int64_t nnz_ff = 0, nnz_fc = 0, max_pairs = 0;
+    int umax = 0, fx_shift = 0;
+    int64_t pair_counts[5] = {0, 0, 0, 0, 0};
+    double delta = 0, psi = 0;
+    int mc = 1, precision = 0;
+    uint64_t seed = 0;
+    // device arrays
+    double *tetX = nullptr, *vol = nullptr;
+    int32_t* tets = nullptr;
+    uint8_t* region = nullptr;
+    int32_t *free_id = nullptr, *free_to_vertex = nullptr, *outer_ids = nullptr;
+    int64_t* pair_off = nullptr;
+    int32_t* pair_m = nullptr;
+    uint16_t* pair_cls = nullptr;
+    int64_t *ve_off = nullptr, *rec_off = nullptr, *trans_off = nullptr;
+    int32_t* ve_ids = nullptr;
+    uint32_t *tpos = nullptr, *perm = nullptr;
+    int64_t *seg_off = nullptr, *dest = nullptr;
+    int64_t *ff_row_ptr = nullptr, *fc_row_ptr = nullptr;
+    int32_t *ff_col = nullptr, *fc_col = nullptr;
+    double *g_buf = nullptr, *rec_val = nullptr, *rhs_f = nullptr, *fc_val_int = nullptr;
+    double times[6] = {0, 0, 0, 0, 0, 0};
+
+    template <typename Tp>
+    Tp* alloc(size_t n) {
+        void* p = dalloc(ctx, n * sizeof(Tp));
+        if (p) owned.push_back(p);
+        return (Tp*)p;
+    }
+    void release() {
+        for (void* p : owned) dfree(ctx, p);
+        owned.clear();
+    }
+};
+
+namespace {
+
+// scoped temporary device buffer
+struct Tmp {
+    nlfem_ctx* c;
+    void* p = nullptr;
+    Tmp(nlfem_ctx* c_, size_t bytes) : c(c_) { p = dalloc(c, bytes); }
+    ~Tmp() { dfree(c, p); }
+    template <typename Tp>
+    Tp* as() {
+        return (Tp*)p;
+    }
+};
+
+struct Timer {
+    hipEvent_t a, b;
+    hipStream_t s;
+    explicit Timer(hipStream_t s_) : s(s_) {
+        hipEventCreate(&a);
+        hipEventCreate(&b);
+        hipEventRecord(a, s);
+    }
+    double stop() {
+        hipEventRecord(b, s);
+        hipEventSynchronize(b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer() {
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+    }
+};
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            return fail(c, NLFEM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                                         \
+    } while (0)
+
+#define ALLOC(ptr, T, n)                                      \
+    do {                                                      \
+        ptr = pl->alloc<T>((size_t)(n));                      \
+        if (!ptr) return fail(c, NLFEM_E_OOM, c->err);        \
+    } while (0)
+
+#define TMP(name, bytes)                                       \
+    Tmp name(c, (bytes));                                      \
+    if (!name.p) return fail(c, NLFEM_E_OOM, c->err)
+
+int64_t read_i64(nlfem_ctx* c, const int64_t* dev) {
+    hipMemcpyAsync(c->pinned_i, dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    return c->pinned_i[0];
+}
+
+nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, const nlfem_params* prm) {
+    hipStream_t s = c->stream;
+    const int64_t V = mesh->n_vertices, K = mesh->n_tets;
+    pl->V = V;
+    pl->K = K;
+    Timer total(s);
+    // ---- mesh on device -------------------------------------------------
+    const double* coords = mesh->coords;
+    const int32_t* tets = mesh->tets;
+    const uint8_t* vfree = mesh->vertex_free;
+    const uint8_t* region_in = mesh->tet_region;
+    const uint8_t* mask = prm->outer_mask;
+    Tmp t_coords(c, mesh->mem_kind == 0 ? (size_t)V * 24 + 8 : 8);
+    Tmp t_vfree(c, mesh->mem_kind == 0 ? (size_t)V + 8 : 8);
+    Tmp t_region(c, (mesh->mem_kind == 0 && region_in) ? (size_t)K + 8 : 8);
+    Tmp t_mask(c, (mesh->mem_kind == 0 && mask) ? (size_t)K + 8 : 8);
+    if (!t_coords.p || !t_vfree.p || !t_region.p || !t_mask.p) return fail(c, NLFEM_E_OOM, c->err);
+    ALLOC(pl->tets, int32_t, 4 * K + 4);
+    if (mesh->mem_kind == 0) {
+        if (V) HIPCHK(hipMemcpyAsync(t_coords.p, coords, (size_t)V * 24, hipMemcpyHostToDevice, s));
+        if (V) HIPCHK(hipMemcpyAsync(t_vfree.p, vfree, (size_t)V, hipMemcpyHostToDevice, s));
+        if (K) HIPCHK(hipMemcpyAsync(pl->tets, tets, (size_t)K * 16, hipMemcpyHostToDevice, s));
+        if (region_in && K) HIPCHK(hipMemcpyAsync(t_region.p, region_in, (size_t)K, hipMemcpyHostToDevice, s));
+        if (mask && K) HIPCHK(hipMemcpyAsync(t_mask.p, mask, (size_t)K, hipMemcpyHostToDevice, s));
+        coords = t_coords.as<double>();
+        vfree = t_vfree.as<uint8_t>();
+        if (region_in) region_in = t_region.as<uint8_t>();
+        if (mask) mask = t_mask.as<uint8_t>();
+    } else {
+        if (K) HIPCHK(hipMemcpyAsync(pl->tets, tets, (size_t)K * 16, hipMemcpyDeviceToDevice, s));
+    }
+    ALLOC(pl->tetX, double, 12 * K + 12);
+    ALLOC(pl->vol, double, K + 1);
+    ALLOC(pl->region, uint8_t, K + 8);
+    TMP(t_min, (size_t)3 * K * 8 + 8);
+    TMP(t_small, 32 * sizeof(double));
+    TMP(t_err, 64);
+    HIPCHK(hipMemsetAsync(t_err.p, 0, 64, s));
+    MeshDev md{coords, pl->tets, vfree, region_in, V, K};
+    double* small = t_small.as<double>();
+    HIPCHK(launch_mesh_prep(md, pl->tetX, pl->vol, pl->region, t_min.as<double>(), small, small + 1,
+                            t_err.as<unsigned>(), s));
+    // free ids
+    ALLOC(pl->free_id, int32_t, V + 1);
+    TMP(t_fscan, (size_t)(V + 2) * 4);
+    TMP(t_scantmp, (size_t)(2 * V + 8) * 8 + scan_temp_bytes(V + 1) + scan_temp_bytes(K + 1) + 4096);
+    HIPCHK(exclusive_scan_u8_to_i32(vfree, t_fscan.as<int32_t>(), V, t_scantmp.p, s));
+    int32_t nf32 = 0;
+    HIPCHK(hipMemcpyAsync(&nf32, t_fscan.as<int32_t>() + V, 4, hipMemcpyDeviceToHost, s));
+    unsigned errbits = 0;
+    HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
+    double hs_small[8];
+    HIPCHK(hipMemcpyAsync(hs_small, small, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (errbits & ERR_INDEX) return fail(c, NLFEM_E_MESH, "tet vertex index out of range");
+    if (errbits & ERR_VOLUME) return fail(c, NLFEM_E_MESH, "zero-volume tetrahedron");
+    if (errbits & ERR_REGION) return fail(c, NLFEM_E_MESH, "free vertex in a tet marked as T_OmegaI");
+    pl->n_free = nf32;
+    const int64_t nf = pl->n_free;
+    ALLOC(pl->free_to_vertex, int32_t, nf + 1);
+    HIPCHK(launch_free_ids(vfree, t_fscan.as<int32_t>(), V, pl->free_id, pl->free_to_vertex, s));
+    // outer tets
+    TMP(t_oflags, (size_t)(K + 1) * 8);
+    TMP(t_oscan, (size_t)(K + 2) * 8);
+    HIPCHK(launch_outer_flags(pl->region, mask, K, t_oflags.as<int64_t>(), s));
+    HIPCHK(exclusive_scan_i64(t_oflags.as<int64_t>(), t_oscan.as<int64_t>(), K, t_scantmp.p, s));
+    pl->n_outer = read_i64(c, t_oscan.as<int64_t>() + K);
+    const int64_t no = pl->n_outer;
+    ALLOC(pl->outer_ids, int32_t, no + 1);
+    HIPCHK(launch_outer_compact(t_oflags.as<int64_t>(), t_oscan.as<int64_t>(), K, pl->outer_ids, s));
+    // ---- cell list --------------------------------------------------------
+    const double ext = hs_small[0];
+    Grid g;
+    double cs = ext > 0 ? ext * (1.0 + 1e-12) : 1.0;
+    double bmin[3] = {hs_small[1], hs_small[2], hs_small[3]}, bmax[3] = {hs_small[4], hs_small[5], hs_small[6]};
+    int dims[3];
+    while (true) {
+        double cells = 1;
+        for (int i = 0; i < 3; ++i) {
+            dims[i] = (int)std::floor((bmax[i] - bmin[i]) / cs) + 1;
+            if (dims[i] < 1) dims[i] = 1;
+            cells *= dims[i];
+        }
+        if (cells <= (double)(1 << 24)) break;
+        cs *= 1.25;
+    }
+    g.ox = bmin[0]; g.oy = bmin[1]; g.oz = bmin[2];
+    g.cs = cs;
+    g.nx = dims[0]; g.ny = dims[1]; g.nz = dims[2];
+    const int64_t n_cells = (int64_t)dims[0] * dims[1] * dims[2];
+    int64_t* cell_start = nullptr;
+    uint32_t* cell_tets = nullptr;
+    TMP(t_cstart, (size_t)(n_cells + 2) * 8);
+    TMP(t_ckeys, (size_t)(K + 1) * 8 * 2);
+    TMP(t_cvals, (size_t)(K + 1) * 4 * 2);
+    TMP(t_rstmp, radix_sort_temp_bytes(K + 1));
+    cell_start = t_cstart.as<int64_t>();
+    {
+        uint64_t* keys = t_ckeys.as<uint64_t>();
+        uint32_t* vals = t_cvals.as<uint32_t>();
+        HIPCHK(launch_cell_keys(t_min.as<double>(), K, g, keys, vals, s));
+        HIPCHK(radix_sort_u64_u32(keys, vals, keys + K, vals + K, K, bits_for((uint64_t)n_cells), t_rstmp.p, s));
+        HIPCHK(launch_cell_start(keys, K, n_cells, cell_start, s));
+        cell_tets = vals;
+    }
+    // ---- classification -------------------------------------------------
+    Timer tcls(s);
+    TMP(t_cnt, (size_t)(5 * no + 5) * 8);
+    TMP(t_tot, (size_t)(no + 1) * 8);
+    ALLOC(pl->pair_off, int64_t, no + 2);
+    HIPCHK(launch_classify(false, pl->tetX, pl->outer_ids, no, cell_start, cell_tets, g, prm->delta,
+                           t_cnt.as<int64_t>(), nullptr, nullptr, nullptr, s));
+    HIPCHK(launch_pair_totals(t_cnt.as<int64_t>(), no, t_tot.as<int64_t>(), s));
+    TMP(t_scan2, scan_temp_bytes(no + 1) + scan_temp_bytes(K + 1) + 4096);
+    HIPCHK(exclusive_scan_i64(t_tot.as<int64_t>(), pl->pair_off, no, t_scan2.p, s));
+    HIPCHK(reduce_max_i64(t_tot.as<int64_t>(), no, (int64_t*)(small + 8), s));
+    pl->P = read_i64(c, pl->pair_off + no);
+    pl->max_pairs = read_i64(c, (int64_t*)(small + 8));
+    const int64_t P = pl->P;
+    if (P >= (int64_t)0xFFFFFFFFll) return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 pairs in one plan");
+    ALLOC(pl->pair_m, int32_t, P + 1);
+    ALLOC(pl->pair_cls, uint16_t, P + 1);
+    HIPCHK(launch_classify(true, pl->tetX, pl->outer_ids, no, cell_start, cell_tets, g, prm->delta,
+                           t_cnt.as<int64_t>(), pl->pair_off, pl->pair_m, pl->pair_cls, s));
+    {
+        TMP(t_cc, 64);
+        HIPCHK(hipMemsetAsync(t_cc.p, 0, 64, s));
+        HIPCHK(launch_class_counts(pl->pair_cls, P, t_cc.as<unsigned long long>(), s));
+        unsigned long long cc[6];
+        HIPCHK(hipMemcpyAsync(cc, t_cc.p, sizeof cc, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < 5; ++i) pl->pair_counts[i] = (int64_t)cc[1 + i];
+    }
+    pl->times[1] = tcls.stop();
+    Timer tpat(s);
+    // ---- transposed pair order (by inner tet) ---------------------------
+    ALLOC(pl->trans_off, int64_t, K + 2);
+    ALLOC(pl->tpos, uint32_t, P + 1);
+    {
+        TMP(t_tk, (size_t)(P + 1) * 16);
+        TMP(t_tv, (size_t)(P + 1) * 8);
+        TMP(t_rs2, radix_sort_temp_bytes(P + 1));
+        uint64_t* keys = t_tk.as<uint64_t>();
+        uint32_t* vals = t_tv.as<uint32_t>();
+        HIPCHK(launch_trans_keys(pl->pair_m, P, keys, vals, s));
+        HIPCHK(radix_sort_u64_u32(keys, vals, keys + P, vals + P, P, bits_for((uint64_t)K), t_rs2.p, s));
+        HIPCHK(launch_trans_finish(keys, vals, P, K, pl->trans_off, pl->tpos, s));
+    }
+    // ---- local vertex sets and record keys -------------------------------
+    TMP(t_ucount, (size_t)(no + 1) * 8);
+    int hash_cap = (int)std::max<int64_t>(256, next_pow2(2 * (pl->max_pairs + 16)));
+    while (true) {
+        if ((size_t)hash_cap * 4 > c->lds_max)
+            return fail(c, NLFEM_E_UNSUPPORTED, "local vertex set too large for LDS");
+        HIPCHK(hipMemsetAsync(t_err.p, 0, 64, s));
+        HIPCHK(launch_pattern(false, pl->tets, pl->outer_ids, no, pl->pair_off, pl->pair_m, pl->free_id, V, nf,
+                              hash_cap, t_ucount.as<int64_t>(), nullptr, nullptr, nullptr, nullptr, nullptr,
+                              t_err.as<unsigned>(), s));
+        HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!(errbits & ERR_HASH)) break;
+        hash_cap *= 2;
+    }
+    ALLOC(pl->ve_off, int64_t, no + 2);
+    ALLOC(pl->rec_off, int64_t, no + 2);
+    HIPCHK(exclusive_scan_i64(t_ucount.as<int64_t>(), pl->ve_off, no, t_scan2.p, s));
+    HIPCHK(reduce_max_i64(t_ucount.as<int64_t>(), no, (int64_t*)(small + 8), s));
+    pl->umax = (int)read_i64(c, (int64_t*)(small + 8));
+    const int64_t ve_total = read_i64(c, pl->ve_off + no);
+    if (integrate_lds_bytes(pl->umax) > c->lds_max)
+        return fail(c, NLFEM_E_UNSUPPORTED, "ball vertex set of one outer tet too large for LDS");
+    {
+        // record counts 8 U + 4 per outer tet
+        std::vector<int64_t> dummy;
+        (void)dummy;
+    }
+    // rec counts: reuse t_tot as 8U+4
+    {
+        // compute on host from ucount (small arrays: copy)
+        std::vector<int64_t> uc(no);
+        if (no) HIPCHK(hipMemcpyAsync(uc.data(), t_ucount.p, (size_t)no * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int64_t> ro(no + 1);
+        int64_t run = 0;
+        for (int64_t i = 0; i < no; ++i) {
+            ro[i] = run;
+            run += 8 * uc[i] + 4;
+        }
+        ro[no] = run;
+        pl->n_rec_c = run;
+        HIPCHK(hipMemcpyAsync(pl->rec_off, ro.data(), (size_t)(no + 1) * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    pl->n_rec = pl->n_rec_c + 16 * K;
+    if (pl->n_rec >= (int64_t)0xFFFFFFFFll) return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 reduction records");
+    ALLOC(pl->ve_ids, int32_t, ve_total + 1);
+    const int64_t NR = pl->n_rec;
+    const uint64_t key_space = (uint64_t)nf * (uint64_t)V + (uint64_t)nf;
+    {
+        TMP(t_rk, (size_t)(NR + 1) * 16);
+        TMP(t_rv, (size_t)(NR + 1) * 8);
+        uint64_t* keys = t_rk.as<uint64_t>();
+        uint32_t* vals = t_rv.as<uint32_t>();
+        HIPCHK(launch_pattern(true, pl->tets, pl->outer_ids, no, pl->pair_off, pl->pair_m, pl->free_id, V, nf,
+                              hash_cap, t_ucount.as<int64_t>(), pl->ve_off, pl->ve_ids, pl->rec_off, keys, vals,
+                              t_err.as<unsigned>(), s));
+        HIPCHK(launch_g_keys(pl->tets, pl->region, pl->trans_off, pl->free_id, K, V, nf, pl->n_rec_c, keys, vals,
+                             s));
+        {
+            TMP(t_rs3, radix_sort_temp_bytes(NR + 1));
+            HIPCHK(radix_sort_u64_u32(keys, vals, keys + NR, vals + NR, NR, bits_for(key_space), t_rs3.p, s));
+        }
+        // slots
+        TMP(t_flags, (size_t)(NR + 1) * 8);
+        TMP(t_fsc, (size_t)(NR + 2) * 8);
+        TMP(t_scan3, scan_temp_bytes(NR + 1) + 4096);
+        HIPCHK(launch_slot_flags(keys, NR, key_space, t_flags.as<int64_t>(), s));
+        HIPCHK(exclusive_scan_i64(t_flags.as<int64_t>(), t_fsc.as<int64_t>(), NR, t_scan3.p, s));
+        pl->n_slots = read_i64(c, t_fsc.as<int64_t>() + NR);
+        const int64_t NS = pl->n_slots;
+        ALLOC(pl->seg_off, int64_t, NS + 2);
+        TMP(t_skey, (size_t)(NS + 1) * 8);
+        HIPCHK(launch_slot_emit(keys, t_fsc.as<int64_t>(), NR, key_space, pl->seg_off, t_skey.as<uint64_t>(), s));
+        if (NS == 0) HIPCHK(hipMemsetAsync(pl->seg_off, 0, 8, s));
+        // CSR pattern
+        TMP(t_isff, (size_t)(NS + 1) * 8);
+        TMP(t_isfc, (size_t)(NS + 1) * 8);
+        TMP(t_rowff, (size_t)(nf + 2) * 8);
+        TMP(t_rowfc, (size_t)(nf + 2) * 8);
+        HIPCHK(hipMemsetAsync(t_rowff.p, 0, (size_t)(nf + 2) * 8, s));
+        HIPCHK(hipMemsetAsync(t_rowfc.p, 0, (size_t)(nf + 2) * 8, s));
+        HIPCHK(launch_slot_classify(t_skey.as<uint64_t>(), NS, V, nf, pl->free_id, t_isff.as<int64_t>(),
+                                    t_isfc.as<int64_t>(), t_rowff.as<int64_t>(), t_rowfc.as<int64_t>(), s));
+        TMP(t_ffsc, (size_t)(NS + 2) * 8);
+        TMP(t_fcsc, (size_t)(NS + 2) * 8);
+        HIPCHK(exclusive_scan_i64(t_isff.as<int64_t>(), t_ffsc.as<int64_t>(), NS, t_scan3.p, s));
+        HIPCHK(exclusive_scan_i64(t_isfc.as<int64_t>(), t_fcsc.as<int64_t>(), NS, t_scan3.p, s));
+        pl->nnz_ff = read_i64(c, t_ffsc.as<int64_t>() + NS);
+        pl->nnz_fc = read_i64(c, t_fcsc.as<int64_t>() + NS);
+        ALLOC(pl->ff_row_ptr, int64_t, nf + 2);
+        ALLOC(pl->fc_row_ptr, int64_t, nf + 2);
+        ALLOC(pl->ff_col, int32_t, pl->nnz_ff + 1);
+        ALLOC(pl->fc_col, int32_t, pl->nnz_fc + 1);
+        ALLOC(pl->dest, int64_t, NS + 1);
+        HIPCHK(exclusive_scan_i64(t_rowff.as<int64_t>(), pl->ff_row_ptr, nf, t_scan3.p, s));
+        HIPCHK(exclusive_scan_i64(t_rowfc.as<int64_t>(), pl->fc_row_ptr, nf, t_scan3.p, s));
+        HIPCHK(launch_slot_dest(t_skey.as<uint64_t>(), NS, V, nf, pl->free_id, t_ffsc.as<int64_t>(),
+                                t_fcsc.as<int64_t>(), pl->nnz_ff, pl->nnz_fc, pl->dest, pl->ff_col, pl->fc_col, s));
+        ALLOC(pl->perm, uint32_t, NR + 1);
+        HIPCHK(hipMemcpyAsync(pl->perm, vals, (size_t)NR * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    pl->times[2] = tpat.stop();
+    // ---- numeric workspace -------------------------------------------------
+    ALLOC(pl->g_buf, double, 10 * P + 10);
+    ALLOC(pl->rec_val, double, NR + 1);
+    ALLOC(pl->rhs_f, double, nf + 1);
+    ALLOC(pl->fc_val_int, double, pl->nnz_fc + 1);
+    // fixed-point scale: per outer point, sum_m f_m S0 <= 4 * |M_n| * max volume
+    {
+        TMP(t_vmax, 16);
+        HIPCHK(reduce_max_i64((const int64_t*)pl->vol, K, t_vmax.as<int64_t>(), s));  // non-negative doubles
+        int64_t bitsv = read_i64(c, t_vmax.as<int64_t>());
+        double vmax;
+        std::memcpy(&vmax, &bitsv, 8);
+        double bound = 4.0 * (double)std::max<int64_t>(pl->max_pairs, 1) * vmax;
+        int e = 0;
+        std::frexp(bound, &e);  // bound < 2^e
+        pl->fx_shift = 62 - e;
+    }
+    pl->times[0] = total.stop();
+    return NLFEM_OK;
+}
+
+IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
+    IntegrateArgs a;
+    a.tetX = pl->tetX;
+    a.vol = pl->vol;
+    a.region = pl->region;
+    a.tets = pl->tets;
+    a.outer_ids = pl->outer_ids;
+    a.n_outer = pl->n_outer;
+    a.pair_off = pl->pair_off;
+    a.pair_m = pl->pair_m;
+    a.pair_cls = pl->pair_cls;
+    a.tpos = pl->tpos;
+    a.ve_off = pl->ve_off;
+    a.ve_ids = pl->ve_ids;
+    a.rec_off = pl->rec_off;
+    a.f_qp = f_qp;
+    a.delta = pl->delta;
+    a.psi = pl->psi;
+    a.mc_samples = pl->mc;
+    a.key0 = (uint32_t)(pl->seed & 0xFFFFFFFFull);
+    a.key1 = (uint32_t)(pl->seed >> 32);
+    a.fx_shift = pl->fx_shift;
+    a.umax = std::max(pl->umax, 1);
+    a.g_buf = pl->g_buf;
+    a.rec_val = pl->rec_val;
+    return a;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void nlfem_rule_constants(double* alpha, double* beta) {
+    if (alpha) *alpha = kAlpha;
+    if (beta) *beta = kBeta;
+}
+
+nlfem_status nlfem_create(nlfem_ctx** out, int device, void* hip_stream, size_t hbm_budget_bytes) {
+    if (!out) return NLFEM_E_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        hipGetLastError();
+        return NLFEM_E_DEVICE;
+    }
+    if (device < 0 || device >= n) return NLFEM_E_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return NLFEM_E_DEVICE;
+    nlfem_ctx* c = new nlfem_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = hbm_budget_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->lds_max = prop.sharedMemPerBlock;
+    if (hipHostMalloc((void**)&c->pinned, 64, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->pinned_i, 64, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return NLFEM_E_DEVICE;
+    }
+    *out = c;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_destroy(nlfem_ctx* c) {
+    if (!c) return NLFEM_E_INVALID_ARG;
+    hipStreamSynchronize(c->stream);
+    release_cache(c);
+    for (auto& kv : c->sizes) hipFree(kv.first);
+    c->sizes.clear();
+    hipHostFree(c->pinned);
+    hipHostFree(c->pinned_i);
+    delete c;
+    return NLFEM_OK;
+}
+
+const char* nlfem_last_error(const nlfem_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+nlfem_status nlfem_memory_in_use(const nlfem_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return NLFEM_E_INVALID_ARG;
+    *bytes = c->live + c->cached;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_trim(nlfem_ctx* c) {
+    if (!c) return NLFEM_E_INVALID_ARG;
+    hipStreamSynchronize(c->stream);
+    release_cache(c);
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem_params* prm, nlfem_plan** out) {
+    if (!c) return NLFEM_E_INVALID_ARG;
+    if (!out || !mesh || !prm) return fail(c, NLFEM_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (mesh->n_vertices < 0 || mesh->n_tets < 0) return fail(c, NLFEM_E_INVALID_ARG, "negative mesh size");
+    if (mesh->n_tets > 0 && (!mesh->coords || !mesh->tets || !mesh->vertex_free))
+        return fail(c, NLFEM_E_INVALID_ARG, "null mesh array");
+    if (mesh->mem_kind != 0 && mesh->mem_kind != 1) return fail(c, NLFEM_E_INVALID_ARG, "mem_kind must be 0 or 1");
+    if (!(prm->delta > 0.0) || !std::isfinite(prm->delta)) return fail(c, NLFEM_E_INVALID_ARG, "delta must be > 0");
+    if (prm->mc_samples < 1) return fail(c, NLFEM_E_INVALID_ARG, "mc_samples must be >= 1");
+    if (prm->precision != NLFEM_FP64 && prm->precision != NLFEM_FP32_LOCAL)
+        return fail(c, NLFEM_E_INVALID_ARG, "unknown precision");
+    if (mesh->n_tets >= (int64_t)1 << 31 || mesh->n_vertices >= (int64_t)1 << 31)
+        return fail(c, NLFEM_E_UNSUPPORTED, "mesh larger than 2^31 entities");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
+    nlfem_plan* pl = new nlfem_plan();
+    pl->ctx = c;
+    pl->delta = prm->delta;
+    pl->psi = prm->psi;
+    pl->mc = prm->mc_samples;
+    pl->seed = prm->seed;
+    pl->precision = prm->precision;
+    nlfem_status st = build_plan(c, pl, mesh, prm);
+    if (st != NLFEM_OK) {
+        hipStreamSynchronize(c->stream);
+        pl->release();
+        delete pl;
+        return st;
+    }
+    *out = pl;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_plan_info(const nlfem_plan* pl, int64_t* n_free, int64_t* nnz_ff, int64_t* nnz_fc,
+                             int64_t pair_counts[5], size_t* workspace_bytes) {
+    if (!pl) return NLFEM_E_INVALID_ARG;
+    if (n_free) *n_free = pl->n_free;
+    if (nnz_ff) *nnz_ff = pl->nnz_ff;
+    if (nnz_fc) *nnz_fc = pl->nnz_fc;
+    if (pair_counts)
+        for (int i = 0; i < 5; ++i) pair_counts[i] = pl->pair_counts[i];
+    if (workspace_bytes) {
+        size_t b = 0;
+        for (void* p : pl->owned) {
+            auto it = pl->ctx->sizes.find(p);
+            if (it != pl->ctx->sizes.end()) b += it->second;
+        }
+        *workspace_bytes = b;
+    }
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_assemble(nlfem_plan* pl, const double* f_qp, const double* g_nodal, int64_t* ff_row_ptr,
+                            int32_t* ff_col, double* ff_val, int64_t* fc_row_ptr, int32_t* fc_col, double* fc_val,
+                            double* rhs, int32_t* free_to_vertex) {
+    if (!pl) return NLFEM_E_INVALID_ARG;
+    nlfem_ctx* c = pl->ctx;
+    if (pl->nnz_ff > 0 && !ff_val) return fail(c, NLFEM_E_INVALID_ARG, "ff_val is required");
+    if (pl->n_free > 0 && !rhs) return fail(c, NLFEM_E_INVALID_ARG, "rhs is required");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = c->stream;
+    Timer total(s);
+    const int64_t nf = pl->n_free;
+    if (ff_row_ptr) HIPCHK(launch_copy_i64(pl->ff_row_ptr, ff_row_ptr, nf + 1, s));
+    if (ff_col) HIPCHK(launch_copy_i32(pl->ff_col, ff_col, pl->nnz_ff, s));
+    if (fc_row_ptr) HIPCHK(launch_copy_i64(pl->fc_row_ptr, fc_row_ptr, nf + 1, s));
+    if (fc_col) HIPCHK(launch_copy_i32(pl->fc_col, fc_col, pl->nnz_fc, s));
+    if (free_to_vertex) HIPCHK(launch_copy_i32(pl->free_to_vertex, free_to_vertex, nf, s));
+    IntegrateArgs a = make_args(pl, f_qp);
+    Timer tint(s);
+    HIPCHK(launch_integrate(a, pl->precision == NLFEM_FP32_LOCAL, s));
+    pl->times[3] = tint.stop();
+    Timer tred(s);
+    HIPCHK(launch_g_reduce(pl->region, pl->K, pl->trans_off, pl->g_buf, pl->n_rec_c, pl->rec_val, s));
+    HIPCHK(launch_fill_zero_f64(pl->rhs_f, nf, s));
+    double* fcv = fc_val ? fc_val : pl->fc_val_int;
+    HIPCHK(launch_segsum(pl->seg_off, pl->perm, pl->rec_val, pl->n_slots, pl->dest, pl->nnz_ff, pl->nnz_fc, ff_val, fcv,
+                         pl->rhs_f, s));
+    HIPCHK(launch_rhs_final(nf, pl->rhs_f, pl->fc_row_ptr, pl->fc_col, fcv, g_nodal, rhs, s));
+    pl->times[4] = tred.stop();
+    pl->times[5] = total.stop();
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_plan_timings(const nlfem_plan* pl, double times[6]) {
+    if (!pl || !times) return NLFEM_E_INVALID_ARG;
+    for (int i = 0; i < 6; ++i) times[i] = pl->times[i];
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_debug_pairs(nlfem_plan* pl, int64_t q_begin, int64_t q_end, nlfem_pair_record* out,
+                               int64_t out_cap, int64_t* n_written) {
+    if (!pl || !n_written) return NLFEM_E_INVALID_ARG;
+    nlfem_ctx* c = pl->ctx;
+    hipStream_t s = c->stream;
+    *n_written = 0;
+    if (q_end <= q_begin || pl->n_outer == 0) return NLFEM_OK;
+    std::vector<int32_t> oid(pl->n_outer);
+    std::vector<int64_t> poff(pl->n_outer + 1);
+    HIPCHK(hipMemcpyAsync(oid.data(), pl->outer_ids, oid.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(poff.data(), pl->pair_off, poff.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t nlo = q_begin / 4, nhi = (q_end + 3) / 4;
+    int64_t olo = std::lower_bound(oid.begin(), oid.end(), (int32_t)nlo) - oid.begin();
+    int64_t ohi = std::lower_bound(oid.begin(), oid.end(), (int32_t)std::min<int64_t>(nhi, INT32_MAX)) - oid.begin();
+    if (ohi <= olo) return NLFEM_OK;
+    int64_t slots = 4 * (poff[ohi] - poff[olo]);
+    TMP(t_S, (size_t)(slots + 1) * 15 * 8);
+    TMP(t_qm, (size_t)(slots + 1) * 3 * 4);
+    IntegrateArgs a = make_args(pl, nullptr);
+    HIPCHK(launch_debug_pairs(a, pl->precision == NLFEM_FP32_LOCAL, olo, ohi, t_S.as<double>(), t_qm.as<int32_t>(), s));
+    std::vector<double> S((size_t)slots * 15);
+    std::vector<int32_t> qm((size_t)slots * 3);
+    HIPCHK(hipMemcpyAsync(S.data(), t_S.p, S.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(qm.data(), t_qm.p, qm.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < slots; ++i) {
+        int32_t q = qm[3 * i], cl = qm[3 * i + 2];
+        if (cl == 0 || q < q_begin || q >= q_end) continue;
+        if (out && cnt < out_cap) {
+            out[cnt].q = q;
+            out[cnt].m = qm[3 * i + 1];
+            out[cnt].cls = cl;
+            out[cnt].pad = 0;
+            for (int j = 0; j < 15; ++j) out[cnt].S[j] = S[15 * i + j];
+        }
+        ++cnt;
+    }
+    *n_written = cnt;
+    if (cnt > out_cap) return fail(c, NLFEM_E_INVALID_ARG, "out_cap too small");
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_plan_destroy(nlfem_plan* pl) {
+    if (!pl) return NLFEM_E_INVALID_ARG;
+    hipStreamSynchronize(pl->ctx->stream);
+    pl->release();
+    delete pl;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_cg(nlfem_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                      const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters, double* rel_res) {
+    if (!c) return NLFEM_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!row_ptr || !col || !val || !b || !x)) || !iters || !rel_res)
+        return fail(c, NLFEM_E_INVALID_ARG, "bad CG argument");
+    *iters = 0;
+    *rel_res = 0.0;
+    if (n == 0) return NLFEM_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
+    hipStream_t s = c->stream;
+    TMP(t_v, (size_t)3 * n * 8 + 4096 + 8 * 8);
+    double* r = t_v.as<double>();
+    double* p = r + n;
+    double* Ap = p + n;
+    double* partial = Ap + n;       // 512 doubles
+    double* sc = partial + 512;     // sc[0] rr, sc[1] pAp, sc[2] rr_new, sc[3] bb
+    HIPCHK(launch_spmv(n, row_ptr, col, val, x, Ap, s));
+    HIPCHK(launch_cg_init(n, b, Ap, x, r, p, s));
+    HIPCHK(launch_dot(n, r, r, partial, sc + 0, s));
+    HIPCHK(launch_dot(n, b, b, partial, sc + 3, s));
+    double h[4];
+    HIPCHK(hipMemcpyAsync(h, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double bn = std::sqrt(h[3]);
+    if (bn == 0.0) {
+        HIPCHK(launch_fill_zero_f64(x, n, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return NLFEM_OK;
+    }
+    double rr = h[0];
+    bool conv = std::sqrt(rr) <= rtol * bn;
+    int it = 0;
+    while (!conv && it < max_iter) {
+        HIPCHK(launch_spmv(n, row_ptr, col, val, p, Ap, s));
+        HIPCHK(launch_dot(n, p, Ap, partial, sc + 1, s));
+        HIPCHK(launch_cg_xr(n, sc, x, r, p, Ap, s));
+        HIPCHK(launch_dot(n, r, r, partial, sc + 2, s));
+        HIPCHK(hipMemcpyAsync(c->pinned, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(launch_cg_p(n, sc, r, p, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rr = c->pinned[0];
+        ++it;
+        conv = std::sqrt(rr) <= rtol * bn;
+    }
+    *iters = it;
+    *rel_res = std::sqrt(rr) / bn;
+    if (!conv) return fail(c, NLFEM_E_NOT_CONVERGED, "CG did not converge");
+    return NLFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// the nlfem library.  Not part of the public C ABI (include/nlfem.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+
+namespace nlfem {
+
+// pair class codes (3 bits per outer point in the packed per-pair word)
+enum : int { C_OUT = 0, C_IN = 1, C_CUT0 = 2 };
+
+// 4-point degree-2 rule: node r has barycentric alpha on vertex r, beta on
+// the others; alpha = (5 + 3 sqrt 5) / 20, beta = (5 - sqrt 5) / 20 rounded
+// to double.
+constexpr double kAlpha = 0x1.2bbae2a27f932p-1;
+constexpr double kBeta = 0x1.1b06d1d200913p-3;
+
+// Uniform grid over tet bounding-box minimum corners (see k_plan.hip).
+struct Grid {
+    double ox, oy, oz;  // origin
+    double cs;          // cell side >= largest tet bounding-box extent
+    int nx, ny, nz;
+};
+
+// Error bits raised by device validation.
+enum : unsigned { ERR_INDEX = 1u, ERR_VOLUME = 2u, ERR_REGION = 4u, ERR_HASH = 8u, ERR_FIXED = 16u };
+
+// ---- launch wrappers (each returns the hipError_t of its launch) ----------
+// scans / sorts (k_sort.hip)
+size_t scan_temp_bytes(int64_t n);
+hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* temp,
+                              hipStream_t s);  // out[n] = total (out has n+1 entries)
+hipError_t exclusive_scan_u8_to_i32(const uint8_t* in, int32_t* out, int64_t n, void* temp,
+                                    hipStream_t s);  // out[n] = total
+size_t radix_sort_temp_bytes(int64_t n);
+// Stable LSD radix sort of (key, value) on bits [0, nbits).  Result lands in
+// keys/vals (buffers alt_* are scratch of the same size).
+hipError_t radix_sort_u64_u32(uint64_t* keys, uint32_t* vals, uint64_t* alt_keys, uint32_t* alt_vals,
+                              int64_t n, int nbits, void* temp, hipStream_t s);
+hipError_t reduce_max_i64(const int64_t* in, int64_t n, int64_t* out_dev, hipStream_t s);
+
+// plan kernels (k_plan.hip)
+struct MeshDev {
+    const double* coords;   // [V][3]
+    const int32_t* tets;    // [K][4]
+    const uint8_t* vfree;   // [V]
+    const uint8_t* region_in;  // optional
+    int64_t V, K;
+};
+hipError_t launch_mesh_prep(const MeshDev& m, double* tetX, double* vol, uint8_t* region,
+                            double* tet_min, double* ext_max_dev, double* bbox_dev,
+                            unsigned* err, hipStream_t s);
+hipError_t launch_free_ids(const uint8_t* vfree, const int32_t* scan, int64_t V, int32_t* free_id,
+                           int32_t* free_to_vertex, hipStream_t s);
+hipError_t launch_outer_flags(const uint8_t* region, const uint8_t* mask, int64_t K, int64_t* flags,
+                              hipStream_t s);
+hipError_t launch_outer_compact(const int64_t* flags, const int64_t* scan, int64_t K, int32_t* outer_ids,
+                                hipStream_t s);
+hipError_t launch_cell_keys(const double* tet_min, int64_t K, Grid g, uint64_t* keys, uint32_t* vals,
+                            hipStream_t s);
+hipError_t launch_cell_start(const uint64_t* sorted_keys, int64_t K, int64_t n_cells, int64_t* cell_start,
+                             hipStream_t s);
+// classification: count pass (fill = false) writes cnt[n_outer*5]; fill pass
+// writes pair_m / pair_cls at pair_off + bucket offsets.
+hipError_t launch_classify(bool fill, const double* tetX, const int32_t* outer_ids, int64_t n_outer,
+                           const int64_t* cell_start, const uint32_t* cell_tets, Grid g, double delta,
+                           int64_t* cnt, const int64_t* pair_off, int32_t* pair_m, uint16_t* pair_cls,
+                           hipStream_t s);
+hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s);
+// local vertex sets: count pass writes ucount[n]; fill pass writes ve_ids and record keys
+hipError_t launch_pattern(bool fill, const int32_t* tets, const int32_t* outer_ids, int64_t n_outer,
+                          const int64_t* pair_off, const int32_t* pair_m, const int32_t* free_id,
+                          int64_t V, int64_t n_free, int hash_cap, int64_t* ucount, const int64_t* ve_off,
+                          int32_t* ve_ids, const int64_t* rec_off, uint64_t* rec_keys, uint32_t* rec_vals,
+                          unsigned* err, hipStream_t s);
+hipError_t launch_g_keys(const int32_t* tets, const uint8_t* region, const int64_t* trans_off,
+                         const int32_t* free_id, int64_t K, int64_t V, int64_t n_free, int64_t rec_base,
+                         uint64_t* rec_keys, uint32_t* rec_vals, hipStream_t s);
+hipError_t launch_trans_keys(const int32_t* pair_m, int64_t P, uint64_t* keys, uint32_t* vals,
+                             hipStream_t s);
+hipError_t launch_trans_finish(const uint64_t* sorted_keys, const uint32_t* sorted_vals, int64_t P,
+                               int64_t K, int64_t* trans_off, uint32_t* tpos, hipStream_t s);
+hipError_t launch_slot_flags(const uint64_t* skeys, int64_t n, uint64_t key_space, int64_t* flags,
+                             hipStream_t s);
+// after the scan of flags: slot index per sorted record; emits seg_off and slot keys
+hipError_t launch_slot_emit(const uint64_t* skeys, const int64_t* fscan, int64_t n, uint64_t key_space,
+                            int64_t* seg_off, uint64_t* slot_key, hipStream_t s);
+hipError_t launch_slot_classify(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
+                                const int32_t* free_id, int64_t* is_ff, int64_t* is_fc, int64_t* row_ff,
+                                int64_t* row_fc, hipStream_t s);
+hipError_t launch_slot_dest(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
+                            const int32_t* free_id, const int64_t* ff_scan, const int64_t* fc_scan,
+                            int64_t nnz_ff, int64_t nnz_fc, int64_t* dest, int32_t* ff_col, int32_t* fc_col,
+                            hipStream_t s);
+
+// numeric kernels (k_numeric.hip)
+struct IntegrateArgs {
+    const double* tetX;
+    const double* vol;
+    const uint8_t* region;
+    const int32_t* tets;
+    const int32_t* outer_ids;
+    int64_t n_outer;
+    const int64_t* pair_off;
+    const int32_t* pair_m;
+    const uint16_t* pair_cls;
+    const uint32_t* tpos;
+    const int64_t* ve_off;
+    const int32_t* ve_ids;
+    const int64_t* rec_off;
+    const double* f_qp;  // may be null
+    double delta, psi;
+    int mc_samples;
+    uint32_t key0, key1;
+    int fx_shift;  // fixed-point scale 2^fx_shift
+    int umax;
+    double* g_buf;   // [P][10] at transposed positions
+    double* rec_val;
+};
+hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
+size_t integrate_lds_bytes(int umax);
+// per-pair moments of outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k,
+// out_S [slots][15], out_qm [slots][3] = (q, m, class)
+hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, int64_t o_hi, double* out_S,
+                              int32_t* out_qm, hipStream_t s);
+hipError_t launch_g_reduce(const uint8_t* region, int64_t K, const int64_t* trans_off, const double* g_buf,
+                           int64_t rec_base, double* rec_val, hipStream_t s);
+hipError_t launch_class_counts(const uint16_t* pair_cls, int64_t P, unsigned long long* counts, hipStream_t s);
+hipError_t launch_segsum(const int64_t* seg_off, const uint32_t* perm, const double* rec_val, int64_t n_slots,
+                         const int64_t* dest, int64_t nnz_ff, int64_t nnz_fc, double* ff_val, double* fc_val,
+                         double* rhs_f, hipStream_t s);
+hipError_t launch_rhs_final(int64_t n_free, const double* rhs_f, const int64_t* fc_row_ptr, const int32_t* fc_col,
+                            const double* fc_val, const double* g, double* rhs, hipStream_t s);
+hipError_t launch_fill_zero_f64(double* p, int64_t n, hipStream_t s);
+hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int64_t n, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s);
+
+// CG (k_cg.hip)
+hipError_t launch_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* x,
+                       double* y, hipStream_t s);
+hipError_t launch_dot(int64_t n, const double* a, const double* b, double* partial, double* out,
+                      hipStream_t s);
+hipError_t launch_cg_init(int64_t n, const double* b, const double* Ax, double* x, double* r, double* p,
+                          hipStream_t s);
+// x += alpha p; r -= alpha Ap with alpha = sc[0] / sc[1]
+hipError_t launch_cg_xr(int64_t n, const double* sc, double* x, double* r, const double* p, const double* Ap,
+                        hipStream_t s);
+// p = r + beta p with beta = sc[2] / sc[0]; then sc[0] = sc[2]
+hipError_t launch_cg_p(int64_t n, double* sc, const double* r, double* p, hipStream_t s);
+hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s);
+
+}  // namespace nlfem

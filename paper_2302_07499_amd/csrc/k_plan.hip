@@ -1,0 +1,563 @@
+// Symbolic phase: device mesh layout, uniform-grid cell list, exact FP64
+// ball classification of every (outer point, tet) pair, local vertex sets of
+// each outer tet, record keys of the sorted-key reduction and the CSR pattern.
+#include "device_geom.hpp"
+
+namespace nlfem {
+
+namespace {
+
+__device__ __forceinline__ unsigned long long ordered_bits(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// per tet: validate indices, gather coordinates (row-major [4][3]), volume
+// |det|/6, region, bounding-box minimum corner; global max extent and bbox.
+__global__ __launch_bounds__(256) void k_mesh_prep(MeshDev m, double* tetX, double* vol, uint8_t* region,
+                                                   double* tet_min, unsigned long long* ext_bits,
+                                                   unsigned long long* bbox_bits, unsigned* err) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m.K) return;
+    int32_t v[4];
+    bool ok = true;
+    for (int l = 0; l < 4; ++l) {
+        v[l] = m.tets[4 * e + l];
+        ok = ok && v[l] >= 0 && (int64_t)v[l] < m.V;
+    }
+    if (!ok) {
+        atomicOr(err, ERR_INDEX);
+        for (int i = 0; i < 12; ++i) tetX[12 * e + i] = 0.0;
+        vol[e] = 0.0;
+        region[e] = 0;
+        for (int i = 0; i < 3; ++i) tet_min[3 * e + i] = 0.0;
+        return;
+    }
+    double X[12];
+    for (int l = 0; l < 4; ++l)
+        for (int i = 0; i < 3; ++i) X[3 * l + i] = m.coords[3 * (int64_t)v[l] + i];
+    for (int i = 0; i < 12; ++i) tetX[12 * e + i] = X[i];
+    double V6 = fabs(orient3(X, X + 3, X + 6, X + 9)) / 6.0;
+    vol[e] = V6;
+    if (!(V6 > 0.0)) atomicOr(err, ERR_VOLUME);
+    bool anyfree = false;
+    for (int l = 0; l < 4; ++l) anyfree = anyfree || (m.vfree[v[l]] != 0);
+    uint8_t rg = m.region_in ? (m.region_in[e] ? 1 : 0) : (anyfree ? 1 : 0);
+    if (!rg && anyfree) atomicOr(err, ERR_REGION);
+    region[e] = rg;
+    double ext = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double lo = fmin(fmin(X[i], X[3 + i]), fmin(X[6 + i], X[9 + i]));
+        double hi = fmax(fmax(X[i], X[3 + i]), fmax(X[6 + i], X[9 + i]));
+        tet_min[3 * e + i] = lo;
+        ext = fmax(ext, hi - lo);
+        atomicMin(&bbox_bits[i], ordered_bits(lo));
+        atomicMax(&bbox_bits[3 + i], ordered_bits(hi));
+    }
+    atomicMax(ext_bits, ordered_bits(ext));
+}
+
+__global__ void k_init_bits(unsigned long long* ext_bits, unsigned long long* bbox_bits) {
+    *ext_bits = 0ull;
+    for (int i = 0; i < 3; ++i) {
+        bbox_bits[i] = ~0ull;
+        bbox_bits[3 + i] = 0ull;
+    }
+}
+
+__global__ void k_decode_bits(const unsigned long long* bits, int n, double* out) {
+    int i = threadIdx.x;
+    if (i < n) {
+        unsigned long long b = bits[i];
+        unsigned long long r = (b >> 63) ? (b & 0x7FFFFFFFFFFFFFFFull) : ~b;
+        out[i] = __longlong_as_double((long long)r);
+    }
+}
+
+__global__ void k_free_ids(const uint8_t* vfree, const int32_t* scan, int64_t V, int32_t* free_id,
+                           int32_t* free_to_vertex) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    if (vfree[v]) {
+        free_id[v] = scan[v];
+        free_to_vertex[scan[v]] = (int32_t)v;
+    } else {
+        free_id[v] = -1;
+    }
+}
+
+__global__ void k_outer_flags(const uint8_t* region, const uint8_t* mask, int64_t K, int64_t* flags) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    flags[e] = (region[e] && (!mask || mask[e])) ? 1 : 0;
+}
+
+__global__ void k_outer_compact(const int64_t* flags, const int64_t* scan, int64_t K, int32_t* outer_ids) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    if (flags[e]) outer_ids[scan[e]] = (int32_t)e;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double o, double cs, int n) {
+    double f = floor((x - o) / cs);
+    if (f < 0.0) return 0;
+    if (f > (double)(n - 1)) return n - 1;
+    return (int)f;
+}
+
+__global__ void k_cell_keys(const double* tet_min, int64_t K, Grid g, uint64_t* keys, uint32_t* vals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    int cx = cell_coord(tet_min[3 * e], g.ox, g.cs, g.nx);
+    int cy = cell_coord(tet_min[3 * e + 1], g.oy, g.cs, g.ny);
+    int cz = cell_coord(tet_min[3 * e + 2], g.oz, g.cs, g.nz);
+    keys[e] = (uint64_t)cx + (uint64_t)g.nx * ((uint64_t)cy + (uint64_t)g.ny * (uint64_t)cz);
+    vals[e] = (uint32_t)e;
+}
+
+// cell_start[c] = first sorted position with key >= c; cell_start[n_cells] = K
+__global__ void k_cell_start(const uint64_t* skeys, int64_t K, int64_t n_cells, int64_t* cell_start) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > K) return;
+    int64_t prev = (i == 0) ? -1 : (int64_t)skeys[i - 1];
+    int64_t cur = (i == K) ? n_cells : (int64_t)skeys[i];
+    for (int64_t c = prev + 1; c <= cur; ++c) cell_start[c] = i;
+}
+
+// One wave per outer tet: candidates from the cells covering the bounding box
+// of the four balls (expanded by one cell side for the tets' extent and one
+// cell of rounding guard), then the exact classification for each of the 4
+// outer points.  Non-OUT candidates are written grouped by how many of the 4
+// points cut them (4 first), in candidate order within a group.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
+                                                  const int64_t* cell_start, const uint32_t* cell_tets, Grid g,
+                                                  double delta, int64_t* cnt, const int64_t* pair_off,
+                                                  int32_t* pair_m, uint16_t* pair_cls) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
+    if (oi >= n_outer) return;
+    const int n = outer_ids[oi];
+    double Xn[12];
+    for (int i = 0; i < 12; ++i) Xn[i] = tetX[12 * (int64_t)n + i];
+    double P[4][3];
+    for (int k = 0; k < 4; ++k) outer_point(Xn, k, P[k]);
+    const double d2 = delta * delta;
+    double lo[3], hi[3];
+    for (int i = 0; i < 3; ++i) {
+        lo[i] = fmin(fmin(P[0][i], P[1][i]), fmin(P[2][i], P[3][i])) - delta;
+        hi[i] = fmax(fmax(P[0][i], P[1][i]), fmax(P[2][i], P[3][i])) + delta;
+    }
+    const double o[3] = {g.ox, g.oy, g.oz};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    int clo[3], chi[3];
+    for (int i = 0; i < 3; ++i) {
+        double a = floor((lo[i] - g.cs - o[i]) / g.cs) - 1.0;
+        double b = floor((hi[i] - o[i]) / g.cs) + 1.0;
+        clo[i] = (a < 0.0) ? 0 : (a > (double)(nn[i] - 1) ? nn[i] - 1 : (int)a);
+        chi[i] = (b < 0.0) ? 0 : (b > (double)(nn[i] - 1) ? nn[i] - 1 : (int)b);
+    }
+    int64_t c[5] = {0, 0, 0, 0, 0};
+    int64_t base[5] = {0, 0, 0, 0, 0};
+    if (FILL) {
+        int64_t run = pair_off[oi];
+        for (int b = 4; b >= 0; --b) {
+            base[b] = run;
+            run += cnt[oi * 5 + b];
+        }
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int cz = clo[2]; cz <= chi[2]; ++cz) {
+        for (int cy = clo[1]; cy <= chi[1]; ++cy) {
+            int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
+            int64_t beg = cell_start[row + clo[0]];
+            int64_t end = cell_start[row + chi[0] + 1];
+            for (int64_t j = beg; j < end; j += 64) {
+                int64_t idx = j + lane;
+                bool valid = idx < end;
+                uint32_t code = 0;
+                int ncut = 0;
+                bool hit = false;
+                int m = 0;
+                if (valid) {
+                    m = (int)cell_tets[idx];
+                    double X[12];
+                    for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
+                    for (int k = 0; k < 4; ++k) {
+                        double r2[4];
+                        int cl = classify(X, P[k], d2, r2);
+                        code |= (uint32_t)cl << (3 * k);
+                        hit = hit || (cl != C_OUT);
+                        ncut += (cl >= C_CUT0) ? 1 : 0;
+                    }
+                }
+                for (int b = 0; b <= 4; ++b) {
+                    bool mine = hit && ncut == b;
+                    uint64_t mask = __ballot(mine);
+                    if (FILL && mine) {
+                        int64_t pos = base[b] + c[b] + __popcll(mask & lt);
+                        pair_m[pos] = m;
+                        pair_cls[pos] = (uint16_t)code;
+                    }
+                    c[b] += __popcll(mask);
+                }
+            }
+        }
+    }
+    if (!FILL && lane == 0)
+        for (int b = 0; b < 5; ++b) cnt[oi * 5 + b] = c[b];
+}
+
+__global__ void k_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_outer) return;
+    tot[i] = cnt[5 * i] + cnt[5 * i + 1] + cnt[5 * i + 2] + cnt[5 * i + 3] + cnt[5 * i + 4];
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// One block per outer tet: the sorted set Ve of vertices of its non-OUT inner
+// tets (LDS hash set, then bitonic sort), and in the fill pass the record keys
+// of its block of the reduction: [4][U] direct rows V_n x Ve, [U][4]
+// transposed rows Ve x V_n, [4] right-hand-side rows.  Keys of rows that are
+// not free are the dummy key (sorted past every real slot).
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, const int32_t* outer_ids, int64_t n_outer,
+                                                 const int64_t* pair_off, const int32_t* pair_m, const int32_t* free_id,
+                                                 int64_t V, int64_t n_free, int hash_cap, int64_t* ucount,
+                                                 const int64_t* ve_off, int32_t* ve_ids, const int64_t* rec_off,
+                                                 uint64_t* rec_keys, uint32_t* rec_vals, unsigned* err) {
+    extern __shared__ uint32_t hs[];
+    __shared__ int sU;
+    const uint32_t EMPTY = 0xFFFFFFFFu;
+    const int64_t oi = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int i = t; i < hash_cap; i += 256) hs[i] = EMPTY;
+    if (t == 0) sU = 0;
+    __syncthreads();
+    const int64_t p0 = pair_off[oi], p1 = pair_off[oi + 1];
+    const uint32_t hmask = (uint32_t)hash_cap - 1u;
+    for (int64_t p = p0 + t; p < p1; p += 256) {
+        int m = pair_m[p];
+        for (int j = 0; j < 4; ++j) {
+            uint32_t v = (uint32_t)tets[4 * (int64_t)m + j];
+            uint32_t h = hash32(v) & hmask;
+            int probes = 0;
+            while (true) {
+                uint32_t old = atomicCAS(&hs[h], EMPTY, v);
+                if (old == EMPTY || old == v) break;
+                h = (h + 1u) & hmask;
+                if (++probes >= hash_cap) {
+                    atomicOr(err, ERR_HASH);
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= hash_cap; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < hash_cap; i += 256) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    uint32_t a = hs[i], b = hs[ixj];
+                    bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        hs[i] = b;
+                        hs[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < hash_cap; i += 256)
+        if (hs[i] != EMPTY && (i == hash_cap - 1 || hs[i + 1] == EMPTY)) sU = i + 1;
+    __syncthreads();
+    const int U = sU;
+    if (!FILL) {
+        if (t == 0) ucount[oi] = U;
+        return;
+    }
+    const int64_t vb = ve_off[oi];
+    for (int i = t; i < U; i += 256) ve_ids[vb + i] = (int32_t)hs[i];
+    const int n = outer_ids[oi];
+    int32_t vn[4], fn[4];
+    for (int j = 0; j < 4; ++j) {
+        vn[j] = tets[4 * (int64_t)n + j];
+        fn[j] = free_id[vn[j]];
+    }
+    const uint64_t dummy = (uint64_t)n_free * (uint64_t)V + (uint64_t)n_free;
+    const int64_t rb = rec_off[oi];
+    for (int r = t; r < 4 * U; r += 256) {
+        int j = r / U, i = r - j * U;
+        uint64_t key = (fn[j] >= 0) ? (uint64_t)fn[j] * (uint64_t)V + hs[i] : dummy;
+        rec_keys[rb + r] = key;
+        rec_vals[rb + r] = (uint32_t)(rb + r);
+    }
+    for (int r = t; r < 4 * U; r += 256) {
+        int i = r >> 2, j = r & 3;
+        int32_t fv = free_id[hs[i]];
+        uint64_t key = (fv >= 0) ? (uint64_t)fv * (uint64_t)V + (uint64_t)vn[j] : dummy;
+        rec_keys[rb + 4 * U + r] = key;
+        rec_vals[rb + 4 * U + r] = (uint32_t)(rb + 4 * U + r);
+    }
+    if (t < 4) {
+        uint64_t key = (fn[t] >= 0) ? (uint64_t)n_free * (uint64_t)V + (uint64_t)fn[t] : dummy;
+        rec_keys[rb + 8 * U + t] = key;
+        rec_vals[rb + 8 * U + t] = (uint32_t)(rb + 8 * U + t);
+    }
+}
+
+// G records: [K][4][4] rows V_m[a] (if free) x columns V_m[b] for the T_Omega
+// tets that occur in some ball (trans count > 0).
+__global__ void k_g_keys(const int32_t* tets, const uint8_t* region, const int64_t* trans_off, const int32_t* free_id,
+                         int64_t K, int64_t V, int64_t n_free, int64_t rec_base, uint64_t* rec_keys,
+                         uint32_t* rec_vals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= K) return;
+    const uint64_t dummy = (uint64_t)n_free * (uint64_t)V + (uint64_t)n_free;
+    bool use = region[e] && trans_off[e + 1] > trans_off[e];
+    int32_t v[4];
+    for (int j = 0; j < 4; ++j) v[j] = tets[4 * e + j];
+    for (int a = 0; a < 4; ++a) {
+        int32_t fa = free_id[v[a]];
+        for (int b = 0; b < 4; ++b) {
+            int64_t r = rec_base + 16 * e + 4 * a + b;
+            rec_keys[r] = (use && fa >= 0) ? (uint64_t)fa * (uint64_t)V + (uint64_t)v[b] : dummy;
+            rec_vals[r] = (uint32_t)r;
+        }
+    }
+}
+
+__global__ void k_trans_keys(const int32_t* pair_m, int64_t P, uint64_t* keys, uint32_t* vals) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    keys[p] = (uint64_t)pair_m[p];
+    vals[p] = (uint32_t)p;
+}
+
+__global__ void k_trans_finish(const uint64_t* skeys, const uint32_t* svals, int64_t P, int64_t K, int64_t* trans_off,
+                               uint32_t* tpos) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > P) return;
+    int64_t prev = (i == 0) ? -1 : (int64_t)skeys[i - 1];
+    int64_t cur = (i == P) ? K : (int64_t)skeys[i];
+    for (int64_t c = prev + 1; c <= cur; ++c) trans_off[c] = i;
+    if (i < P) tpos[svals[i]] = (uint32_t)i;
+}
+
+__global__ void k_slot_flags(const uint64_t* skeys, int64_t n, uint64_t key_space, int64_t* flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t k = skeys[i];
+    flags[i] = (k < key_space && (i == 0 || skeys[i - 1] != k)) ? 1 : 0;
+}
+
+__global__ void k_slot_emit(const uint64_t* skeys, const int64_t* fscan, int64_t n, uint64_t key_space,
+                            int64_t* seg_off, uint64_t* slot_key) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t k = skeys[i];
+    if (k >= key_space) return;
+    int64_t s = fscan[i];
+    if (i == 0 || skeys[i - 1] != k) {
+        seg_off[s] = i;
+        slot_key[s] = k;
+    }
+    if (i == n - 1 || skeys[i + 1] >= key_space) seg_off[fscan[n]] = i + 1;
+}
+
+__global__ void k_slot_classify(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
+                                const int32_t* free_id, int64_t* is_ff, int64_t* is_fc, int64_t* row_ff,
+                                int64_t* row_fc) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slots) return;
+    uint64_t k = slot_key[s];
+    uint64_t mat = (uint64_t)n_free * (uint64_t)V;
+    int64_t ff = 0, fc = 0;
+    if (k < mat) {
+        int64_t row = (int64_t)(k / (uint64_t)V);
+        int64_t col = (int64_t)(k - (uint64_t)row * (uint64_t)V);
+        if (free_id[col] >= 0) {
+            ff = 1;
+            atomicAdd((unsigned long long*)&row_ff[row], 1ull);
+        } else {
+            fc = 1;
+            atomicAdd((unsigned long long*)&row_fc[row], 1ull);
+        }
+    }
+    is_ff[s] = ff;
+    is_fc[s] = fc;
+}
+
+__global__ void k_slot_dest(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
+                            const int32_t* free_id, const int64_t* ff_scan, const int64_t* fc_scan, int64_t nnz_ff,
+                            int64_t nnz_fc, int64_t* dest, int32_t* ff_col, int32_t* fc_col) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slots) return;
+    uint64_t k = slot_key[s];
+    uint64_t mat = (uint64_t)n_free * (uint64_t)V;
+    if (k < mat) {
+        int64_t row = (int64_t)(k / (uint64_t)V);
+        int64_t col = (int64_t)(k - (uint64_t)row * (uint64_t)V);
+        int32_t fcid = free_id[col];
+        if (fcid >= 0) {
+            dest[s] = ff_scan[s];
+            ff_col[ff_scan[s]] = fcid;
+        } else {
+            dest[s] = nnz_ff + fc_scan[s];
+            fc_col[fc_scan[s]] = (int32_t)col;
+        }
+    } else {
+        dest[s] = nnz_ff + nnz_fc + (int64_t)(k - mat);
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_mesh_prep(const MeshDev& m, double* tetX, double* vol, uint8_t* region, double* tet_min,
+                            double* ext_max_dev, double* bbox_dev, unsigned* err, hipStream_t s) {
+    // ext_max_dev / bbox_dev: 7 doubles of output; bits scratch placed after them
+    unsigned long long* bits = (unsigned long long*)(bbox_dev + 6);
+    k_init_bits<<<1, 1, 0, s>>>(bits, bits + 1);
+    if (m.K > 0)
+        k_mesh_prep<<<blocks_for(m.K), 256, 0, s>>>(m, tetX, vol, region, tet_min, bits, bits + 1, err);
+    k_decode_bits<<<1, 64, 0, s>>>(bits, 1, ext_max_dev);
+    k_decode_bits<<<1, 64, 0, s>>>(bits + 1, 6, bbox_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_free_ids(const uint8_t* vfree, const int32_t* scan, int64_t V, int32_t* free_id,
+                           int32_t* free_to_vertex, hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    k_free_ids<<<blocks_for(V), 256, 0, s>>>(vfree, scan, V, free_id, free_to_vertex);
+    return hipGetLastError();
+}
+
+hipError_t launch_outer_flags(const uint8_t* region, const uint8_t* mask, int64_t K, int64_t* flags, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    k_outer_flags<<<blocks_for(K), 256, 0, s>>>(region, mask, K, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_outer_compact(const int64_t* flags, const int64_t* scan, int64_t K, int32_t* outer_ids,
+                                hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    k_outer_compact<<<blocks_for(K), 256, 0, s>>>(flags, scan, K, outer_ids);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_keys(const double* tet_min, int64_t K, Grid g, uint64_t* keys, uint32_t* vals,
+                            hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    k_cell_keys<<<blocks_for(K), 256, 0, s>>>(tet_min, K, g, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_start(const uint64_t* sorted_keys, int64_t K, int64_t n_cells, int64_t* cell_start,
+                             hipStream_t s) {
+    k_cell_start<<<blocks_for(K + 1), 256, 0, s>>>(sorted_keys, K, n_cells, cell_start);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(bool fill, const double* tetX, const int32_t* outer_ids, int64_t n_outer,
+                           const int64_t* cell_start, const uint32_t* cell_tets, Grid g, double delta, int64_t* cnt,
+                           const int64_t* pair_off, int32_t* pair_m, uint16_t* pair_cls, hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((n_outer + 3) / 4);
+    if (fill)
+        k_classify<true><<<nb, 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g, delta, cnt,
+                                            pair_off, pair_m, pair_cls);
+    else
+        k_classify<false><<<nb, 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g, delta, cnt,
+                                             pair_off, pair_m, pair_cls);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    k_pair_totals<<<blocks_for(n_outer), 256, 0, s>>>(cnt, n_outer, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_pattern(bool fill, const int32_t* tets, const int32_t* outer_ids, int64_t n_outer,
+                          const int64_t* pair_off, const int32_t* pair_m, const int32_t* free_id, int64_t V,
+                          int64_t n_free, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
+                          const int64_t* rec_off, uint64_t* rec_keys, uint32_t* rec_vals, unsigned* err,
+                          hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    size_t sh = (size_t)hash_cap * sizeof(uint32_t);
+    if (fill)
+        k_pattern<true><<<(unsigned)n_outer, 256, sh, s>>>(tets, outer_ids, n_outer, pair_off, pair_m, free_id, V,
+                                                          n_free, hash_cap, ucount, ve_off, ve_ids, rec_off,
+                                                          rec_keys, rec_vals, err);
+    else
+        k_pattern<false><<<(unsigned)n_outer, 256, sh, s>>>(tets, outer_ids, n_outer, pair_off, pair_m, free_id, V,
+                                                           n_free, hash_cap, ucount, ve_off, ve_ids, rec_off,
+                                                           rec_keys, rec_vals, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_g_keys(const int32_t* tets, const uint8_t* region, const int64_t* trans_off, const int32_t* free_id,
+                         int64_t K, int64_t V, int64_t n_free, int64_t rec_base, uint64_t* rec_keys,
+                         uint32_t* rec_vals, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    k_g_keys<<<blocks_for(K), 256, 0, s>>>(tets, region, trans_off, free_id, K, V, n_free, rec_base, rec_keys,
+                                           rec_vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_trans_keys(const int32_t* pair_m, int64_t P, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+    if (P <= 0) return hipSuccess;
+    k_trans_keys<<<blocks_for(P), 256, 0, s>>>(pair_m, P, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_trans_finish(const uint64_t* sorted_keys, const uint32_t* sorted_vals, int64_t P, int64_t K,
+                               int64_t* trans_off, uint32_t* tpos, hipStream_t s) {
+    k_trans_finish<<<blocks_for(P + 1), 256, 0, s>>>(sorted_keys, sorted_vals, P, K, trans_off, tpos);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_flags(const uint64_t* skeys, int64_t n, uint64_t key_space, int64_t* flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_slot_flags<<<blocks_for(n), 256, 0, s>>>(skeys, n, key_space, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_emit(const uint64_t* skeys, const int64_t* fscan, int64_t n, uint64_t key_space,
+                            int64_t* seg_off, uint64_t* slot_key, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_slot_emit<<<blocks_for(n), 256, 0, s>>>(skeys, fscan, n, key_space, seg_off, slot_key);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_classify(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
+                                const int32_t* free_id, int64_t* is_ff, int64_t* is_fc, int64_t* row_ff,
+                                int64_t* row_fc, hipStream_t s) {
+    if (n_slots <= 0) return hipSuccess;
+    k_slot_classify<<<blocks_for(n_slots), 256, 0, s>>>(slot_key, n_slots, V, n_free, free_id, is_ff, is_fc, row_ff,
+                                                        row_fc);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_dest(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
+                            const int32_t* free_id, const int64_t* ff_scan, const int64_t* fc_scan, int64_t nnz_ff,
+                            int64_t nnz_fc, int64_t* dest, int32_t* ff_col, int32_t* fc_col, hipStream_t s) {
+    if (n_slots <= 0) return hipSuccess;
+    k_slot_dest<<<blocks_for(n_slots), 256, 0, s>>>(slot_key, n_slots, V, n_free, free_id, ff_scan, fc_scan, nnz_ff,
+                                                    nnz_fc, dest, ff_col, fc_col);
+    return hipGetLastError();
+}
+
+}  // namespace nlfem

@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bars: classification, pair lists and CSR pattern bit-exact; FP64 entries
+within 1e-12 of the row scale (and 1e-12 relative on entries above 1e-6 of
+it); FP32-local entries within 1e-5 of the row scale; CG solutions within
+1e-9 relative.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _say(msg):
+    sys.stdout.write(f"[gpu-test] {msg}\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_07499_amd as P
+    d = P.Device(0)
+    yield d
+    d.close()
+
+
+def _gpu_system(dev, pb, outer_mask=None, precision=None):
+    import paper_2302_07499_amd as P
+    if precision is not None:
+        pb.precision = precision
+    _say(f"plan {pb.name} n={pb.mesh.n} K={pb.mesh.n_tets} delta={pb.delta:.5g} N={pb.mc_samples} {pb.precision}")
+    plan = dev.plan_problem(pb, outer_mask=outer_mask)
+    s = plan.assemble(pb.f_qp, pb.g_nodal)
+    return plan, s, P.system_to_numpy(s)
+
+
+@pytest.fixture(scope="module")
+def plain(dev, orc):
+    pb = mg.plain_problem()
+    plan, s, g = _gpu_system(dev, pb)
+    o = orc.problem_assemble(pb)
+    return pb, plan, s, g, o
+
+
+def test_plain_pattern_and_pair_counts(plain):
+    pb, plan, s, g, o = plain
+    assert np.array_equal(g["pair_counts"], o["pair_counts"])
+    H.pattern_equal(g, o)
+
+
+def test_plain_values_fp64(plain):
+    pb, plan, s, g, o = plain
+    e = H.value_errors(g, o)
+    _say(f"plain fp64 errors {e}")
+    assert e["ff_abs"] <= FP64_TOL and e["fc_abs"] <= FP64_TOL
+    assert e["ff_rel"] <= FP64_TOL and e["fc_rel"] <= FP64_TOL
+    assert e["rhs"] <= FP64_TOL
+
+
+def test_plain_pair_moments_match_oracle(plain, orc):
+    """Every non-OUT pair of a few outer points: same class, moments equal to
+    1e-14 relative (same samples; Monte Carlo sums are exact dyadics)."""
+    pb, plan, s, g, o = plain
+    m = pb.mesh
+    region = np.array([pb.vertex_free[t].any() for t in m.tets])
+    outer = np.nonzero(region)[0]
+    for n in outer[:: max(1, len(outer) // 6)]:
+        rec = plan.debug_pairs(4 * int(n), 4 * int(n) + 4)
+        for k in range(4):
+            cls, S = orc.point_moments(m.coords, m.tets, int(n), k, pb.delta, pb.mc_samples, pb.seed)
+            sel = rec["q"] == 4 * n + k
+            mm = rec["m"][sel]
+            order = np.argsort(mm)
+            mm = mm[order]
+            assert np.array_equal(mm, np.nonzero(cls)[0])
+            assert np.array_equal(rec["cls"][sel][order], cls[mm])
+            Sg = rec["S"][sel][order]
+            scale = np.abs(S[mm]).max(axis=1, keepdims=True)
+            assert np.max(np.abs(Sg - S[mm]) / scale) <= 1e-14
+
+
+def test_plain_invariants_and_determinism(dev, plain):
+    import paper_2302_07499_amd as P
+    pb, plan, s, g, o = plain
+    tot, mag = H.row_sums(g)
+    assert np.all(np.abs(tot) <= 1e-12 * mag)
+    A = H.dense_ff(g)
+    assert np.max(np.abs(A - A.T)) <= 1e-14 * np.abs(A).max()
+    s2 = plan.assemble(pb.f_qp, pb.g_nodal)
+    g2 = P.system_to_numpy(s2)
+    for k in ["ff_val", "fc_val", "rhs"]:
+        assert np.array_equal(g[k], g2[k]), k
+
+
+def test_plain_cg_matches_oracle(plain, orc):
+    pb, plan, s, g, o = plain
+    x, it, rr, ok = plan.solve(s, rtol=1e-10)
+    assert ok and rr <= 1e-10
+    xo, ito, rro, rc = orc.cg(o["ff_row_ptr"], o["ff_col"], o["ff_val"], o["rhs"], rtol=1e-10)
+    xg = x.cpu().numpy()
+    assert abs(it - ito) <= 1
+    assert np.max(np.abs(xg - xo)) <= 1e-9 * np.max(np.abs(xo))
+
+
+def test_plain_fp32_local(dev, plain):
+    pb, plan, s, g, o = plain
+    pb32 = mg.plain_problem()
+    plan32, s32, g32 = _gpu_system(dev, pb32, precision="fp32")
+    H.pattern_equal(g32, o)
+    e = H.value_errors(g32, o)
+    _say(f"plain fp32-local errors {e}")
+    assert e["ff_abs"] <= FP32_TOL and e["fc_abs"] <= FP32_TOL and e["rhs"] <= FP32_TOL
+
+
+@pytest.fixture(scope="module")
+def precision_subset(dev, orc):
+    """Precision workload (32^3 cubes, jitter 0.2h, delta = 3h, N = 64) on a
+    deterministic subset of about 0.15% of the outer tets."""
+    pb = mg.precision_problem()
+    mask = mg.outer_subset_mask(pb.mesh.n_tets, 0.0015, seed=11)
+    plan, s, g = _gpu_system(dev, pb, outer_mask=mask)
+    _say("oracle on the subset ...")
+    o = orc.problem_assemble(pb, outer_mask=mask)
+    return pb, mask, plan, s, g, o
+
+
+def test_precision_subset_fp64(precision_subset):
+    pb, mask, plan, s, g, o = precision_subset
+    assert np.array_equal(g["pair_counts"], o["pair_counts"])
+    H.pattern_equal(g, o)
+    e = H.value_errors(g, o)
+    _say(f"precision subset fp64 errors {e}")
+    assert e["ff_abs"] <= FP64_TOL and e["fc_abs"] <= FP64_TOL
+    assert e["ff_rel"] <= FP64_TOL and e["fc_rel"] <= FP64_TOL
+    assert e["rhs"] <= FP64_TOL
+
+
+def test_precision_subset_fp32(dev, precision_subset):
+    pb, mask, plan, s, g, o = precision_subset
+    pb32 = mg.precision_problem("fp32")
+    plan32, s32, g32 = _gpu_system(dev, pb32, outer_mask=mask)
+    H.pattern_equal(g32, o)
+    e = H.value_errors(g32, o)
+    _say(f"precision subset fp32-local errors {e}")
+    assert e["ff_abs"] <= FP32_TOL and e["fc_abs"] <= FP32_TOL and e["rhs"] <= FP32_TOL
+
+
+def test_precision_full_sampled_points(dev, orc):
+    """Full precision workload in the benchmark's configuration: pair lists and
+    moments of sampled outer points against the oracle's brute force, plus
+    A 1 = 0 and symmetry over the whole matrix."""
+    import paper_2302_07499_amd as P
+    pb = mg.precision_problem()
+    plan, s, g = _gpu_system(dev, pb)
+    tot, mag = H.row_sums(g)
+    assert np.all(np.abs(tot) <= 1e-12 * mag)
+    A = H.sparse_ff(g)
+    d = abs(A - A.T)
+    assert d.max() <= 1e-14 * abs(A).max()
+    m = pb.mesh
+    region = np.array([pb.vertex_free[t].any() for t in m.tets])
+    outer = np.nonzero(region)[0]
+    rng = np.random.default_rng(5)
+    for n in rng.choice(outer, size=3, replace=False):
+        rec = plan.debug_pairs(4 * int(n), 4 * int(n) + 4)
+        for k in range(4):
+            cls, S = orc.point_moments(m.coords, m.tets, int(n), k, pb.delta, pb.mc_samples, pb.seed)
+            sel = rec["q"] == 4 * n + k
+            mm = rec["m"][sel]
+            order = np.argsort(mm)
+            mm = mm[order]
+            assert np.array_equal(mm, np.nonzero(cls)[0])
+            assert np.array_equal(rec["cls"][sel][order], cls[mm])
+            scale = np.abs(S[mm]).max(axis=1, keepdims=True)
+            assert np.max(np.abs(rec["S"][sel][order] - S[mm]) / scale) <= 1e-14
+
+
+# ---------------------------------------------------------------- edge cases --
+def test_empty_system(dev, orc):
+    """n = 8, delta/h = 4: no free vertex -> empty system, CG returns at once."""
+    pb = mg.make_problem("empty", 8, delta_over_h=4.0, jitter=0.15, jitter_seed=3, mc_samples=8)
+    assert pb.vertex_free.sum() == 0
+    plan, s, g = _gpu_system(dev, pb)
+    assert g["n_free"] == 0 and plan.info["nnz_ff"] == 0
+    x, it, rr, ok = plan.solve(s)
+    assert ok and it == 0
+
+
+def test_single_tet_and_tiny_meshes(dev, orc):
+    import paper_2302_07499_amd as P
+    m = mg.six_tet_cube_mesh()
+    vf = np.ones(m.n_vertices, np.uint8)
+    for delta, N in [(0.3, 16), (0.5, 33), (0.8, 7)]:
+        plan = dev.plan(m.coords, m.tets, vf, delta, 1.3, N, 4)
+        g = P.system_to_numpy(plan.assemble(np.ones((6, 4)), None))
+        o = orc.assemble(m.coords, m.tets, vf, delta, 1.3, N, 4, f_qp=np.ones((6, 4)))
+        H.pattern_equal(g, o)
+        e = H.value_errors(g, o)
+        assert e["ff_abs"] <= FP64_TOL and e["rhs"] <= FP64_TOL, (delta, e)
+    t = mg.single_tet_mesh(0.5)
+    vf = np.array([1, 0, 0, 0], np.uint8)
+    plan = dev.plan(t.coords, t.tets, vf, 0.2, 2.0, 12, 1)
+    g = P.system_to_numpy(plan.assemble(None, np.arange(4.0)))
+    o = orc.assemble(t.coords, t.tets, vf, 0.2, 2.0, 12, 1, g_nodal=np.arange(4.0))
+    H.pattern_equal(g, o)
+    e = H.value_errors(g, o)
+    assert e["ff_abs"] <= FP64_TOL and e["fc_abs"] <= FP64_TOL and e["rhs"] <= FP64_TOL
+
+
+def test_error_paths(dev):
+    import paper_2302_07499_amd as P
+    m = mg.kuhn_cube_mesh(2)
+    vf = mg.free_mask_box(m.coords, 0.3)
+    with pytest.raises(P.NlfemError) as ei:
+        dev.plan(m.coords, m.tets, vf, -1.0, 1.0, 8, 0)
+    assert ei.value.status == P.NLFEM_E_INVALID_ARG
+    bad = m.tets.copy()
+    bad[3, 2] = m.n_vertices + 5
+    with pytest.raises(P.NlfemError) as ei:
+        dev.plan(m.coords, bad, vf, 0.3, 1.0, 8, 0)
+    assert ei.value.status == P.NLFEM_E_MESH
+    flat = m.coords.copy()
+    flat[m.tets[0]] = flat[m.tets[0][0]]
+    with pytest.raises(P.NlfemError) as ei:
+        dev.plan(flat, m.tets, vf, 0.3, 1.0, 8, 0)
+    assert ei.value.status == P.NLFEM_E_MESH
+    with pytest.raises(P.NlfemError) as ei:
+        dev.plan(m.coords, m.tets, vf, 0.3, 1.0, 0, 0)
+    assert ei.value.status == P.NLFEM_E_INVALID_ARG
+    tiny = P.Device(0, hbm_budget_bytes=4096)
+    with pytest.raises(P.NlfemError) as ei:
+        tiny.plan(m.coords, m.tets, vf, 0.3, 1.0, 8, 0)
+    assert ei.value.status == P.NLFEM_E_OOM
+    tiny.close()

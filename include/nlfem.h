@@ -79,6 +79,8 @@ typedef struct {
  * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes caps the device
  * memory the library may hold at once (0 = no cap).                          */
 nlfem_status nlfem_create(nlfem_ctx **ctx, int device, void *hip_stream, size_t hbm_budget_bytes);
+/* Frees the context and every device buffer it holds.  Destroy the context's
+ * plans first: a plan must not be used or destroyed after its context.      */
 nlfem_status nlfem_destroy(nlfem_ctx *ctx);
 const char *nlfem_last_error(const nlfem_ctx *ctx);
 /* Device memory currently held by the context (plans and cached scratch).   */

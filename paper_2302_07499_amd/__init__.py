@@ -6,8 +6,10 @@ libnlfem.so and raises if it is missing -- there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -73,7 +75,7 @@ def load():
     L.nlfem_plan_create.argtypes = [P, C.POINTER(nlfem_mesh), C.POINTER(nlfem_params), C.POINTER(P)]
     L.nlfem_plan_info.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                   C.POINTER(C.c_size_t)]
-    L.nlfem_assemble.argtypes = [P] * 12
+    L.nlfem_assemble.argtypes = [P] * 11
     L.nlfem_cg.argtypes = [P, i64, P, P, P, P, P, C.c_double, C.c_int32, C.POINTER(C.c_int32),
                            C.POINTER(C.c_double)]
     L.nlfem_plan_destroy.argtypes = [P]
@@ -207,8 +209,12 @@ class System:
     info: dict
 
 
+_OPEN_DEVICES = weakref.WeakSet()
+
+
 class Device:
-    """A context bound to a torch device and its current stream."""
+    """A context bound to a torch device and its current stream.  Plans made
+    from it are destroyed before the context (close(), or at interpreter exit)."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
         import torch
@@ -216,8 +222,12 @@ class Device:
         self.device = device
         self.dev = torch.device("cuda", device)
         self.ctx = nlfem_create(device, torch.cuda.current_stream(device), hbm_budget_bytes)
+        self.plans = weakref.WeakSet()
+        _OPEN_DEVICES.add(self)
 
     def close(self):
+        for p in list(self.plans):
+            p.destroy()
         if self.ctx is not None:
             nlfem_destroy(self.ctx)
             self.ctx = None
@@ -262,11 +272,12 @@ class Plan:
         self.dev = dev
         self.handle = handle
         self.info = nlfem_plan_info(handle)
+        dev.plans.add(self)
 
     def destroy(self):
-        if self.handle is not None:
+        if self.handle is not None and self.dev.ctx is not None:
             nlfem_plan_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -307,6 +318,15 @@ class Plan:
 
     def debug_pairs(self, q_begin, q_end):
         return nlfem_debug_pairs(self.handle, q_begin, q_end, ctx=self.dev.ctx)
+
+
+@atexit.register
+def _close_all():
+    for d in list(_OPEN_DEVICES):
+        try:
+            d.close()
+        except Exception:
+            pass
 
 
 def system_to_numpy(s: System) -> dict:

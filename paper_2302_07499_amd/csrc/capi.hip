@@ -328,6 +328,9 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     pl->max_pairs = read_i64(c, (int64_t*)(small + 8));
     const int64_t P = pl->P;
     if (P >= (int64_t)0xFFFFFFFFll) return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 pairs in one plan");
+    // the fine fixed-point words take < 2^48 per contribution and must not overflow 2^63
+    if (pl->max_pairs >= ((int64_t)1 << 15))
+        return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^15 interacting tets for one outer tet");
     ALLOC(pl->pair_m, int32_t, P + 1);
     ALLOC(pl->pair_cls, uint16_t, P + 1);
     HIPCHK(launch_classify(true, pl->tetX, pl->outer_ids, no, cell_start, cell_tets, g, prm->delta,
@@ -466,7 +469,8 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     ALLOC(pl->rec_val, double, NR + 1);
     ALLOC(pl->rhs_f, double, nf + 1);
     ALLOC(pl->fc_val_int, double, pl->nnz_fc + 1);
-    // fixed-point scale: per outer point, sum_m f_m S0 <= 4 * |M_n| * max volume
+    // fixed-point scale of the coarse words: per outer point, sum_m f_m S0 <= 4 |M_n| max|E|
+    // (S0 <= 2 |E_m| for one pair: subtets plus a Monte Carlo count of at most N)
     {
         TMP(t_vmax, 16);
         HIPCHK(reduce_max_i64((const int64_t*)pl->vol, K, t_vmax.as<int64_t>(), s));  // non-negative doubles

@@ -28,25 +28,46 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t 
     return lo;
 }
 
-// One workgroup per outer tet.  LDS: R [4][umax] and T0 [4] as 64-bit
-// fixed-point sums (order-independent, hence deterministic), Ve [umax].
+// Non-negative x is added to a two-word fixed-point sum: the coarse word
+// counts units of 2^-s, the fine word the remainder in units of 2^-(s+48).
+// Integer sums are order-independent, so the result is deterministic, and the
+// fine word keeps small contributions (thin cut slivers) relatively exact.
+constexpr int FX_LO_BITS = 48;
+
+__device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long long* lo, double x, double fx) {
+    const double xs = x * fx;  // exact: fx is a power of two
+    const double h = floor(xs);
+    const double r = xs - h;   // exact, in [0, 1)
+    atomicAdd(hi, (unsigned long long)h);
+    atomicAdd(lo, (unsigned long long)__double2ull_rn(r * 281474976710656.0));  // r * 2^48
+}
+
+__device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo, int shift) {
+    return (double)hi * ldexp(1.0, -shift) + (double)lo * ldexp(1.0, -(shift + FX_LO_BITS));
+}
+
+// One workgroup per outer tet.  LDS: R [4][umax] and T0 [4] as two-word
+// fixed-point sums (coarse words, then fine words), Ve [umax].
 template <typename T>
 __global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
     const int umax = a.umax;
-    unsigned long long* R = smem64;
-    unsigned long long* T0 = R + 4 * umax;
-    int32_t* ve = (int32_t*)(T0 + 4);
+    unsigned long long* R = smem64;             // coarse [4][umax]
+    unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax]
+    unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
+    unsigned long long* T0l = T0 + 4;           // fine   [4]
+    int32_t* ve = (int32_t*)(T0l + 4);
     const int64_t oi = blockIdx.x;
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
     const int U = (int)(a.ve_off[oi + 1] - vb);
     const int t = threadIdx.x;
     for (int i = t; i < U; i += 256) ve[i] = a.ve_ids[vb + i];
-    for (int i = t; i < 4 * umax; i += 256) R[i] = 0ull;
+    for (int i = t; i < 8 * umax; i += 256) R[i] = 0ull;
     if (t < 4) {
         T0[t] = 0ull;
+        T0l[t] = 0ull;
         double Xn[12];
         for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
         outer_point(Xn, t, P[t]);
@@ -75,10 +96,10 @@ __global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
             double S[15];
             pair_moments<T>(X, volm, P[k], d2, c, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k), (uint32_t)m,
                             S);
-            atomicAdd(&T0[k], (unsigned long long)__double2ull_rn((fm * S[0]) * fx));
+            fx_add(&T0[k], &T0l[k], fm * S[0], fx);
             for (int j = 0; j < 4; ++j)
                 if (lv[j] < U)  // always true: Ve holds every vertex of the pair list's tets
-                    atomicAdd(&R[k * umax + lv[j]], (unsigned long long)__double2ull_rn((fm * S[1 + j]) * fx));
+                    fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
             for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
         }
         if (omega) {
@@ -89,17 +110,17 @@ __global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
     }
     __syncthreads();
     const double pw = a.psi * w;
-    const double ifx = ldexp(1.0, -a.fx_shift);
+    const int sh = a.fx_shift;
     int32_t vn[4];
     for (int j = 0; j < 4; ++j) vn[j] = a.tets[4 * (int64_t)n + j];
     double t0[4];
-    for (int k = 0; k < 4; ++k) t0[k] = (double)T0[k] * ifx;
+    for (int k = 0; k < 4; ++k) t0[k] = fx_value(T0[k], T0l[k], sh);
     const int64_t rb = a.rec_off[oi];
     // direct rows u = V_n[j], columns Ve[i]: psi w (sum_k c_u c_v T0_k [v in V_n] - sum_k c_u R_k(v))
     for (int r = t; r < 4 * U; r += 256) {
         const int j = r / U, i = r - j * U;
         double cR = 0.0;
-        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * ((double)R[k * umax + i] * ifx);
+        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
         const int32_t v = ve[i];
         double O = 0.0;
         for (int jj = 0; jj < 4; ++jj)
@@ -111,7 +132,7 @@ __global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
     for (int r = t; r < 4 * U; r += 256) {
         const int i = r >> 2, j = r & 3;
         double cR = 0.0;
-        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * ((double)R[k * umax + i] * ifx);
+        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
         a.rec_val[rb + 4 * (int64_t)U + r] = -(pw * cR);
     }
     // load vector: sum_k w c_u f(p_k)
@@ -231,7 +252,7 @@ inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 
 }  // namespace
 
-size_t integrate_lds_bytes(int umax) { return (size_t)umax * 36 + 32; }
+size_t integrate_lds_bytes(int umax) { return (size_t)umax * 68 + 64; }
 
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;

@@ -35,7 +35,7 @@ def value_errors(g, o):
             out[blk + "_rel"] = 0.0
             continue
         d = np.abs(a - b)
-        s = sc[rows]
+        s = np.maximum(sc[rows], 1e-300)
         out[blk + "_abs"] = float(np.max(d / s))
         big = np.abs(b) > 1e-6 * s
         out[blk + "_rel"] = float(np.max(d[big] / np.abs(b[big]))) if big.any() else 0.0

@@ -87,7 +87,7 @@ def test_plain_pair_moments_match_oracle(plain, orc):
             assert np.array_equal(mm, np.nonzero(cls)[0])
             assert np.array_equal(rec["cls"][sel][order], cls[mm])
             Sg = rec["S"][sel][order]
-            scale = np.abs(S[mm]).max(axis=1, keepdims=True)
+            scale = np.maximum(np.abs(S[mm]).max(axis=1, keepdims=True), 1e-300)
             assert np.max(np.abs(Sg - S[mm]) / scale) <= 1e-14
 
 
@@ -183,7 +183,7 @@ def test_precision_full_sampled_points(dev, orc):
             mm = mm[order]
             assert np.array_equal(mm, np.nonzero(cls)[0])
             assert np.array_equal(rec["cls"][sel][order], cls[mm])
-            scale = np.abs(S[mm]).max(axis=1, keepdims=True)
+            scale = np.maximum(np.abs(S[mm]).max(axis=1, keepdims=True), 1e-300)
             assert np.max(np.abs(rec["S"][sel][order] - S[mm]) / scale) <= 1e-14
 
 

@@ -62,7 +62,7 @@ typedef struct {
 } nlfem_mesh;
 
 /* Method parameters (Sec. 2.1 kernel gamma = psi * indicator of B_delta(x);
- * Sec. 4.3 fullcaps with N Monte Carlo samples per cut (point, element) pair). */
+ * Sec. 4.2.2 fullcaps with N Monte Carlo samples per cut (point, element) pair). */
 typedef struct {
     double delta;                /* horizon > 0                                                       */
     double psi;                  /* kernel constant; the operator is L u = 2 int_B (u(y)-u(x)) psi dy */
@@ -89,7 +89,7 @@ nlfem_status nlfem_memory_in_use(const nlfem_ctx *ctx, size_t *bytes);
 nlfem_status nlfem_trim(nlfem_ctx *ctx);
 
 /* The library's own copies of the 4-point rule constants alpha, beta
- * (Sec. 4.3: degree-2, 4 points, equal weights), for checks.                */
+ * (Sec. 4.2.1: degree-2, 4 points, equal weights), for checks.                */
 void nlfem_rule_constants(double *alpha, double *beta);
 
 /* ---- symbolic phase ------------------------------------------------------ */

@@ -14,14 +14,14 @@
  *     rows and split into the free x free block A_ff and the free x
  *     constrained block A_fc, and the load vector  b = F_h - A_fc g;
  *   - the outer integral by the 4-point degree-2 rule on every T_Omega tet
- *     (Sec. 4.3, "Nocaps with Gauss Quadrature Rules");
+ *     (Sec. 4.2.1, "Nocaps with Gauss Quadrature Rules");
  *   - the inner integral over the approximate ball B_{delta,h}(p) built by
- *     the fullcaps strategy (Sec. 4.3, Algorithm "construction of fullcaps"):
+ *     the fullcaps strategy (Sec. 4.2.2, Algorithm "construction of fullcaps"):
  *     inside tets by the 4-point rule, cut tets by the 4-point rule on the
  *     subdivision T_I of conv(I u P) (Def. "simplex's dividing strategy")
  *     plus Monte Carlo over the fullcap (E - U_I) n B_delta(p);
  *   - the per-(point, element) Tuples/Pairs of the main assembly algorithm
- *     (Sec. 4.4), reduced by sort + reduce as the paper's Sec. 4.5 describes;
+ *     (Sec. 4.3), reduced by sort + reduce as the paper's Sec. 4.4 describes;
  *   - an unpreconditioned FP64 conjugate-gradient solve.
  * The ball query is brute force over every tet of the mesh (the definition
  * of the ball; the paper's breadth-first search visits the same set when the
@@ -41,7 +41,7 @@
 #define OR_CUT0 2 /* CUT with n_in inside vertices is OR_CUT0 + n_in */
 
 /* ------------------------------------------------------------------------ */
-/* 4-point degree-2 rule on a tetrahedron (Sec. 4.3: the same rule is used for
+/* 4-point degree-2 rule on a tetrahedron (Sec. 4.2.1: the same rule is used for
  * the outer and the inner integrals).  Barycentric node r has weight 1/4 and
  * coordinates alpha on vertex r, beta on the others, with
  * alpha = (5 + 3 sqrt 5)/20, beta = (5 - sqrt 5)/20.                          */
@@ -295,7 +295,7 @@ static void set_sub(cutgeom *g, int s, const double *v0, const double *v1, const
 }
 
 /* Builds T_I = subdivision of U_I = conv(I u P) and the half-space form of U_I
- * (fullcaps construction, Sec. 4.3).  P holds the m (4-m) edge points where
+ * (fullcaps construction, Sec. 4.2.2).  P holds the m (4-m) edge points where
  * the sphere crosses the edges joining inside and outside vertices.
  *  - edge point: X_a + t (X_b - X_a) with |.| = delta, the root in (0,1] of
  *    A t^2 + 2 B t + C = 0, A = |X_b-X_a|^2, B = (X_a-p).(X_b-X_a),
@@ -597,7 +597,7 @@ int or_pair_geometry(const double *coords, const int32_t *tets, int64_t n, int k
 }
 
 /* ------------------------------------------------------------------------ */
-/* Assembly (Sec. 4.4, main algorithm).                                      */
+/* Assembly (Sec. 4.3, main algorithm).                                      */
 typedef struct {
     int64_t n_vertices, n_tets;
     const double *coords;

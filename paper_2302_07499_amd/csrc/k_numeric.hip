@@ -2,7 +2,7 @@
 // tet's contributions in LDS, the inner-element terms, the sorted-key
 // segmented sums into the CSR values and the right-hand side.
 //
-// Decomposition of the pair contribution (main assembly algorithm, Sec. 4.4):
+// Decomposition of the pair contribution (main assembly algorithm, Sec. 4.3):
 // with a_u(y) = phi_(m,u)(y) - phi_(n,u)(p) and the moments S0, S1, S2 of the
 // inner tet's barycentric coordinates over E_m n B_{delta,h}(p),
 //   K_uv = f_m psi w [S2_uv - c_u S1_v - c_v S1_u + c_u c_v S0]

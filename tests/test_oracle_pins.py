@@ -20,7 +20,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 # ---------------------------------------------------------------- quadrature --
 def test_rule_constants_and_mass_identity(orc):
-    """4-point degree-2 rule (Sec. 4.3): weights 1/4; sum_r K_r/4 = 1/4 and
+    """4-point degree-2 rule (Sec. 4.2.1): weights 1/4; sum_r K_r/4 = 1/4 and
     sum_r K_r K_r^T / 4 = (1 + delta_ij)/20 (P1 mass matrix on the reference tet)."""
     a, b = orc.rule_constants()
     assert a == (5 + 3 * math.sqrt(5)) / 20 and b == (5 - math.sqrt(5)) / 20

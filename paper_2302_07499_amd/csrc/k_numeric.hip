@@ -14,6 +14,10 @@
 // tet's workgroup, G_m through a buffer ordered by inner tet.
 #include "device_geom.hpp"
 
+#ifndef NLFEM_INTEGRATE_WAVES
+#define NLFEM_INTEGRATE_WAVES 3  // minimum waves per SIMD requested for k_integrate (register cap)
+#endif
+
 namespace nlfem {
 
 namespace {
@@ -49,7 +53,7 @@ __device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long 
 // One workgroup per outer tet.  LDS: R [4][umax] and T0 [4] as two-word
 // fixed-point sums (coarse words, then fine words), Ve [umax].
 template <typename T>
-__global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a) {
+__global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
     const int umax = a.umax;

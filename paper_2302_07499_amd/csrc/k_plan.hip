@@ -124,57 +124,118 @@ __global__ void k_cell_start(const uint64_t* skeys, int64_t K, int64_t n_cells, 
     for (int64_t c = prev + 1; c <= cur; ++c) cell_start[c] = i;
 }
 
-// One wave per outer tet: candidates from the cells covering the bounding box
-// of the four balls (expanded by one cell side for the tets' extent and one
-// cell of rounding guard), then the exact classification for each of the 4
-// outer points.  Non-OUT candidates are written grouped by how many of the 4
-// points cut them (4 first), in candidate order within a group.
-template <bool FILL>
+// Candidate cells of one outer tet.  Every tet that meets one of the four
+// balls B(p_k, delta) has a point y with |y - c| < R (c = mean of the p_k,
+// R = delta + max_k |p_k - c|, inflated by 1e-7), and its bounding-box minimum
+// corner t lies within one cell side below y on every axis.  A cell row
+// (cy, cz) is visited only if the slab of possible y over that row comes
+// closer than R to c, and then only over the x cells that can hold t.  Cell
+// boundaries are widened by 1e-6 cells and one guard cell on each end of a
+// range absorbs rounding of the cell index, so the candidate set contains
+// every tet that the exact test can find.
+struct CandBall {
+    double c[3];
+    double R;
+};
+
+__device__ __forceinline__ CandBall cand_ball(const double P[4][3], double delta) {
+    CandBall b;
+    for (int i = 0; i < 3; ++i) b.c[i] = 0.25 * ((P[0][i] + P[1][i]) + (P[2][i] + P[3][i]));
+    double r = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double dx = P[k][0] - b.c[0], dy = P[k][1] - b.c[1], dz = P[k][2] - b.c[2];
+        r = fmax(r, sqrt((dx * dx + dy * dy) + dz * dz));
+    }
+    b.R = (delta + r) * (1.0 + 1e-7);
+    return b;
+}
+
+__device__ __forceinline__ int clampi(double v, int n) { return v < 0.0 ? 0 : (v > (double)(n - 1) ? n - 1 : (int)v); }
+
+__device__ __forceinline__ double slab_gap(double c, double o, double cs, int cidx) {
+    const double m = 1e-6 * cs;
+    const double lo = o + (double)cidx * cs - m, hi = o + (double)(cidx + 2) * cs + m;
+    return fmax(fmax(lo - c, c - hi), 0.0);
+}
+
+// range of cell rows along one axis
+__device__ __forceinline__ void axis_range(const CandBall& b, int ax, const Grid& g, int& lo, int& hi) {
+    const double o = ax == 0 ? g.ox : (ax == 1 ? g.oy : g.oz);
+    const int n = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+    lo = clampi(floor((b.c[ax] - b.R - g.cs - o) / g.cs) - 1.0, n);
+    hi = clampi(floor((b.c[ax] + b.R - o) / g.cs) + 1.0, n);
+}
+
+// x cells of row (cy, cz); returns false if the row is skipped
+__device__ __forceinline__ bool row_range(const CandBall& b, const Grid& g, int cy, int cz, int& x0, int& x1) {
+    const double dy = slab_gap(b.c[1], g.oy, g.cs, cy);
+    const double dz = slab_gap(b.c[2], g.oz, g.cs, cz);
+    const double rem = b.R * b.R - (dy * dy + dz * dz);
+    if (!(rem > 0.0)) return false;
+    const double hw = sqrt(rem);
+    x0 = clampi(floor((b.c[0] - hw - g.cs - g.ox) / g.cs) - 1.0, g.nx);
+    x1 = clampi(floor((b.c[0] + hw - g.ox) / g.cs) + 1.0, g.nx);
+    return true;
+}
+
+__device__ __forceinline__ void load_outer_points(const double* tetX, int n, double P[4][3]) {
+    double Xn[12];
+    for (int i = 0; i < 12; ++i) Xn[i] = tetX[12 * (int64_t)n + i];
+    for (int k = 0; k < 4; ++k) outer_point(Xn, k, P[k]);
+}
+
+// candidates per outer tet (an upper bound of its pair count)
+__global__ void k_cand_count(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
+                             Grid g, double delta, int64_t* cand) {
+    const int64_t oi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (oi >= n_outer) return;
+    double P[4][3];
+    load_outer_points(tetX, outer_ids[oi], P);
+    const CandBall b = cand_ball(P, delta);
+    int y0, y1, z0, z1;
+    axis_range(b, 1, g, y0, y1);
+    axis_range(b, 2, g, z0, z1);
+    int64_t tot = 0;
+    for (int cz = z0; cz <= z1; ++cz)
+        for (int cy = y0; cy <= y1; ++cy) {
+            int x0, x1;
+            if (!row_range(b, g, cy, cz, x0, x1)) continue;
+            const int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
+            tot += cell_start[row + x1 + 1] - cell_start[row + x0];
+        }
+    cand[oi] = tot;
+}
+
+// One wave per outer tet: exact classification of every candidate for the
+// four outer points; hits go to the tet's candidate region in candidate
+// order, with their count per "number of cut points" bucket.
 __global__ __launch_bounds__(256) void k_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                                                   const int64_t* cell_start, const uint32_t* cell_tets, Grid g,
-                                                  double delta, int64_t* cnt, const int64_t* pair_off,
-                                                  int32_t* pair_m, uint16_t* pair_cls) {
+                                                  double delta, const int64_t* cand_off, int64_t* cnt, int32_t* hit_m,
+                                                  uint16_t* hit_cls) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
-    const int n = outer_ids[oi];
-    double Xn[12];
-    for (int i = 0; i < 12; ++i) Xn[i] = tetX[12 * (int64_t)n + i];
     double P[4][3];
-    for (int k = 0; k < 4; ++k) outer_point(Xn, k, P[k]);
+    load_outer_points(tetX, outer_ids[oi], P);
     const double d2 = delta * delta;
-    double lo[3], hi[3];
-    for (int i = 0; i < 3; ++i) {
-        lo[i] = fmin(fmin(P[0][i], P[1][i]), fmin(P[2][i], P[3][i])) - delta;
-        hi[i] = fmax(fmax(P[0][i], P[1][i]), fmax(P[2][i], P[3][i])) + delta;
-    }
-    const double o[3] = {g.ox, g.oy, g.oz};
-    const int nn[3] = {g.nx, g.ny, g.nz};
-    int clo[3], chi[3];
-    for (int i = 0; i < 3; ++i) {
-        double a = floor((lo[i] - g.cs - o[i]) / g.cs) - 1.0;
-        double b = floor((hi[i] - o[i]) / g.cs) + 1.0;
-        clo[i] = (a < 0.0) ? 0 : (a > (double)(nn[i] - 1) ? nn[i] - 1 : (int)a);
-        chi[i] = (b < 0.0) ? 0 : (b > (double)(nn[i] - 1) ? nn[i] - 1 : (int)b);
-    }
-    int64_t c[5] = {0, 0, 0, 0, 0};
-    int64_t base[5] = {0, 0, 0, 0, 0};
-    if (FILL) {
-        int64_t run = pair_off[oi];
-        for (int b = 4; b >= 0; --b) {
-            base[b] = run;
-            run += cnt[oi * 5 + b];
-        }
-    }
+    const CandBall b = cand_ball(P, delta);
+    int y0, y1, z0, z1;
+    axis_range(b, 1, g, y0, y1);
+    axis_range(b, 2, g, z0, z1);
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int cz = clo[2]; cz <= chi[2]; ++cz) {
-        for (int cy = clo[1]; cy <= chi[1]; ++cy) {
-            int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
-            int64_t beg = cell_start[row + clo[0]];
-            int64_t end = cell_start[row + chi[0] + 1];
+    const int64_t base = cand_off[oi];
+    int64_t nhit = 0;
+    int64_t c[5] = {0, 0, 0, 0, 0};
+    for (int cz = z0; cz <= z1; ++cz) {
+        for (int cy = y0; cy <= y1; ++cy) {
+            int x0, x1;
+            if (!row_range(b, g, cy, cz, x0, x1)) continue;
+            const int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
+            const int64_t beg = cell_start[row + x0], end = cell_start[row + x1 + 1];
             for (int64_t j = beg; j < end; j += 64) {
-                int64_t idx = j + lane;
-                bool valid = idx < end;
+                const int64_t idx = j + lane;
+                const bool valid = idx < end;
                 uint32_t code = 0;
                 int ncut = 0;
                 bool hit = false;
@@ -185,27 +246,61 @@ __global__ __launch_bounds__(256) void k_classify(const double* tetX, const int3
                     for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
                     for (int k = 0; k < 4; ++k) {
                         double r2[4];
-                        int cl = classify(X, P[k], d2, r2);
+                        const int cl = classify(X, P[k], d2, r2);
                         code |= (uint32_t)cl << (3 * k);
                         hit = hit || (cl != C_OUT);
                         ncut += (cl >= C_CUT0) ? 1 : 0;
                     }
                 }
-                for (int b = 0; b <= 4; ++b) {
-                    bool mine = hit && ncut == b;
-                    uint64_t mask = __ballot(mine);
-                    if (FILL && mine) {
-                        int64_t pos = base[b] + c[b] + __popcll(mask & lt);
-                        pair_m[pos] = m;
-                        pair_cls[pos] = (uint16_t)code;
-                    }
-                    c[b] += __popcll(mask);
+                const uint64_t mask = __ballot(hit);
+                if (hit) {
+                    const int64_t pos = base + nhit + __popcll(mask & lt);
+                    hit_m[pos] = m;
+                    hit_cls[pos] = (uint16_t)(code | ((uint32_t)ncut << 12));
                 }
+                nhit += __popcll(mask);
+                for (int bb = 0; bb <= 4; ++bb) c[bb] += __popcll(__ballot(hit && ncut == bb));
             }
         }
     }
-    if (!FILL && lane == 0)
-        for (int b = 0; b < 5; ++b) cnt[oi * 5 + b] = c[b];
+    if (lane == 0)
+        for (int bb = 0; bb < 5; ++bb) cnt[oi * 5 + bb] = c[bb];
+}
+
+// One wave per outer tet: the hits, grouped by cut count (4 first) and in
+// candidate order within a group, to the final pair arrays.
+__global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cnt,
+                                                      const int64_t* pair_off, const int32_t* hit_m,
+                                                      const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
+    if (oi >= n_outer) return;
+    int64_t base[5];
+    int64_t run = pair_off[oi];
+    for (int b = 4; b >= 0; --b) {
+        base[b] = run;
+        run += cnt[oi * 5 + b];
+    }
+    const int64_t n = run - pair_off[oi];
+    const int64_t src = cand_off[oi];
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int64_t c[5] = {0, 0, 0, 0, 0};
+    for (int64_t j = 0; j < n; j += 64) {
+        const bool valid = j + lane < n;
+        const uint32_t code = valid ? hit_cls[src + j + lane] : 0u;
+        const int m = valid ? hit_m[src + j + lane] : 0;
+        const int nc = (int)(code >> 12);
+        for (int b = 0; b <= 4; ++b) {
+            const bool mine = valid && nc == b;
+            const uint64_t mask = __ballot(mine);
+            if (mine) {
+                const int64_t pos = base[b] + c[b] + __popcll(mask & lt);
+                pair_m[pos] = m;
+                pair_cls[pos] = (uint16_t)(code & 0xFFFu);
+            }
+            c[b] += __popcll(mask);
+        }
+    }
 }
 
 __global__ void k_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot) {
@@ -470,17 +565,28 @@ hipError_t launch_cell_start(const uint64_t* sorted_keys, int64_t K, int64_t n_c
     return hipGetLastError();
 }
 
-hipError_t launch_classify(bool fill, const double* tetX, const int32_t* outer_ids, int64_t n_outer,
-                           const int64_t* cell_start, const uint32_t* cell_tets, Grid g, double delta, int64_t* cnt,
-                           const int64_t* pair_off, int32_t* pair_m, uint16_t* pair_cls, hipStream_t s) {
+hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
+                             const int64_t* cell_start, Grid g, double delta, int64_t* cand, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    unsigned nb = (unsigned)((n_outer + 3) / 4);
-    if (fill)
-        k_classify<true><<<nb, 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g, delta, cnt,
-                                            pair_off, pair_m, pair_cls);
-    else
-        k_classify<false><<<nb, 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g, delta, cnt,
-                                             pair_off, pair_m, pair_cls);
+    k_cand_count<<<blocks_for(n_outer), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, g, delta, cand);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
+                           const uint32_t* cell_tets, Grid g, double delta, const int64_t* cand_off, int64_t* cnt,
+                           int32_t* hit_m, uint16_t* hit_cls, hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    k_classify<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g, delta,
+                                                             cand_off, cnt, hit_m, hit_cls);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cnt, const int64_t* pair_off,
+                               const int32_t* hit_m, const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls,
+                               hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cnt, pair_off, hit_m, hit_cls,
+                                                                 pair_m, pair_cls);
     return hipGetLastError();
 }
 

@@ -154,6 +154,42 @@ typedef struct {
 nlfem_status nlfem_debug_pairs(nlfem_plan *plan, int64_t q_begin, int64_t q_end,
                                nlfem_pair_record *out, int64_t out_cap, int64_t *n_written);
 
+/* ---- batching ----------------------------------------------------------------
+ * Many independent meshes of uneven size and horizon assembled together
+ * (the parallel assembly of Sec. 4.4 extended across problems).  The
+ * symbolic phase runs per mesh as in nlfem_plan_create; the numeric phase of
+ * all meshes is ONE persistent integration launch that pulls (mesh, outer
+ * tet) work items, longest first, from a device queue, followed by the
+ * per-mesh reductions, all captured once in a HIP graph and replayed.  The
+ * workgroup size and persistent grid are picked by timing the candidates on
+ * the first call (cached per shape class for the process).  Results are
+ * bitwise those of nlfem_assemble on each mesh alone.                         */
+typedef struct nlfem_batch nlfem_batch;
+
+/* meshes[n], params[n] (HOST arrays of structs; the mesh arrays they point to
+ * follow mem_kind).  All params must use the same precision.                  */
+nlfem_status nlfem_batch_create(nlfem_ctx *ctx, int32_t n, const nlfem_mesh *meshes,
+                                const nlfem_params *params, nlfem_batch **batch);
+nlfem_status nlfem_batch_info(const nlfem_batch *batch, int32_t i, int64_t *n_free, int64_t *nnz_ff,
+                              int64_t *nnz_fc, int64_t pair_counts[5]);
+/* f_qp[i], g_nodal[i]: DEVICE pointers per mesh (as in nlfem_assemble; the
+ * host arrays f_qp / g_nodal may themselves be NULL for all-zero inputs).
+ * Outputs stay in the batch's device buffers (nlfem_batch_system).  The
+ * graph is re-captured when a g pointer changes.                              */
+nlfem_status nlfem_batch_assemble(nlfem_batch *batch, const double *const *f_qp,
+                                  const double *const *g_nodal);
+/* DEVICE pointers to mesh i's assembled system, owned by the batch.           */
+nlfem_status nlfem_batch_system(const nlfem_batch *batch, int32_t i, const int64_t **ff_row_ptr,
+                                const int32_t **ff_col, const double **ff_val,
+                                const int64_t **fc_row_ptr, const int32_t **fc_col,
+                                const double **fc_val, const double **rhs,
+                                const int32_t **free_to_vertex);
+/* Chosen workgroup size and grid, the tuned integration time and the time of
+ * the last graph replay (milliseconds, HIP events).                          */
+nlfem_status nlfem_batch_tuning(const nlfem_batch *batch, int32_t *block, int32_t *grid,
+                                double *tuned_integrate_ms, double *last_graph_ms);
+nlfem_status nlfem_batch_destroy(nlfem_batch *batch);
+
 /* Device kernel timing of the last nlfem_assemble / nlfem_plan_create on the
  * plan, measured with HIP events on the context's stream (milliseconds):
  * times[0] plan total, [1] classify, [2] pattern+sort, [3] integrate,

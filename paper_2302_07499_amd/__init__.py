@@ -49,7 +49,9 @@ class nlfem_pair_record(C.Structure):
 
 EXPORTS = ["nlfem_create", "nlfem_destroy", "nlfem_last_error", "nlfem_memory_in_use", "nlfem_trim",
            "nlfem_rule_constants", "nlfem_plan_create", "nlfem_plan_info", "nlfem_assemble", "nlfem_cg",
-           "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings"]
+           "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings",
+           "nlfem_batch_create", "nlfem_batch_info", "nlfem_batch_assemble", "nlfem_batch_system",
+           "nlfem_batch_tuning", "nlfem_batch_destroy"]
 
 _lib = None
 
@@ -81,6 +83,13 @@ def load():
     L.nlfem_plan_destroy.argtypes = [P]
     L.nlfem_debug_pairs.argtypes = [P, i64, i64, P, i64, C.POINTER(i64)]
     L.nlfem_plan_timings.argtypes = [P, C.POINTER(C.c_double)]
+    L.nlfem_batch_create.argtypes = [P, C.c_int32, C.POINTER(nlfem_mesh), C.POINTER(nlfem_params), C.POINTER(P)]
+    L.nlfem_batch_info.argtypes = [P, C.c_int32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.nlfem_batch_assemble.argtypes = [P, C.POINTER(P), C.POINTER(P)]
+    L.nlfem_batch_system.argtypes = [P, C.c_int32] + [C.POINTER(P)] * 8
+    L.nlfem_batch_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+    L.nlfem_batch_destroy.argtypes = [P]
     for name in EXPORTS:
         if name != "nlfem_rule_constants" and name != "nlfem_last_error":
             getattr(L, name).restype = C.c_int
@@ -318,6 +327,102 @@ class Plan:
 
     def debug_pairs(self, q_begin, q_end):
         return nlfem_debug_pairs(self.handle, q_begin, q_end, ctx=self.dev.ctx)
+
+
+class Batch:
+    """Many meshes assembled by one persistent fused launch replayed from a HIP graph."""
+
+    def __init__(self, dev: Device, problems, outer_masks=None):
+        t = dev.torch
+        self.dev = dev
+        self.n = len(problems)
+        self.keep = []
+        meshes = (nlfem_mesh * max(self.n, 1))()
+        params = (nlfem_params * max(self.n, 1))()
+        for i, pb in enumerate(problems):
+            m, keep = dev.mesh(pb.mesh.coords, pb.mesh.tets, pb.vertex_free)
+            om = None
+            if outer_masks is not None and outer_masks[i] is not None:
+                om = dev.to_dev(outer_masks[i], t.uint8)
+            self.keep.append((keep, om))
+            meshes[i] = m
+            params[i] = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
+                                     NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
+                                     None if om is None else om.data_ptr())
+        h = C.c_void_p()
+        _check(load().nlfem_batch_create(dev.ctx, self.n, meshes, params, C.byref(h)), dev.ctx)
+        self.handle = h
+        self.infos = []
+        for i in range(self.n):
+            nf, nff, nfc = C.c_int64(), C.c_int64(), C.c_int64()
+            pc = (C.c_int64 * 5)()
+            _check(load().nlfem_batch_info(h, i, C.byref(nf), C.byref(nff), C.byref(nfc), pc))
+            self.infos.append({"n_free": nf.value, "nnz_ff": nff.value, "nnz_fc": nfc.value, "pair_counts": list(pc)})
+        self.inputs = None
+        dev.plans.add(self)
+
+    def set_inputs(self, f_list, g_list):
+        t = self.dev.torch
+        self.inputs = ([None if f is None else self.dev.to_dev(f, t.float64) for f in f_list],
+                       [None if g is None else self.dev.to_dev(g, t.float64) for g in g_list])
+
+    def assemble(self):
+        fl, gl = self.inputs if self.inputs is not None else ([None] * self.n, [None] * self.n)
+        fa = (C.c_void_p * max(self.n, 1))(*[None if f is None else f.data_ptr() for f in fl])
+        ga = (C.c_void_p * max(self.n, 1))(*[None if g is None else g.data_ptr() for g in gl])
+        _check(load().nlfem_batch_assemble(self.handle, fa, ga), self.dev.ctx)
+
+    def system_numpy(self, i):
+        import torch
+        ptrs = [C.c_void_p() for _ in range(8)]
+        _check(load().nlfem_batch_system(self.handle, i, *[C.byref(p) for p in ptrs]))
+        info = self.infos[i]
+        nf, nff, nfc = info["n_free"], info["nnz_ff"], info["nnz_fc"]
+        sizes = [(nf + 1, np.int64), (nff, np.int32), (nff, np.float64), (nf + 1, np.int64), (nfc, np.int32),
+                 (nfc, np.float64), (nf, np.float64), (nf, np.int32)]
+        torch.cuda.synchronize()
+        out = []
+        for p, (cnt, dt) in zip(ptrs, sizes):
+            a = np.empty(cnt, dtype=dt)
+            if cnt:
+                _hip_d2h(a, p.value)
+            out.append(a)
+        names = ["ff_row_ptr", "ff_col", "ff_val", "fc_row_ptr", "fc_col", "fc_val", "rhs", "free_to_vertex"]
+        d = dict(zip(names, out))
+        d["n_free"] = nf
+        d["pair_counts"] = np.array(info["pair_counts"], dtype=np.int64)
+        return d
+
+    def tuning(self):
+        b, g, tm, lm = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+        _check(load().nlfem_batch_tuning(self.handle, C.byref(b), C.byref(g), C.byref(tm), C.byref(lm)))
+        return {"block": b.value, "grid": g.value, "tuned_integrate_ms": tm.value, "last_graph_ms": lm.value}
+
+    def destroy(self):
+        if self.handle is not None and self.dev.ctx is not None:
+            _check(load().nlfem_batch_destroy(self.handle))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _hip_d2h(arr, dev_ptr):
+    """Copies device memory owned by the library into a numpy array (hipMemcpy)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    rc = _hip.hipMemcpy(arr.ctypes.data, C.c_void_p(dev_ptr), arr.nbytes, 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise NlfemError(NLFEM_E_DEVICE, f"hipMemcpy failed ({rc})")
 
 
 @atexit.register

@@ -520,6 +520,119 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     return a;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner cache: shape class -> (block, workgroups per CU), shared by all
+// batches of the process.
+struct TuneKey {
+    int log2_pairs, log2_items, mc, fp32;
+    bool operator<(const TuneKey& o) const {
+        if (log2_pairs != o.log2_pairs) return log2_pairs < o.log2_pairs;
+        if (log2_items != o.log2_items) return log2_items < o.log2_items;
+        if (mc != o.mc) return mc < o.mc;
+        return fp32 < o.fp32;
+    }
+};
+struct TuneVal {
+    int block, wg_per_cu;
+    double ms;
+};
+std::map<TuneKey, TuneVal>& tune_cache() {
+    static std::map<TuneKey, TuneVal> m;
+    return m;
+}
+
+int ilog2(int64_t x) {
+    int b = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+}  // namespace
+
+struct nlfem_batch {
+    nlfem_ctx* ctx = nullptr;
+    std::vector<nlfem_plan*> plans;
+    struct Out {
+        int64_t* ff_row_ptr;
+        int32_t* ff_col;
+        double* ff_val;
+        int64_t* fc_row_ptr;
+        int32_t* fc_col;
+        double* fc_val;
+        double* rhs;
+        int32_t* f2v;
+    };
+    std::vector<Out> outs;
+    std::vector<void*> owned;
+    std::vector<IntegrateArgs> descs;
+    IntegrateArgs* d_descs = nullptr;
+    int2* d_items = nullptr;
+    int64_t n_items = 0, total_pairs = 0;
+    unsigned long long* d_head = nullptr;
+    int umax_all = 1;
+    bool fp32 = false;
+    int block = 256, grid = 0, n_cu = 256;
+    double tune_ms = 0.0;
+    bool tuned = false;
+    hipStream_t gs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const double*> cap_f, cap_g;
+    double last_ms = 0.0;
+    void* alloc(size_t b) {
+        void* p = dalloc(ctx, b);
+        if (p) owned.push_back(p);
+        return p;
+    }
+};
+
+namespace {
+
+void batch_free(nlfem_batch* b) {
+    if (!b) return;
+    if (b->gs) hipStreamSynchronize(b->gs);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->ev_in) hipEventDestroy(b->ev_in);
+    if (b->ev_out) hipEventDestroy(b->ev_out);
+    if (b->gs) hipStreamDestroy(b->gs);
+    for (nlfem_plan* p : b->plans) {
+        p->release();
+        delete p;
+    }
+    for (void* p : b->owned) dfree(b->ctx, p);
+    delete b;
+}
+
+// numeric phase of every mesh of the batch on stream s
+nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStream_t s, int block, int grid) {
+    nlfem_ctx* c = b->ctx;
+    HIPCHK(launch_integrate_batch(b->d_descs, b->d_items, b->n_items, b->d_head, b->umax_all, b->fp32, block, grid, s));
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        nlfem_plan* pl = b->plans[i];
+        const nlfem_batch::Out& o = b->outs[i];
+        HIPCHK(launch_g_reduce(pl->region, pl->K, pl->trans_off, pl->g_buf, pl->n_rec_c, pl->rec_val, s));
+        HIPCHK(launch_fill_zero_f64(pl->rhs_f, pl->n_free, s));
+        HIPCHK(launch_segsum(pl->seg_off, pl->perm, pl->rec_val, pl->n_slots, pl->dest, pl->nnz_ff, pl->nnz_fc,
+                             o.ff_val, o.fc_val, pl->rhs_f, s));
+        HIPCHK(launch_rhs_final(pl->n_free, pl->rhs_f, pl->fc_row_ptr, pl->fc_col, o.fc_val,
+                                g_nodal ? g_nodal[i] : nullptr, o.rhs, s));
+    }
+    return NLFEM_OK;
+}
+
+double time_integrate(nlfem_batch* b, int block, int grid) {
+    Timer t(b->gs);
+    if (launch_integrate_batch(b->d_descs, b->d_items, b->n_items, b->d_head, b->umax_all, b->fp32, block, grid,
+                               b->gs) != hipSuccess)
+        return 1e30;
+    return t.stop();
+}
+
 }  // namespace
 
 // ============================================================================
@@ -713,6 +826,214 @@ nlfem_status nlfem_debug_pairs(nlfem_plan* pl, int64_t q_begin, int64_t q_end, n
     }
     *n_written = cnt;
     if (cnt > out_cap) return fail(c, NLFEM_E_INVALID_ARG, "out_cap too small");
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshes, const nlfem_params* params,
+                                nlfem_batch** out) {
+    if (!c) return NLFEM_E_INVALID_ARG;
+    if (!out || n < 0 || (n > 0 && (!meshes || !params))) return fail(c, NLFEM_E_INVALID_ARG, "bad batch argument");
+    *out = nullptr;
+    for (int32_t i = 0; i < n; ++i)
+        if (params[i].precision != params[0].precision)
+            return fail(c, NLFEM_E_INVALID_ARG, "all meshes of a batch must use the same precision");
+    nlfem_batch* b = new nlfem_batch();
+    b->ctx = c;
+    b->fp32 = n > 0 && params[0].precision == NLFEM_FP32_LOCAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) b->n_cu = prop.multiProcessorCount;
+    for (int32_t i = 0; i < n; ++i) {
+        nlfem_plan* pl = nullptr;
+        nlfem_status st = nlfem_plan_create(c, &meshes[i], &params[i], &pl);
+        if (st != NLFEM_OK) {
+            batch_free(b);
+            return st;
+        }
+        b->plans.push_back(pl);
+    }
+    hipStream_t s = c->stream;
+    std::vector<int2> items;
+    std::vector<int64_t> cost;
+    b->outs.resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        nlfem_plan* pl = b->plans[i];
+        nlfem_batch::Out& o = b->outs[i];
+        const int64_t nf = pl->n_free;
+        o.ff_row_ptr = (int64_t*)b->alloc((size_t)(nf + 1) * 8);
+        o.ff_col = (int32_t*)b->alloc((size_t)(pl->nnz_ff + 1) * 4);
+        o.ff_val = (double*)b->alloc((size_t)(pl->nnz_ff + 1) * 8);
+        o.fc_row_ptr = (int64_t*)b->alloc((size_t)(nf + 1) * 8);
+        o.fc_col = (int32_t*)b->alloc((size_t)(pl->nnz_fc + 1) * 4);
+        o.fc_val = (double*)b->alloc((size_t)(pl->nnz_fc + 1) * 8);
+        o.rhs = (double*)b->alloc((size_t)(nf + 1) * 8);
+        o.f2v = (int32_t*)b->alloc((size_t)(nf + 1) * 4);
+        if (!o.ff_row_ptr || !o.ff_col || !o.ff_val || !o.fc_row_ptr || !o.fc_col || !o.fc_val || !o.rhs || !o.f2v) {
+            batch_free(b);
+            return fail(c, NLFEM_E_OOM, c->err);
+        }
+        HIPCHK(launch_copy_i64(pl->ff_row_ptr, o.ff_row_ptr, nf + 1, s));
+        HIPCHK(launch_copy_i32(pl->ff_col, o.ff_col, pl->nnz_ff, s));
+        HIPCHK(launch_copy_i64(pl->fc_row_ptr, o.fc_row_ptr, nf + 1, s));
+        HIPCHK(launch_copy_i32(pl->fc_col, o.fc_col, pl->nnz_fc, s));
+        HIPCHK(launch_copy_i32(pl->free_to_vertex, o.f2v, nf, s));
+        b->descs.push_back(make_args(pl, nullptr));
+        b->umax_all = std::max(b->umax_all, std::max(pl->umax, 1));
+        std::vector<int64_t> off(pl->n_outer + 1);
+        HIPCHK(hipMemcpyAsync(off.data(), pl->pair_off, off.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t oi = 0; oi < pl->n_outer; ++oi) {
+            items.push_back(make_int2(i, (int)oi));
+            cost.push_back(off[oi + 1] - off[oi]);
+        }
+        b->total_pairs += pl->P;
+    }
+    for (auto& d : b->descs) d.umax = b->umax_all;
+    if (integrate_lds_bytes(b->umax_all) > c->lds_max) {
+        batch_free(b);
+        return fail(c, NLFEM_E_UNSUPPORTED, "batch ball vertex set too large for LDS");
+    }
+    // longest items first
+    std::vector<int64_t> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t bb) { return cost[a] > cost[bb]; });
+    std::vector<int2> sorted(items.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+    b->n_items = (int64_t)sorted.size();
+    b->d_items = (int2*)b->alloc(sorted.size() * sizeof(int2) + 16);
+    b->d_descs = (IntegrateArgs*)b->alloc(b->descs.size() * sizeof(IntegrateArgs) + 16);
+    b->d_head = (unsigned long long*)b->alloc(64);
+    if (!b->d_items || !b->d_descs || !b->d_head) {
+        batch_free(b);
+        return fail(c, NLFEM_E_OOM, c->err);
+    }
+    if (!sorted.empty())
+        HIPCHK(hipMemcpyAsync(b->d_items, sorted.data(), sorted.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    if (!b->descs.empty())
+        HIPCHK(hipMemcpyAsync(b->d_descs, b->descs.data(), b->descs.size() * sizeof(IntegrateArgs),
+                              hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        batch_free(b);
+        return fail(c, NLFEM_E_DEVICE, "stream/event creation failed");
+    }
+    *out = b;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_batch_info(const nlfem_batch* b, int32_t i, int64_t* n_free, int64_t* nnz_ff, int64_t* nnz_fc,
+                              int64_t pair_counts[5]) {
+    if (!b || i < 0 || i >= (int32_t)b->plans.size()) return NLFEM_E_INVALID_ARG;
+    return nlfem_plan_info(b->plans[i], n_free, nnz_ff, nnz_fc, pair_counts, nullptr);
+}
+
+nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, const double* const* g_nodal) {
+    if (!b) return NLFEM_E_INVALID_ARG;
+    nlfem_ctx* c = b->ctx;
+    const size_t n = b->plans.size();
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
+    // inputs: f pointers live in the device descriptors (updated outside the graph)
+    bool fchanged = false;
+    for (size_t i = 0; i < n; ++i) {
+        const double* f = f_qp ? f_qp[i] : nullptr;
+        if (b->descs[i].f_qp != f) {
+            b->descs[i].f_qp = f;
+            fchanged = true;
+        }
+    }
+    HIPCHK(hipEventRecord(b->ev_in, c->stream));
+    HIPCHK(hipStreamWaitEvent(b->gs, b->ev_in, 0));
+    if (fchanged && n)
+        HIPCHK(hipMemcpyAsync(b->d_descs, b->descs.data(), n * sizeof(IntegrateArgs), hipMemcpyHostToDevice, b->gs));
+    if (!b->tuned) {
+        TuneKey key{ilog2(std::max<int64_t>(b->total_pairs, 1)), ilog2(std::max<int64_t>(b->n_items, 1)),
+                    n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0};
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            b->block = it->second.block;
+            b->grid = b->n_cu * it->second.wg_per_cu;
+            b->tune_ms = it->second.ms;
+        } else {
+            const int blocks[2] = {128, 256};
+            const int wpc[4] = {2, 3, 4, 6};
+            double best = 1e30;
+            TuneVal bv{256, 3, 0.0};
+            for (int bi = 0; bi < 2; ++bi)
+                for (int wi = 0; wi < 4; ++wi) {
+                    // 3 waves per SIMD at most: 12 waves per CU
+                    if ((blocks[bi] / 64) * wpc[wi] > 12) continue;
+                    double ms = time_integrate(b, blocks[bi], b->n_cu * wpc[wi]);
+                    if (ms < best) {
+                        best = ms;
+                        bv = TuneVal{blocks[bi], wpc[wi], ms};
+                    }
+                }
+            tune_cache()[key] = bv;
+            b->block = bv.block;
+            b->grid = b->n_cu * bv.wg_per_cu;
+            b->tune_ms = bv.ms;
+        }
+        b->tuned = true;
+    }
+    std::vector<const double*> gcur(n);
+    for (size_t i = 0; i < n; ++i) gcur[i] = g_nodal ? g_nodal[i] : nullptr;
+    if (!b->exec || gcur != b->cap_g) {
+        if (b->exec) {
+            hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        HIPCHK(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
+        nlfem_status st = batch_enqueue(b, gcur.data(), b->gs, b->block, b->grid);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(b->gs, &g);
+        if (st != NLFEM_OK) return st;
+        if (ee != hipSuccess) return fail(c, NLFEM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ee));
+        b->graph = g;
+        HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->cap_g = gcur;
+    }
+    Timer t(b->gs);
+    HIPCHK(hipGraphLaunch(b->exec, b->gs));
+    b->last_ms = t.stop();
+    HIPCHK(hipEventRecord(b->ev_out, b->gs));
+    HIPCHK(hipStreamWaitEvent(c->stream, b->ev_out, 0));
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_batch_system(const nlfem_batch* b, int32_t i, const int64_t** ff_row_ptr, const int32_t** ff_col,
+                                const double** ff_val, const int64_t** fc_row_ptr, const int32_t** fc_col,
+                                const double** fc_val, const double** rhs, const int32_t** free_to_vertex) {
+    if (!b || i < 0 || i >= (int32_t)b->plans.size()) return NLFEM_E_INVALID_ARG;
+    const nlfem_batch::Out& o = b->outs[i];
+    if (ff_row_ptr) *ff_row_ptr = o.ff_row_ptr;
+    if (ff_col) *ff_col = o.ff_col;
+    if (ff_val) *ff_val = o.ff_val;
+    if (fc_row_ptr) *fc_row_ptr = o.fc_row_ptr;
+    if (fc_col) *fc_col = o.fc_col;
+    if (fc_val) *fc_val = o.fc_val;
+    if (rhs) *rhs = o.rhs;
+    if (free_to_vertex) *free_to_vertex = o.f2v;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_batch_tuning(const nlfem_batch* b, int32_t* block, int32_t* grid, double* tuned_integrate_ms,
+                                double* last_graph_ms) {
+    if (!b) return NLFEM_E_INVALID_ARG;
+    if (block) *block = b->block;
+    if (grid) *grid = b->grid;
+    if (tuned_integrate_ms) *tuned_integrate_ms = b->tune_ms;
+    if (last_graph_ms) *last_graph_ms = b->last_ms;
+    return NLFEM_OK;
+}
+
+nlfem_status nlfem_batch_destroy(nlfem_batch* b) {
+    if (!b) return NLFEM_E_INVALID_ARG;
+    batch_free(b);
     return NLFEM_OK;
 }
 

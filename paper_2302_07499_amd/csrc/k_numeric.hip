@@ -50,25 +50,24 @@ __device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long 
     return (double)hi * ldexp(1.0, -shift) + (double)lo * ldexp(1.0, -(shift + FX_LO_BITS));
 }
 
-// One workgroup per outer tet.  LDS: R [4][umax] and T0 [4] as two-word
-// fixed-point sums (coarse words, then fine words), Ve [umax].
-template <typename T>
-__global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
-    extern __shared__ unsigned long long smem64[];
-    __shared__ double P[4][3];
+// One workgroup of BLOCK threads integrates one outer tet.  LDS: R [4][umax]
+// and T0 [4] as two-word fixed-point sums (coarse words, then fine words),
+// Ve [umax], and the 4 outer points.
+template <typename T, int BLOCK>
+__device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t oi, unsigned long long* smem64,
+                                                double (*P)[3]) {
     const int umax = a.umax;
     unsigned long long* R = smem64;             // coarse [4][umax]
     unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax]
     unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
     unsigned long long* T0l = T0 + 4;           // fine   [4]
     int32_t* ve = (int32_t*)(T0l + 4);
-    const int64_t oi = blockIdx.x;
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
     const int U = (int)(a.ve_off[oi + 1] - vb);
     const int t = threadIdx.x;
-    for (int i = t; i < U; i += 256) ve[i] = a.ve_ids[vb + i];
-    for (int i = t; i < 8 * umax; i += 256) R[i] = 0ull;
+    for (int i = t; i < U; i += BLOCK) ve[i] = a.ve_ids[vb + i];
+    for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
     if (t < 4) {
         T0[t] = 0ull;
         T0l[t] = 0ull;
@@ -81,7 +80,7 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(Integr
     const double d2 = a.delta * a.delta;
     const double fx = ldexp(1.0, a.fx_shift);
     const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
-    for (int64_t p = p0 + t; p < p1; p += 256) {
+    for (int64_t p = p0 + t; p < p1; p += BLOCK) {
         const int m = a.pair_m[p];
         const uint32_t code = a.pair_cls[p];
         double X[12];
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(Integr
     for (int k = 0; k < 4; ++k) t0[k] = fx_value(T0[k], T0l[k], sh);
     const int64_t rb = a.rec_off[oi];
     // direct rows u = V_n[j], columns Ve[i]: psi w (sum_k c_u c_v T0_k [v in V_n] - sum_k c_u R_k(v))
-    for (int r = t; r < 4 * U; r += 256) {
+    for (int r = t; r < 4 * U; r += BLOCK) {
         const int j = r / U, i = r - j * U;
         double cR = 0.0;
         for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
@@ -133,7 +132,7 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(Integr
         a.rec_val[rb + r] = pw * (O - cR);
     }
     // transposed rows Ve[i], columns u = V_n[j]: the cross term again
-    for (int r = t; r < 4 * U; r += 256) {
+    for (int r = t; r < 4 * U; r += BLOCK) {
         const int i = r >> 2, j = r & 3;
         double cR = 0.0;
         for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
@@ -147,6 +146,36 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(Integr
         a.rec_val[rb + 8 * (int64_t)U + t] = f;
     }
 }
+
+template <typename T>
+__global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
+    extern __shared__ unsigned long long smem64[];
+    __shared__ double P[4][3];
+    integrate_outer<T, 256>(a, (int64_t)blockIdx.x, smem64, P);
+}
+
+// Persistent batched integration: every workgroup takes work items (mesh,
+// outer tet) from a device queue until it is empty.  Items are ordered by
+// decreasing estimated cost; each item's results depend on the item only.
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batch(const IntegrateArgs* descs, const int2* items,
+                                                           int64_t n_items, unsigned long long* head) {
+    extern __shared__ unsigned long long smem64[];
+    __shared__ double P[4][3];
+    __shared__ long long cur;
+    while (true) {
+        if (threadIdx.x == 0) cur = (long long)atomicAdd(head, 1ull);
+        __syncthreads();
+        const long long it = cur;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        integrate_outer<T, BLOCK>(descs[item.x], (int64_t)item.y, smem64, P);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_u64(unsigned long long* p) { *p = 0ull; }
 
 // per-pair moments for outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k
 template <typename T>
@@ -263,6 +292,21 @@ hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     size_t sh = integrate_lds_bytes(a.umax);
     if (fp32) k_integrate<float><<<(unsigned)a.n_outer, 256, sh, s>>>(a);
     else k_integrate<double><<<(unsigned)a.n_outer, 256, sh, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
+                                  unsigned long long* head, int umax, bool fp32, int block, int grid, hipStream_t s) {
+    size_t sh = integrate_lds_bytes(umax);
+    k_reset_u64<<<1, 1, 0, s>>>(head);
+    if (n_items <= 0) return hipGetLastError();
+    if (block == 128) {
+        if (fp32) k_integrate_batch<float, 128><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+        else k_integrate_batch<double, 128><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+    } else {
+        if (fp32) k_integrate_batch<float, 256><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+        else k_integrate_batch<double, 256><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+    }
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Host runtime behind the C ABI of include/nlfem.h: contexts with a caching
 // device allocator and an HBM budget, the symbolic plan (mesh layout, cell
-// list, classification, local vertex sets, sorted-key reduction plan, CSR
+// list, classification, local vertex sets, vertex-keyed sorted lists, CSR
 // pattern), the numeric assembly and the CG solver loop.
 #include <hip/hip_runtime.h>
 
@@ -113,28 +113,32 @@ struct nlfem_plan {
     nlfem_ctx* ctx = nullptr;
     std::vector<void*> owned;
     // sizes
-    int64_t V = 0, K = 0, n_free = 0, n_outer = 0, P = 0, n_rec = 0, n_rec_c = 0, n_slots = 0;
-    int64_t nnz_ff = 0, nnz_fc = 0, max_pairs = 0;
-    int umax = 0, fx_shift = 0;
+    int64_t V = 0, K = 0, n_free = 0, n_outer = 0, P = 0, ve_total = 0;
+    int64_t nnz_ff = 0, nnz_fc = 0, max_pairs = 0, max_inner = 0, max_vt = 0;
+    int umax = 0, max_row = 0, fx_shift = 0, g_shift = 0, w_shift = 0, row_shift = 0;
     int64_t pair_counts[5] = {0, 0, 0, 0, 0};
     double delta = 0, psi = 0;
     int mc = 1, precision = 0;
     uint64_t seed = 0;
-    // device arrays
+    // device arrays: mesh and ball query
     double *tetX = nullptr, *vol = nullptr;
     int32_t* tets = nullptr;
     uint8_t* region = nullptr;
-    int32_t *free_id = nullptr, *free_to_vertex = nullptr, *outer_ids = nullptr;
+    int32_t *free_id = nullptr, *free_to_vertex = nullptr, *outer_ids = nullptr, *outer_pos = nullptr;
     int64_t* pair_off = nullptr;
     int32_t* pair_m = nullptr;
     uint16_t* pair_cls = nullptr;
-    int64_t *ve_off = nullptr, *rec_off = nullptr, *trans_off = nullptr;
-    int32_t* ve_ids = nullptr;
-    uint32_t *tpos = nullptr, *perm = nullptr;
-    int64_t *seg_off = nullptr, *dest = nullptr;
+    int32_t* inner_cnt = nullptr;
+    // local vertex sets and the vertex-keyed lists
+    int64_t *ve_off = nullptr, *vt_off = nullptr, *inc_off = nullptr;
+    int32_t *ve_ids = nullptr, *ve_owner = nullptr;
+    uint32_t *vt_val = nullptr, *inc_val = nullptr;
+    // CSR pattern
     int64_t *ff_row_ptr = nullptr, *fc_row_ptr = nullptr;
-    int32_t *ff_col = nullptr, *fc_col = nullptr;
-    double *g_buf = nullptr, *rec_val = nullptr, *rhs_f = nullptr, *fc_val_int = nullptr;
+    int32_t *ff_col = nullptr, *fc_col = nullptr, *all_cols = nullptr;
+    // numeric workspace
+    double *cblk = nullptr, *oblk = nullptr, *gvals = nullptr, *fc_val_int = nullptr;
+    unsigned long long* gacc = nullptr;
     double times[6] = {0, 0, 0, 0, 0, 0};
 
     template <typename Tp>
@@ -206,6 +210,16 @@ int64_t read_i64(nlfem_ctx* c, const int64_t* dev) {
     hipMemcpyAsync(c->pinned_i, dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
     return c->pinned_i[0];
+}
+
+RowPlan make_row_plan(nlfem_plan* pl);
+
+// shift s with bound * 2^s < 2^62
+int shift_for(double bound) {
+    if (!(bound > 0.0) || !std::isfinite(bound)) return 62;
+    int e = 0;
+    std::frexp(bound, &e);  // bound < 2^e
+    return std::min(62 - e, 1000);
 }
 
 nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, const nlfem_params* prm) {
@@ -352,144 +366,179 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     }
     pl->times[1] = tcls.stop();
     Timer tpat(s);
-    // ---- transposed pair order (by inner tet) ---------------------------
-    ALLOC(pl->trans_off, int64_t, K + 2);
-    ALLOC(pl->tpos, uint32_t, P + 1);
+    // ---- pairs per inner tet, outer positions ----------------------------
+    ALLOC(pl->inner_cnt, int32_t, K + 1);
+    ALLOC(pl->outer_pos, int32_t, K + 1);
+    HIPCHK(launch_fill_i32(pl->inner_cnt, K, 0, s));
+    HIPCHK(launch_inner_count(pl->pair_m, P, pl->inner_cnt, s));
+    HIPCHK(launch_outer_pos(pl->outer_ids, no, pl->outer_pos, K, s));
     {
-        TMP(t_tk, (size_t)(P + 1) * 16);
-        TMP(t_tv, (size_t)(P + 1) * 8);
-        TMP(t_rs2, radix_sort_temp_bytes(P + 1));
-        uint64_t* keys = t_tk.as<uint64_t>();
-        uint32_t* vals = t_tv.as<uint32_t>();
-        HIPCHK(launch_trans_keys(pl->pair_m, P, keys, vals, s));
-        HIPCHK(radix_sort_u64_u32(keys, vals, keys + P, vals + P, P, bits_for((uint64_t)K), t_rs2.p, s));
-        HIPCHK(launch_trans_finish(keys, vals, P, K, pl->trans_off, pl->tpos, s));
+        std::vector<int32_t> ic(K);
+        if (K) HIPCHK(hipMemcpyAsync(ic.data(), pl->inner_cnt, (size_t)K * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t e = 0; e < K; ++e) pl->max_inner = std::max<int64_t>(pl->max_inner, ic[e]);
     }
-    // ---- local vertex sets and record keys -------------------------------
+    if (pl->max_inner >= ((int64_t)1 << 15))
+        return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^15 outer tets interacting with one inner tet");
+    // ---- local vertex sets ---------------------------------------------------
     TMP(t_ucount, (size_t)(no + 1) * 8);
     int hash_cap = (int)std::max<int64_t>(256, next_pow2(2 * (pl->max_pairs + 16)));
     while (true) {
         if ((size_t)hash_cap * 4 > c->lds_max)
             return fail(c, NLFEM_E_UNSUPPORTED, "local vertex set too large for LDS");
-        HIPCHK(hipMemsetAsync(t_err.p, 0, 64, s));
-        HIPCHK(launch_pattern(false, pl->tets, pl->outer_ids, no, pl->pair_off, pl->pair_m, pl->free_id, V, nf,
-                              hash_cap, t_ucount.as<int64_t>(), nullptr, nullptr, nullptr, nullptr, nullptr,
-                              t_err.as<unsigned>(), s));
+        HIPCHK(launch_fill_i32((int32_t*)t_err.p, 16, 0, s));
+        HIPCHK(launch_pattern(false, pl->tets, no, pl->pair_off, pl->pair_m, hash_cap, t_ucount.as<int64_t>(), nullptr,
+                              nullptr, t_err.as<unsigned>(), s));
         HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (!(errbits & ERR_HASH)) break;
         hash_cap *= 2;
     }
     ALLOC(pl->ve_off, int64_t, no + 2);
-    ALLOC(pl->rec_off, int64_t, no + 2);
     HIPCHK(exclusive_scan_i64(t_ucount.as<int64_t>(), pl->ve_off, no, t_scan2.p, s));
     HIPCHK(reduce_max_i64(t_ucount.as<int64_t>(), no, (int64_t*)(small + 8), s));
     pl->umax = (int)read_i64(c, (int64_t*)(small + 8));
-    const int64_t ve_total = read_i64(c, pl->ve_off + no);
+    pl->ve_total = read_i64(c, pl->ve_off + no);
+    const int64_t VT = pl->ve_total;
     if (integrate_lds_bytes(pl->umax) > c->lds_max)
         return fail(c, NLFEM_E_UNSUPPORTED, "ball vertex set of one outer tet too large for LDS");
+    if (VT >= (int64_t)0xFFFFFFFFll || 4 * K >= (int64_t)0xFFFFFFFFll)
+        return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 local vertex set entries");
+    ALLOC(pl->ve_ids, int32_t, VT + 1);
+    HIPCHK(launch_pattern(true, pl->tets, no, pl->pair_off, pl->pair_m, hash_cap, t_ucount.as<int64_t>(), pl->ve_off,
+                          pl->ve_ids, t_err.as<unsigned>(), s));
+    // ---- vertex -> tets and vertex -> local vertex set entries -------------
+    ALLOC(pl->vt_off, int64_t, V + 2);
+    ALLOC(pl->vt_val, uint32_t, 4 * K + 1);
+    ALLOC(pl->inc_off, int64_t, V + 2);
+    ALLOC(pl->inc_val, uint32_t, VT + 1);
+    ALLOC(pl->ve_owner, int32_t, VT + 1);
+    const int vbits = std::max(1, bits_for((uint64_t)V));
     {
-        // record counts 8 U + 4 per outer tet
-        std::vector<int64_t> dummy;
-        (void)dummy;
-    }
-    // rec counts: reuse t_tot as 8U+4
-    {
-        // compute on host from ucount (small arrays: copy)
-        std::vector<int64_t> uc(no);
-        if (no) HIPCHK(hipMemcpyAsync(uc.data(), t_ucount.p, (size_t)no * 8, hipMemcpyDeviceToHost, s));
+        TMP(t_k, (size_t)(4 * K + 1) * 16);
+        TMP(t_v, (size_t)(4 * K + 1) * 8);
+        TMP(t_rs, radix_sort_temp_bytes(4 * K + 1));
+        uint64_t* keys = t_k.as<uint64_t>();
+        uint32_t* vals = t_v.as<uint32_t>();
+        HIPCHK(launch_vt_keys(pl->tets, K, keys, vals, s));
+        HIPCHK(radix_sort_u64_u32(keys, vals, keys + 4 * K, vals + 4 * K, 4 * K, vbits, t_rs.p, s));
+        HIPCHK(launch_offsets(keys, 4 * K, V, pl->vt_off, s));
+        HIPCHK(launch_copy_i32((const int32_t*)vals, (int32_t*)pl->vt_val, 4 * K, s));
         HIPCHK(hipStreamSynchronize(s));
-        std::vector<int64_t> ro(no + 1);
-        int64_t run = 0;
-        for (int64_t i = 0; i < no; ++i) {
-            ro[i] = run;
-            run += 8 * uc[i] + 4;
+    }
+    {
+        TMP(t_k, (size_t)(VT + 1) * 16);
+        TMP(t_v, (size_t)(VT + 1) * 8);
+        TMP(t_rs, radix_sort_temp_bytes(VT + 1));
+        uint64_t* keys = t_k.as<uint64_t>();
+        uint32_t* vals = t_v.as<uint32_t>();
+        HIPCHK(launch_inc_keys(pl->ve_off, no, pl->ve_ids, keys, vals, pl->ve_owner, s));
+        HIPCHK(radix_sort_u64_u32(keys, vals, keys + VT, vals + VT, VT, vbits, t_rs.p, s));
+        HIPCHK(launch_offsets(keys, VT, V, pl->inc_off, s));
+        HIPCHK(launch_copy_i32((const int32_t*)vals, (int32_t*)pl->inc_val, VT, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    {
+        std::vector<int64_t> vo(V + 1);
+        HIPCHK(hipMemcpyAsync(vo.data(), pl->vt_off, (size_t)(V + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int64_t v = 0; v < V; ++v) pl->max_vt = std::max<int64_t>(pl->max_vt, vo[v + 1] - vo[v]);
+    }
+    // the fine words of a row slot take < 2^48 from each of at most 4 max_vt terms
+    if (pl->max_vt >= ((int64_t)1 << 13)) return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^13 tets at one vertex");
+    // ---- CSR pattern, row by row -------------------------------------------
+    RowPlan rp = make_row_plan(pl);
+    TMP(t_nff, (size_t)(nf + 2) * 8);
+    TMP(t_nfc, (size_t)(nf + 2) * 8);
+    int row_cap = (int)std::max<int64_t>(512, next_pow2(4 * (int64_t)std::max(pl->umax, 1)));
+    while (true) {
+        if ((size_t)row_cap * 4 + 2048 > c->lds_max) return fail(c, NLFEM_E_UNSUPPORTED, "matrix row too large for LDS");
+        HIPCHK(launch_fill_i32((int32_t*)t_err.p, 16, 0, s));
+        HIPCHK(launch_row_pattern(false, rp, nf, row_cap, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), nullptr, nullptr,
+                                  nullptr, nullptr, nullptr, t_err.as<unsigned>(), s));
+        HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!(errbits & ERR_HASH)) break;
+        row_cap *= 2;
+    }
+    ALLOC(pl->ff_row_ptr, int64_t, nf + 2);
+    ALLOC(pl->fc_row_ptr, int64_t, nf + 2);
+    HIPCHK(exclusive_scan_i64(t_nff.as<int64_t>(), pl->ff_row_ptr, nf, t_scan2.p, s));
+    HIPCHK(exclusive_scan_i64(t_nfc.as<int64_t>(), pl->fc_row_ptr, nf, t_scan2.p, s));
+    pl->nnz_ff = read_i64(c, pl->ff_row_ptr + nf);
+    pl->nnz_fc = read_i64(c, pl->fc_row_ptr + nf);
+    {
+        std::vector<int64_t> a(nf), b(nf);
+        if (nf) {
+            HIPCHK(hipMemcpyAsync(a.data(), t_nff.p, (size_t)nf * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(b.data(), t_nfc.p, (size_t)nf * 8, hipMemcpyDeviceToHost, s));
         }
-        ro[no] = run;
-        pl->n_rec_c = run;
-        HIPCHK(hipMemcpyAsync(pl->rec_off, ro.data(), (size_t)(no + 1) * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
+        for (int64_t r = 0; r < nf; ++r) pl->max_row = (int)std::max<int64_t>(pl->max_row, a[r] + b[r]);
     }
-    pl->n_rec = pl->n_rec_c + 16 * K;
-    if (pl->n_rec >= (int64_t)0xFFFFFFFFll) return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 reduction records");
-    ALLOC(pl->ve_ids, int32_t, ve_total + 1);
-    const int64_t NR = pl->n_rec;
-    const uint64_t key_space = (uint64_t)nf * (uint64_t)V + (uint64_t)nf;
-    {
-        TMP(t_rk, (size_t)(NR + 1) * 16);
-        TMP(t_rv, (size_t)(NR + 1) * 8);
-        uint64_t* keys = t_rk.as<uint64_t>();
-        uint32_t* vals = t_rv.as<uint32_t>();
-        HIPCHK(launch_pattern(true, pl->tets, pl->outer_ids, no, pl->pair_off, pl->pair_m, pl->free_id, V, nf,
-                              hash_cap, t_ucount.as<int64_t>(), pl->ve_off, pl->ve_ids, pl->rec_off, keys, vals,
-                              t_err.as<unsigned>(), s));
-        HIPCHK(launch_g_keys(pl->tets, pl->region, pl->trans_off, pl->free_id, K, V, nf, pl->n_rec_c, keys, vals,
-                             s));
-        {
-            TMP(t_rs3, radix_sort_temp_bytes(NR + 1));
-            HIPCHK(radix_sort_u64_u32(keys, vals, keys + NR, vals + NR, NR, bits_for(key_space), t_rs3.p, s));
-        }
-        // slots
-        TMP(t_flags, (size_t)(NR + 1) * 8);
-        TMP(t_fsc, (size_t)(NR + 2) * 8);
-        TMP(t_scan3, scan_temp_bytes(NR + 1) + 4096);
-        HIPCHK(launch_slot_flags(keys, NR, key_space, t_flags.as<int64_t>(), s));
-        HIPCHK(exclusive_scan_i64(t_flags.as<int64_t>(), t_fsc.as<int64_t>(), NR, t_scan3.p, s));
-        pl->n_slots = read_i64(c, t_fsc.as<int64_t>() + NR);
-        const int64_t NS = pl->n_slots;
-        ALLOC(pl->seg_off, int64_t, NS + 2);
-        TMP(t_skey, (size_t)(NS + 1) * 8);
-        HIPCHK(launch_slot_emit(keys, t_fsc.as<int64_t>(), NR, key_space, pl->seg_off, t_skey.as<uint64_t>(), s));
-        if (NS == 0) HIPCHK(hipMemsetAsync(pl->seg_off, 0, 8, s));
-        // CSR pattern
-        TMP(t_isff, (size_t)(NS + 1) * 8);
-        TMP(t_isfc, (size_t)(NS + 1) * 8);
-        TMP(t_rowff, (size_t)(nf + 2) * 8);
-        TMP(t_rowfc, (size_t)(nf + 2) * 8);
-        HIPCHK(hipMemsetAsync(t_rowff.p, 0, (size_t)(nf + 2) * 8, s));
-        HIPCHK(hipMemsetAsync(t_rowfc.p, 0, (size_t)(nf + 2) * 8, s));
-        HIPCHK(launch_slot_classify(t_skey.as<uint64_t>(), NS, V, nf, pl->free_id, t_isff.as<int64_t>(),
-                                    t_isfc.as<int64_t>(), t_rowff.as<int64_t>(), t_rowfc.as<int64_t>(), s));
-        TMP(t_ffsc, (size_t)(NS + 2) * 8);
-        TMP(t_fcsc, (size_t)(NS + 2) * 8);
-        HIPCHK(exclusive_scan_i64(t_isff.as<int64_t>(), t_ffsc.as<int64_t>(), NS, t_scan3.p, s));
-        HIPCHK(exclusive_scan_i64(t_isfc.as<int64_t>(), t_fcsc.as<int64_t>(), NS, t_scan3.p, s));
-        pl->nnz_ff = read_i64(c, t_ffsc.as<int64_t>() + NS);
-        pl->nnz_fc = read_i64(c, t_fcsc.as<int64_t>() + NS);
-        ALLOC(pl->ff_row_ptr, int64_t, nf + 2);
-        ALLOC(pl->fc_row_ptr, int64_t, nf + 2);
-        ALLOC(pl->ff_col, int32_t, pl->nnz_ff + 1);
-        ALLOC(pl->fc_col, int32_t, pl->nnz_fc + 1);
-        ALLOC(pl->dest, int64_t, NS + 1);
-        HIPCHK(exclusive_scan_i64(t_rowff.as<int64_t>(), pl->ff_row_ptr, nf, t_scan3.p, s));
-        HIPCHK(exclusive_scan_i64(t_rowfc.as<int64_t>(), pl->fc_row_ptr, nf, t_scan3.p, s));
-        HIPCHK(launch_slot_dest(t_skey.as<uint64_t>(), NS, V, nf, pl->free_id, t_ffsc.as<int64_t>(),
-                                t_fcsc.as<int64_t>(), pl->nnz_ff, pl->nnz_fc, pl->dest, pl->ff_col, pl->fc_col, s));
-        ALLOC(pl->perm, uint32_t, NR + 1);
-        HIPCHK(hipMemcpyAsync(pl->perm, vals, (size_t)NR * 4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-    }
+    if (row_assemble_lds_bytes(pl->max_row) + row_assemble_static_lds() > c->lds_max)
+        return fail(c, NLFEM_E_UNSUPPORTED, "matrix row too large for LDS accumulation");
+    ALLOC(pl->ff_col, int32_t, pl->nnz_ff + 1);
+    ALLOC(pl->fc_col, int32_t, pl->nnz_fc + 1);
+    ALLOC(pl->all_cols, int32_t, pl->nnz_ff + pl->nnz_fc + 1);
+    HIPCHK(launch_row_pattern(true, rp, nf, row_cap, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), pl->ff_row_ptr,
+                              pl->fc_row_ptr, pl->all_cols, pl->ff_col, pl->fc_col, t_err.as<unsigned>(), s));
+    HIPCHK(hipStreamSynchronize(s));
     pl->times[2] = tpat.stop();
     // ---- numeric workspace -------------------------------------------------
-    ALLOC(pl->g_buf, double, 10 * P + 10);
-    ALLOC(pl->rec_val, double, NR + 1);
-    ALLOC(pl->rhs_f, double, nf + 1);
+    ALLOC(pl->cblk, double, 4 * VT + 4);
+    ALLOC(pl->oblk, double, 20 * no + 20);
+    ALLOC(pl->gacc, unsigned long long, 22 * K + 22);
+    ALLOC(pl->gvals, double, 10 * K + 10);
     ALLOC(pl->fc_val_int, double, pl->nnz_fc + 1);
-    // fixed-point scale of the coarse words: per outer point, sum_m f_m S0 <= 4 |M_n| max|E|
-    // (S0 <= 2 |E_m| for one pair: subtets plus a Monte Carlo count of at most N)
+    // fixed-point scales (each sum stays below 2^62 in units of its coarse word):
+    //  T0_k, R_k(v) <= B_R = sum over the pair list of f_m S0 <= 4 max_pairs max|E|
+    //    (S0 <= 2 |E_m| for one pair: subtets plus a Monte Carlo count of at most N)
+    //  G_m cut part <= |psi| max|E|^2 2 max_inner, inside weight <= |psi| max|E| max_inner
+    //  one row slot: at most 4 max_vt terms of C, O (<= |psi| max|E| B_R / 4) or G
     {
         TMP(t_vmax, 16);
         HIPCHK(reduce_max_i64((const int64_t*)pl->vol, K, t_vmax.as<int64_t>(), s));  // non-negative doubles
         int64_t bitsv = read_i64(c, t_vmax.as<int64_t>());
         double vmax;
         std::memcpy(&vmax, &bitsv, 8);
-        double bound = 4.0 * (double)std::max<int64_t>(pl->max_pairs, 1) * vmax;
-        int e = 0;
-        std::frexp(bound, &e);  // bound < 2^e
-        pl->fx_shift = 62 - e;
+        const double apsi = std::fabs(pl->psi);
+        const double bR = 4.0 * (double)std::max<int64_t>(pl->max_pairs, 1) * vmax;
+        const double bW = 2.0 * apsi * vmax * (double)std::max<int64_t>(pl->max_inner, 1);
+        const double bG = 4.0 * apsi * vmax * vmax * (double)std::max<int64_t>(pl->max_inner, 1);
+        const double bC = apsi * vmax * bR * 0.5 + bG + bW * vmax;
+        const double bRow = bC * 8.0 * (double)std::max<int64_t>(pl->max_vt, 1);
+        pl->fx_shift = shift_for(bR);
+        pl->w_shift = shift_for(bW);
+        pl->g_shift = shift_for(bG);
+        pl->row_shift = shift_for(bRow);
     }
     pl->times[0] = total.stop();
     return NLFEM_OK;
+}
+
+RowPlan make_row_plan(nlfem_plan* pl) {
+    RowPlan rp;
+    rp.tets = pl->tets;
+    rp.region = pl->region;
+    rp.inner_cnt = pl->inner_cnt;
+    rp.free_id = pl->free_id;
+    rp.free_to_vertex = pl->free_to_vertex;
+    rp.outer_ids = pl->outer_ids;
+    rp.outer_pos = pl->outer_pos;
+    rp.vt_off = pl->vt_off;
+    rp.vt_val = pl->vt_val;
+    rp.ve_off = pl->ve_off;
+    rp.ve_ids = pl->ve_ids;
+    rp.ve_owner = pl->ve_owner;
+    rp.inc_off = pl->inc_off;
+    rp.inc_val = pl->inc_val;
+    rp.ff_row_ptr = pl->ff_row_ptr;
+    rp.fc_row_ptr = pl->fc_row_ptr;
+    rp.all_cols = pl->all_cols;
+    rp.fc_col = pl->fc_col;
+    rp.max_row = std::max(pl->max_row, 1);
+    return rp;
 }
 
 IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
@@ -503,10 +552,8 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.pair_off = pl->pair_off;
     a.pair_m = pl->pair_m;
     a.pair_cls = pl->pair_cls;
-    a.tpos = pl->tpos;
     a.ve_off = pl->ve_off;
     a.ve_ids = pl->ve_ids;
-    a.rec_off = pl->rec_off;
     a.f_qp = f_qp;
     a.delta = pl->delta;
     a.psi = pl->psi;
@@ -514,10 +561,32 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.key0 = (uint32_t)(pl->seed & 0xFFFFFFFFull);
     a.key1 = (uint32_t)(pl->seed >> 32);
     a.fx_shift = pl->fx_shift;
+    a.g_shift = pl->g_shift;
+    a.w_shift = pl->w_shift;
     a.umax = std::max(pl->umax, 1);
-    a.g_buf = pl->g_buf;
-    a.rec_val = pl->rec_val;
+    a.cblk = pl->cblk;
+    a.oblk = pl->oblk;
+    a.gacc = pl->gacc;
     return a;
+}
+
+// numeric phase of one plan after its integration: G_m, then the rows
+nlfem_status enqueue_rows(nlfem_ctx* c, nlfem_plan* pl, const double* g_nodal, double* ff_val, double* fc_val,
+                          double* rhs, hipStream_t s) {
+    HIPCHK(launch_g_finalize(pl->K, pl->region, pl->inner_cnt, pl->vol, pl->gacc, pl->g_shift, pl->w_shift, pl->gvals,
+                             s));
+    RowPlan rp = make_row_plan(pl);
+    RowNumeric nm;
+    nm.cblk = pl->cblk;
+    nm.oblk = pl->oblk;
+    nm.gvals = pl->gvals;
+    nm.g_nodal = g_nodal;
+    nm.row_shift = pl->row_shift;
+    nm.ff_val = ff_val;
+    nm.fc_val = fc_val ? fc_val : pl->fc_val_int;
+    nm.rhs = rhs;
+    HIPCHK(launch_row_assemble(rp, nm, pl->n_free, s));
+    return NLFEM_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -611,16 +680,12 @@ void batch_free(nlfem_batch* b) {
 // numeric phase of every mesh of the batch on stream s
 nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStream_t s, int block, int grid) {
     nlfem_ctx* c = b->ctx;
+    for (nlfem_plan* pl : b->plans) HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
     HIPCHK(launch_integrate_batch(b->d_descs, b->d_items, b->n_items, b->d_head, b->umax_all, b->fp32, block, grid, s));
     for (size_t i = 0; i < b->plans.size(); ++i) {
-        nlfem_plan* pl = b->plans[i];
         const nlfem_batch::Out& o = b->outs[i];
-        HIPCHK(launch_g_reduce(pl->region, pl->K, pl->trans_off, pl->g_buf, pl->n_rec_c, pl->rec_val, s));
-        HIPCHK(launch_fill_zero_f64(pl->rhs_f, pl->n_free, s));
-        HIPCHK(launch_segsum(pl->seg_off, pl->perm, pl->rec_val, pl->n_slots, pl->dest, pl->nnz_ff, pl->nnz_fc,
-                             o.ff_val, o.fc_val, pl->rhs_f, s));
-        HIPCHK(launch_rhs_final(pl->n_free, pl->rhs_f, pl->fc_row_ptr, pl->fc_col, o.fc_val,
-                                g_nodal ? g_nodal[i] : nullptr, o.rhs, s));
+        nlfem_status st = enqueue_rows(c, b->plans[i], g_nodal ? g_nodal[i] : nullptr, o.ff_val, o.fc_val, o.rhs, s);
+        if (st != NLFEM_OK) return st;
     }
     return NLFEM_OK;
 }
@@ -765,15 +830,12 @@ nlfem_status nlfem_assemble(nlfem_plan* pl, const double* f_qp, const double* g_
     if (free_to_vertex) HIPCHK(launch_copy_i32(pl->free_to_vertex, free_to_vertex, nf, s));
     IntegrateArgs a = make_args(pl, f_qp);
     Timer tint(s);
+    HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
     HIPCHK(launch_integrate(a, pl->precision == NLFEM_FP32_LOCAL, s));
     pl->times[3] = tint.stop();
     Timer tred(s);
-    HIPCHK(launch_g_reduce(pl->region, pl->K, pl->trans_off, pl->g_buf, pl->n_rec_c, pl->rec_val, s));
-    HIPCHK(launch_fill_zero_f64(pl->rhs_f, nf, s));
-    double* fcv = fc_val ? fc_val : pl->fc_val_int;
-    HIPCHK(launch_segsum(pl->seg_off, pl->perm, pl->rec_val, pl->n_slots, pl->dest, pl->nnz_ff, pl->nnz_fc, ff_val, fcv,
-                         pl->rhs_f, s));
-    HIPCHK(launch_rhs_final(nf, pl->rhs_f, pl->fc_row_ptr, pl->fc_col, fcv, g_nodal, rhs, s));
+    nlfem_status st = enqueue_rows(c, pl, g_nodal, ff_val, fc_val, rhs, s);
+    if (st != NLFEM_OK) return st;
     pl->times[4] = tred.stop();
     pl->times[5] = total.stop();
     return NLFEM_OK;

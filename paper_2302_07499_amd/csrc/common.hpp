@@ -75,31 +75,11 @@ hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const i
                                const int32_t* hit_m, const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls,
                                hipStream_t s);
 hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s);
-// local vertex sets: count pass writes ucount[n]; fill pass writes ve_ids and record keys
-hipError_t launch_pattern(bool fill, const int32_t* tets, const int32_t* outer_ids, int64_t n_outer,
-                          const int64_t* pair_off, const int32_t* pair_m, const int32_t* free_id,
-                          int64_t V, int64_t n_free, int hash_cap, int64_t* ucount, const int64_t* ve_off,
-                          int32_t* ve_ids, const int64_t* rec_off, uint64_t* rec_keys, uint32_t* rec_vals,
+// local vertex sets Ve of the outer tets: count pass writes ucount[oi], fill
+// pass writes the sorted sets at ve_off
+hipError_t launch_pattern(bool fill, const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
+                          const int32_t* pair_m, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
                           unsigned* err, hipStream_t s);
-hipError_t launch_g_keys(const int32_t* tets, const uint8_t* region, const int64_t* trans_off,
-                         const int32_t* free_id, int64_t K, int64_t V, int64_t n_free, int64_t rec_base,
-                         uint64_t* rec_keys, uint32_t* rec_vals, hipStream_t s);
-hipError_t launch_trans_keys(const int32_t* pair_m, int64_t P, uint64_t* keys, uint32_t* vals,
-                             hipStream_t s);
-hipError_t launch_trans_finish(const uint64_t* sorted_keys, const uint32_t* sorted_vals, int64_t P,
-                               int64_t K, int64_t* trans_off, uint32_t* tpos, hipStream_t s);
-hipError_t launch_slot_flags(const uint64_t* skeys, int64_t n, uint64_t key_space, int64_t* flags,
-                             hipStream_t s);
-// after the scan of flags: slot index per sorted record; emits seg_off and slot keys
-hipError_t launch_slot_emit(const uint64_t* skeys, const int64_t* fscan, int64_t n, uint64_t key_space,
-                            int64_t* seg_off, uint64_t* slot_key, hipStream_t s);
-hipError_t launch_slot_classify(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
-                                const int32_t* free_id, int64_t* is_ff, int64_t* is_fc, int64_t* row_ff,
-                                int64_t* row_fc, hipStream_t s);
-hipError_t launch_slot_dest(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
-                            const int32_t* free_id, const int64_t* ff_scan, const int64_t* fc_scan,
-                            int64_t nnz_ff, int64_t nnz_fc, int64_t* dest, int32_t* ff_col, int32_t* fc_col,
-                            hipStream_t s);
 
 // numeric kernels (k_numeric.hip)
 struct IntegrateArgs {
@@ -112,18 +92,19 @@ struct IntegrateArgs {
     const int64_t* pair_off;
     const int32_t* pair_m;
     const uint16_t* pair_cls;
-    const uint32_t* tpos;
     const int64_t* ve_off;
     const int32_t* ve_ids;
-    const int64_t* rec_off;
     const double* f_qp;  // may be null
     double delta, psi;
     int mc_samples;
     uint32_t key0, key1;
-    int fx_shift;  // fixed-point scale 2^fx_shift
+    int fx_shift;  // scale 2^fx_shift of the LDS sums T0 and R
+    int g_shift;   // scale of the cut part of G_m (global accumulators)
+    int w_shift;   // scale of the inside-count weight of G_m
     int umax;
-    double* g_buf;   // [P][10] at transposed positions
-    double* rec_val;
+    double* cblk;              // [sum |Ve|][4] cross blocks, at 4 * ve_off
+    double* oblk;              // [n_outer][20]: 4x4 outer-outer block, then 4 load-vector terms
+    unsigned long long* gacc;  // [K][22] two-word sums: 10 cut S2 sums, then the inside weight
 };
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 // persistent integration over work items (mesh index, outer position); block 128 or 256
@@ -134,17 +115,60 @@ size_t integrate_lds_bytes(int umax);
 // out_S [slots][15], out_qm [slots][3] = (q, m, class)
 hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, int64_t o_hi, double* out_S,
                               int32_t* out_qm, hipStream_t s);
-hipError_t launch_g_reduce(const uint8_t* region, int64_t K, const int64_t* trans_off, const double* g_buf,
-                           int64_t rec_base, double* rec_val, hipStream_t s);
 hipError_t launch_class_counts(const uint16_t* pair_cls, int64_t P, unsigned long long* counts, hipStream_t s);
-hipError_t launch_segsum(const int64_t* seg_off, const uint32_t* perm, const double* rec_val, int64_t n_slots,
-                         const int64_t* dest, int64_t nnz_ff, int64_t nnz_fc, double* ff_val, double* fc_val,
-                         double* rhs_f, hipStream_t s);
-hipError_t launch_rhs_final(int64_t n_free, const double* rhs_f, const int64_t* fc_row_ptr, const int32_t* fc_col,
-                            const double* fc_val, const double* g, double* rhs, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int64_t n, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s);
+
+// row-wise assembly (k_rows.hip)
+struct RowPlan {
+    const int32_t* tets;
+    const uint8_t* region;
+    const int32_t* inner_cnt;  // [K] pairs per inner tet (0: the tet occurs in no ball)
+    const int32_t* free_id;
+    const int32_t* free_to_vertex;
+    const int32_t* outer_ids;
+    const int32_t* outer_pos;  // [K] position among the outer tets or -1
+    const int64_t* vt_off;     // [V+1] vertex -> (4 tet + local index), sorted by tet
+    const uint32_t* vt_val;
+    const int64_t* ve_off;
+    const int32_t* ve_ids;
+    const int32_t* ve_owner;   // [sum |Ve|] outer position owning each entry
+    const int64_t* inc_off;    // [V+1] vertex -> entries of the Ve sets holding it
+    const uint32_t* inc_val;
+    const int64_t* ff_row_ptr;
+    const int64_t* fc_row_ptr;
+    const int32_t* all_cols;   // sorted vertex columns of each row, at ff_row_ptr[r] + fc_row_ptr[r]
+    const int32_t* fc_col;
+    int max_row;
+};
+struct RowNumeric {
+    const double* cblk;
+    const double* oblk;
+    const double* gvals;  // [K][10] G_m upper triangles
+    const double* g_nodal;
+    int row_shift;
+    double* ff_val;
+    double* fc_val;
+    double* rhs;
+};
+hipError_t launch_vt_keys(const int32_t* tets, int64_t K, uint64_t* keys, uint32_t* vals, hipStream_t s);
+// off[k] = first position of sorted key >= k, for k in [0, n_keys]
+hipError_t launch_offsets(const uint64_t* skeys, int64_t n, int64_t n_keys, int64_t* off, hipStream_t s);
+hipError_t launch_inc_keys(const int64_t* ve_off, int64_t n_outer, const int32_t* ve_ids, uint64_t* keys,
+                           uint32_t* vals, int32_t* owner, hipStream_t s);
+hipError_t launch_inner_count(const int32_t* pair_m, int64_t P, int32_t* inner_cnt, hipStream_t s);
+hipError_t launch_outer_pos(const int32_t* outer_ids, int64_t n_outer, int32_t* outer_pos, int64_t K, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int64_t* n_ff,
+                              int64_t* n_fc, const int64_t* ff_row_ptr, const int64_t* fc_row_ptr, int32_t* all_cols,
+                              int32_t* ff_col, int32_t* fc_col, unsigned* err, hipStream_t s);
+hipError_t launch_g_finalize(int64_t K, const uint8_t* region, const int32_t* inner_cnt, const double* vol,
+                             const unsigned long long* gacc, int g_shift, int w_shift, double* gvals, hipStream_t s);
+size_t row_assemble_lds_bytes(int max_row);  // dynamic part
+size_t row_assemble_static_lds();
+hipError_t launch_row_assemble(const RowPlan& rp, const RowNumeric& nm, int64_t n_rows, hipStream_t s);
 
 // CG (k_cg.hip)
 hipError_t launch_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* x,

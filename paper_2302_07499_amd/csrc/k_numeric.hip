@@ -1,6 +1,5 @@
-// Numeric phase: per-pair inner integrals (fullcaps), reduction of each outer
-// tet's contributions in LDS, the inner-element terms, the sorted-key
-// segmented sums into the CSR values and the right-hand side.
+// Numeric phase: per-pair inner integrals (fullcaps) and their reduction per
+// outer tet.
 //
 // Decomposition of the pair contribution (main assembly algorithm, Sec. 4.3):
 // with a_u(y) = phi_(m,u)(y) - phi_(n,u)(p) and the moments S0, S1, S2 of the
@@ -10,8 +9,13 @@
 // over the pairs, the c c^T S0 terms only need T0_k = sum_m f_m S0 per outer
 // point, the cross terms only R_k(v) = sum_{m containing v} f_m S1_v per
 // (outer point, vertex), and the S2 terms only the per-inner-tet sum
-// G_m = sum_q psi f_m w_q S2.  The first two are reduced inside the outer
-// tet's workgroup, G_m through a buffer ordered by inner tet.
+// G_m = sum_q psi f_m w_q S2 (needed on T_Omega only: T_OmegaI rows carry no
+// unknowns).  T0 and R are reduced inside the outer tet's workgroup and
+// leave it as the cross block C^n[i][j] = -psi w sum_k c_kj R_k(Ve_i) and the
+// outer block O^n[j][j'] = psi w sum_k c_kj c_kj' T0_k.  G_m is summed in
+// global two-word fixed-point accumulators: the Monte Carlo / subdivision
+// part of cut points directly, inside points as a count weight times the
+// closed-form 4-point-rule moments of E_m (k_rows.hip).
 #include "device_geom.hpp"
 
 #ifndef NLFEM_INTEGRATE_WAVES
@@ -46,8 +50,21 @@ __device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long lon
     atomicAdd(lo, (unsigned long long)__double2ull_rn(r * 281474976710656.0));  // r * 2^48
 }
 
+// carry-normalised: the fine word is reduced below 2^48 first, so both
+// conversions are exact for totals below 2^53 coarse units
 __device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo, int shift) {
-    return (double)hi * ldexp(1.0, -shift) + (double)lo * ldexp(1.0, -(shift + FX_LO_BITS));
+    const unsigned long long h = hi + (lo >> FX_LO_BITS);
+    const double v = (double)(lo & ((1ull << FX_LO_BITS) - 1ull)) * 0x1p-48 + (double)h;
+    return ldexp(v, -shift);
+}
+
+// signed variant for global accumulators: the coarse word is two's complement
+__device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned long long* lo, double x, double fx) {
+    const double xs = x * fx;
+    const double h = floor(xs);
+    const double r = xs - h;
+    atomicAdd(hi, (unsigned long long)(long long)h);
+    atomicAdd(lo, (unsigned long long)__double2ull_rn(r * 281474976710656.0));
 }
 
 // One workgroup of BLOCK threads integrates one outer tet.  LDS: R [4][umax]
@@ -76,9 +93,12 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
         outer_point(Xn, t, P[t]);
     }
     const double w = a.vol[n] * 0.25;
+    const double pw = a.psi * w;
     __syncthreads();
     const double d2 = a.delta * a.delta;
     const double fx = ldexp(1.0, a.fx_shift);
+    const double gfx = ldexp(1.0, a.g_shift);
+    const double wfx = ldexp(1.0, a.w_shift);
     const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
     for (int64_t p = p0 + t; p < p1; p += BLOCK) {
         const int m = a.pair_m[p];
@@ -92,6 +112,7 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
         for (int j = 0; j < 4; ++j) lv[j] = lower_bound_i32(ve, U, a.tets[4 * (int64_t)m + j]);
         double g[10];
         for (int i = 0; i < 10; ++i) g[i] = 0.0;
+        int n_in = 0, n_cut = 0;
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
             const int c = (int)((code >> (3 * k)) & 7u);
@@ -103,47 +124,43 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
             for (int j = 0; j < 4; ++j)
                 if (lv[j] < U)  // always true: Ve holds every vertex of the pair list's tets
                     fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
-            for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
+            if (c == C_IN) {
+                ++n_in;
+            } else {
+                ++n_cut;
+                for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
+            }
         }
         if (omega) {
-            double* gb = a.g_buf + 10 * (size_t)a.tpos[p];
-            const double sc = a.psi * w;
-            for (int i = 0; i < 10; ++i) gb[i] = g[i] * sc;
+            unsigned long long* ga = a.gacc + 22 * (int64_t)m;
+            if (n_in) fxs_add_global(&ga[20], &ga[21], pw * (double)n_in, wfx);
+            if (n_cut)
+                for (int i = 0; i < 10; ++i) fxs_add_global(&ga[2 * i], &ga[2 * i + 1], pw * g[i], gfx);
         }
     }
     __syncthreads();
-    const double pw = a.psi * w;
     const int sh = a.fx_shift;
-    int32_t vn[4];
-    for (int j = 0; j < 4; ++j) vn[j] = a.tets[4 * (int64_t)n + j];
-    double t0[4];
-    for (int k = 0; k < 4; ++k) t0[k] = fx_value(T0[k], T0l[k], sh);
-    const int64_t rb = a.rec_off[oi];
-    // direct rows u = V_n[j], columns Ve[i]: psi w (sum_k c_u c_v T0_k [v in V_n] - sum_k c_u R_k(v))
-    for (int r = t; r < 4 * U; r += BLOCK) {
-        const int j = r / U, i = r - j * U;
-        double cR = 0.0;
-        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
-        const int32_t v = ve[i];
-        double O = 0.0;
-        for (int jj = 0; jj < 4; ++jj)
-            if (vn[jj] == v)
-                for (int k = 0; k < 4; ++k) O += (rule_w(k, j) * rule_w(k, jj)) * t0[k];
-        a.rec_val[rb + r] = pw * (O - cR);
-    }
-    // transposed rows Ve[i], columns u = V_n[j]: the cross term again
+    // cross block [Ve_i][j] = -psi w sum_k c_kj R_k(Ve_i)
+    double* cb = a.cblk + 4 * vb;
     for (int r = t; r < 4 * U; r += BLOCK) {
         const int i = r >> 2, j = r & 3;
         double cR = 0.0;
         for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
-        a.rec_val[rb + 4 * (int64_t)U + r] = -(pw * cR);
+        cb[r] = -(pw * cR);
     }
-    // load vector: sum_k w c_u f(p_k)
-    if (t < 4) {
+    // outer block and load vector (sum_k w c_kj f(p_k))
+    double* ob = a.oblk + 20 * oi;
+    if (t < 16) {
+        const int j = t >> 2, jj = t & 3;
+        double O = 0.0;
+        for (int k = 0; k < 4; ++k) O += (rule_w(k, j) * rule_w(k, jj)) * fx_value(T0[k], T0l[k], sh);
+        ob[t] = pw * O;
+    } else if (t < 20) {
+        const int j = t - 16;
         double f = 0.0;
         if (a.f_qp)
-            for (int k = 0; k < 4; ++k) f += (w * rule_w(k, t)) * a.f_qp[4 * (int64_t)n + k];
-        a.rec_val[rb + 8 * (int64_t)U + t] = f;
+            for (int k = 0; k < 4; ++k) f += (w * rule_w(k, j)) * a.f_qp[4 * (int64_t)n + k];
+        ob[t] = f;
     }
 }
 
@@ -209,49 +226,9 @@ __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_
     }
 }
 
-__device__ __forceinline__ int tri4(int a, int b) {
-    // upper-triangle index of (a,b), a <= b: 00 01 02 03 11 12 13 22 23 33
-    const int rowstart[4] = {0, 4, 7, 9};
-    return rowstart[a] + (b - a);
-}
 
-// G_m = sum over the pairs (n, m) in transposed order; records [16] per tet
-__global__ void k_g_reduce(const uint8_t* region, int64_t K, const int64_t* trans_off, const double* g_buf,
-                           int64_t rec_base, double* rec_val) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= K) return;
-    const int64_t b = trans_off[e], c = trans_off[e + 1];
-    if (!region[e] || c <= b) return;
-    double G[10];
-    for (int j = 0; j < 10; ++j) G[j] = 0.0;
-    for (int64_t i = b; i < c; ++i)
-        for (int j = 0; j < 10; ++j) G[j] += g_buf[10 * i + j];
-    for (int x = 0; x < 4; ++x)
-        for (int y = 0; y < 4; ++y) rec_val[rec_base + 16 * e + 4 * x + y] = G[x <= y ? tri4(x, y) : tri4(y, x)];
-}
 
-__global__ void k_segsum(const int64_t* seg_off, const uint32_t* perm, const double* rec_val, int64_t n_slots,
-                         const int64_t* dest, int64_t nnz_ff, int64_t nnz_fc, double* ff_val, double* fc_val,
-                         double* rhs_f) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_slots) return;
-    double acc = 0.0;
-    for (int64_t i = seg_off[s]; i < seg_off[s + 1]; ++i) acc += rec_val[perm[i]];
-    const int64_t d = dest[s];
-    if (d < nnz_ff) ff_val[d] = acc;
-    else if (d < nnz_ff + nnz_fc) fc_val[d - nnz_ff] = acc;
-    else rhs_f[d - nnz_ff - nnz_fc] = acc;
-}
 
-__global__ void k_rhs_final(int64_t n_free, const double* rhs_f, const int64_t* fc_row_ptr, const int32_t* fc_col,
-                            const double* fc_val, const double* g, double* rhs) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_free) return;
-    double acc = 0.0;
-    if (g)
-        for (int64_t e = fc_row_ptr[r]; e < fc_row_ptr[r + 1]; ++e) acc = acc + fc_val[e] * g[fc_col[e]];
-    rhs[r] = rhs_f[r] - acc;
-}
 
 __global__ void k_fill_zero(double* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -318,28 +295,8 @@ hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, i
     return hipGetLastError();
 }
 
-hipError_t launch_g_reduce(const uint8_t* region, int64_t K, const int64_t* trans_off, const double* g_buf,
-                           int64_t rec_base, double* rec_val, hipStream_t s) {
-    if (K <= 0) return hipSuccess;
-    k_g_reduce<<<blocks_for(K), 256, 0, s>>>(region, K, trans_off, g_buf, rec_base, rec_val);
-    return hipGetLastError();
-}
 
-hipError_t launch_segsum(const int64_t* seg_off, const uint32_t* perm, const double* rec_val, int64_t n_slots,
-                         const int64_t* dest, int64_t nnz_ff, int64_t nnz_fc, double* ff_val, double* fc_val,
-                         double* rhs_f, hipStream_t s) {
-    if (n_slots <= 0) return hipSuccess;
-    k_segsum<<<blocks_for(n_slots), 256, 0, s>>>(seg_off, perm, rec_val, n_slots, dest, nnz_ff, nnz_fc, ff_val,
-                                                 fc_val, rhs_f);
-    return hipGetLastError();
-}
 
-hipError_t launch_rhs_final(int64_t n_free, const double* rhs_f, const int64_t* fc_row_ptr, const int32_t* fc_col,
-                            const double* fc_val, const double* g, double* rhs, hipStream_t s) {
-    if (n_free <= 0) return hipSuccess;
-    k_rhs_final<<<blocks_for(n_free), 256, 0, s>>>(n_free, rhs_f, fc_row_ptr, fc_col, fc_val, g, rhs);
-    return hipGetLastError();
-}
 
 hipError_t launch_fill_zero_f64(double* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -1,6 +1,6 @@
 // Symbolic phase: device mesh layout, uniform-grid cell list, exact FP64
 // ball classification of every (outer point, tet) pair, local vertex sets of
-// each outer tet, record keys of the sorted-key reduction and the CSR pattern.
+// each outer tet.  The CSR pattern is built row by row in k_rows.hip.
 #include "device_geom.hpp"
 
 namespace nlfem {
@@ -318,17 +318,13 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     return x;
 }
 
-// One block per outer tet: the sorted set Ve of vertices of its non-OUT inner
-// tets (LDS hash set, then bitonic sort), and in the fill pass the record keys
-// of its block of the reduction: [4][U] direct rows V_n x Ve, [U][4]
-// transposed rows Ve x V_n, [4] right-hand-side rows.  Keys of rows that are
-// not free are the dummy key (sorted past every real slot).
+// One block per outer tet: the sorted set Ve of vertices of the inner tets of
+// its pair list (LDS hash set, then bitonic sort).  The count pass writes |Ve|,
+// the fill pass the set itself at ve_off.
 template <bool FILL>
-__global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, const int32_t* outer_ids, int64_t n_outer,
-                                                 const int64_t* pair_off, const int32_t* pair_m, const int32_t* free_id,
-                                                 int64_t V, int64_t n_free, int hash_cap, int64_t* ucount,
-                                                 const int64_t* ve_off, int32_t* ve_ids, const int64_t* rec_off,
-                                                 uint64_t* rec_keys, uint32_t* rec_vals, unsigned* err) {
+__global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
+                                                 const int32_t* pair_m, int hash_cap, int64_t* ucount,
+                                                 const int64_t* ve_off, int32_t* ve_ids, unsigned* err) {
     extern __shared__ uint32_t hs[];
     __shared__ int sU;
     const uint32_t EMPTY = 0xFFFFFFFFu;
@@ -383,137 +379,6 @@ __global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, const int3
     }
     const int64_t vb = ve_off[oi];
     for (int i = t; i < U; i += 256) ve_ids[vb + i] = (int32_t)hs[i];
-    const int n = outer_ids[oi];
-    int32_t vn[4], fn[4];
-    for (int j = 0; j < 4; ++j) {
-        vn[j] = tets[4 * (int64_t)n + j];
-        fn[j] = free_id[vn[j]];
-    }
-    const uint64_t dummy = (uint64_t)n_free * (uint64_t)V + (uint64_t)n_free;
-    const int64_t rb = rec_off[oi];
-    for (int r = t; r < 4 * U; r += 256) {
-        int j = r / U, i = r - j * U;
-        uint64_t key = (fn[j] >= 0) ? (uint64_t)fn[j] * (uint64_t)V + hs[i] : dummy;
-        rec_keys[rb + r] = key;
-        rec_vals[rb + r] = (uint32_t)(rb + r);
-    }
-    for (int r = t; r < 4 * U; r += 256) {
-        int i = r >> 2, j = r & 3;
-        int32_t fv = free_id[hs[i]];
-        uint64_t key = (fv >= 0) ? (uint64_t)fv * (uint64_t)V + (uint64_t)vn[j] : dummy;
-        rec_keys[rb + 4 * U + r] = key;
-        rec_vals[rb + 4 * U + r] = (uint32_t)(rb + 4 * U + r);
-    }
-    if (t < 4) {
-        uint64_t key = (fn[t] >= 0) ? (uint64_t)n_free * (uint64_t)V + (uint64_t)fn[t] : dummy;
-        rec_keys[rb + 8 * U + t] = key;
-        rec_vals[rb + 8 * U + t] = (uint32_t)(rb + 8 * U + t);
-    }
-}
-
-// G records: [K][4][4] rows V_m[a] (if free) x columns V_m[b] for the T_Omega
-// tets that occur in some ball (trans count > 0).
-__global__ void k_g_keys(const int32_t* tets, const uint8_t* region, const int64_t* trans_off, const int32_t* free_id,
-                         int64_t K, int64_t V, int64_t n_free, int64_t rec_base, uint64_t* rec_keys,
-                         uint32_t* rec_vals) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= K) return;
-    const uint64_t dummy = (uint64_t)n_free * (uint64_t)V + (uint64_t)n_free;
-    bool use = region[e] && trans_off[e + 1] > trans_off[e];
-    int32_t v[4];
-    for (int j = 0; j < 4; ++j) v[j] = tets[4 * e + j];
-    for (int a = 0; a < 4; ++a) {
-        int32_t fa = free_id[v[a]];
-        for (int b = 0; b < 4; ++b) {
-            int64_t r = rec_base + 16 * e + 4 * a + b;
-            rec_keys[r] = (use && fa >= 0) ? (uint64_t)fa * (uint64_t)V + (uint64_t)v[b] : dummy;
-            rec_vals[r] = (uint32_t)r;
-        }
-    }
-}
-
-__global__ void k_trans_keys(const int32_t* pair_m, int64_t P, uint64_t* keys, uint32_t* vals) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    keys[p] = (uint64_t)pair_m[p];
-    vals[p] = (uint32_t)p;
-}
-
-__global__ void k_trans_finish(const uint64_t* skeys, const uint32_t* svals, int64_t P, int64_t K, int64_t* trans_off,
-                               uint32_t* tpos) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > P) return;
-    int64_t prev = (i == 0) ? -1 : (int64_t)skeys[i - 1];
-    int64_t cur = (i == P) ? K : (int64_t)skeys[i];
-    for (int64_t c = prev + 1; c <= cur; ++c) trans_off[c] = i;
-    if (i < P) tpos[svals[i]] = (uint32_t)i;
-}
-
-__global__ void k_slot_flags(const uint64_t* skeys, int64_t n, uint64_t key_space, int64_t* flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t k = skeys[i];
-    flags[i] = (k < key_space && (i == 0 || skeys[i - 1] != k)) ? 1 : 0;
-}
-
-__global__ void k_slot_emit(const uint64_t* skeys, const int64_t* fscan, int64_t n, uint64_t key_space,
-                            int64_t* seg_off, uint64_t* slot_key) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t k = skeys[i];
-    if (k >= key_space) return;
-    int64_t s = fscan[i];
-    if (i == 0 || skeys[i - 1] != k) {
-        seg_off[s] = i;
-        slot_key[s] = k;
-    }
-    if (i == n - 1 || skeys[i + 1] >= key_space) seg_off[fscan[n]] = i + 1;
-}
-
-__global__ void k_slot_classify(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
-                                const int32_t* free_id, int64_t* is_ff, int64_t* is_fc, int64_t* row_ff,
-                                int64_t* row_fc) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_slots) return;
-    uint64_t k = slot_key[s];
-    uint64_t mat = (uint64_t)n_free * (uint64_t)V;
-    int64_t ff = 0, fc = 0;
-    if (k < mat) {
-        int64_t row = (int64_t)(k / (uint64_t)V);
-        int64_t col = (int64_t)(k - (uint64_t)row * (uint64_t)V);
-        if (free_id[col] >= 0) {
-            ff = 1;
-            atomicAdd((unsigned long long*)&row_ff[row], 1ull);
-        } else {
-            fc = 1;
-            atomicAdd((unsigned long long*)&row_fc[row], 1ull);
-        }
-    }
-    is_ff[s] = ff;
-    is_fc[s] = fc;
-}
-
-__global__ void k_slot_dest(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
-                            const int32_t* free_id, const int64_t* ff_scan, const int64_t* fc_scan, int64_t nnz_ff,
-                            int64_t nnz_fc, int64_t* dest, int32_t* ff_col, int32_t* fc_col) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_slots) return;
-    uint64_t k = slot_key[s];
-    uint64_t mat = (uint64_t)n_free * (uint64_t)V;
-    if (k < mat) {
-        int64_t row = (int64_t)(k / (uint64_t)V);
-        int64_t col = (int64_t)(k - (uint64_t)row * (uint64_t)V);
-        int32_t fcid = free_id[col];
-        if (fcid >= 0) {
-            dest[s] = ff_scan[s];
-            ff_col[ff_scan[s]] = fcid;
-        } else {
-            dest[s] = nnz_ff + fc_scan[s];
-            fc_col[fc_scan[s]] = (int32_t)col;
-        }
-    } else {
-        dest[s] = nnz_ff + nnz_fc + (int64_t)(k - mat);
-    }
 }
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -596,73 +461,17 @@ hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot,
     return hipGetLastError();
 }
 
-hipError_t launch_pattern(bool fill, const int32_t* tets, const int32_t* outer_ids, int64_t n_outer,
-                          const int64_t* pair_off, const int32_t* pair_m, const int32_t* free_id, int64_t V,
-                          int64_t n_free, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
-                          const int64_t* rec_off, uint64_t* rec_keys, uint32_t* rec_vals, unsigned* err,
-                          hipStream_t s) {
+hipError_t launch_pattern(bool fill, const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
+                          const int32_t* pair_m, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
+                          unsigned* err, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
     size_t sh = (size_t)hash_cap * sizeof(uint32_t);
     if (fill)
-        k_pattern<true><<<(unsigned)n_outer, 256, sh, s>>>(tets, outer_ids, n_outer, pair_off, pair_m, free_id, V,
-                                                          n_free, hash_cap, ucount, ve_off, ve_ids, rec_off,
-                                                          rec_keys, rec_vals, err);
+        k_pattern<true><<<(unsigned)n_outer, 256, sh, s>>>(tets, n_outer, pair_off, pair_m, hash_cap, ucount, ve_off,
+                                                          ve_ids, err);
     else
-        k_pattern<false><<<(unsigned)n_outer, 256, sh, s>>>(tets, outer_ids, n_outer, pair_off, pair_m, free_id, V,
-                                                           n_free, hash_cap, ucount, ve_off, ve_ids, rec_off,
-                                                           rec_keys, rec_vals, err);
-    return hipGetLastError();
-}
-
-hipError_t launch_g_keys(const int32_t* tets, const uint8_t* region, const int64_t* trans_off, const int32_t* free_id,
-                         int64_t K, int64_t V, int64_t n_free, int64_t rec_base, uint64_t* rec_keys,
-                         uint32_t* rec_vals, hipStream_t s) {
-    if (K <= 0) return hipSuccess;
-    k_g_keys<<<blocks_for(K), 256, 0, s>>>(tets, region, trans_off, free_id, K, V, n_free, rec_base, rec_keys,
-                                           rec_vals);
-    return hipGetLastError();
-}
-
-hipError_t launch_trans_keys(const int32_t* pair_m, int64_t P, uint64_t* keys, uint32_t* vals, hipStream_t s) {
-    if (P <= 0) return hipSuccess;
-    k_trans_keys<<<blocks_for(P), 256, 0, s>>>(pair_m, P, keys, vals);
-    return hipGetLastError();
-}
-
-hipError_t launch_trans_finish(const uint64_t* sorted_keys, const uint32_t* sorted_vals, int64_t P, int64_t K,
-                               int64_t* trans_off, uint32_t* tpos, hipStream_t s) {
-    k_trans_finish<<<blocks_for(P + 1), 256, 0, s>>>(sorted_keys, sorted_vals, P, K, trans_off, tpos);
-    return hipGetLastError();
-}
-
-hipError_t launch_slot_flags(const uint64_t* skeys, int64_t n, uint64_t key_space, int64_t* flags, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    k_slot_flags<<<blocks_for(n), 256, 0, s>>>(skeys, n, key_space, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_slot_emit(const uint64_t* skeys, const int64_t* fscan, int64_t n, uint64_t key_space,
-                            int64_t* seg_off, uint64_t* slot_key, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    k_slot_emit<<<blocks_for(n), 256, 0, s>>>(skeys, fscan, n, key_space, seg_off, slot_key);
-    return hipGetLastError();
-}
-
-hipError_t launch_slot_classify(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
-                                const int32_t* free_id, int64_t* is_ff, int64_t* is_fc, int64_t* row_ff,
-                                int64_t* row_fc, hipStream_t s) {
-    if (n_slots <= 0) return hipSuccess;
-    k_slot_classify<<<blocks_for(n_slots), 256, 0, s>>>(slot_key, n_slots, V, n_free, free_id, is_ff, is_fc, row_ff,
-                                                        row_fc);
-    return hipGetLastError();
-}
-
-hipError_t launch_slot_dest(const uint64_t* slot_key, int64_t n_slots, int64_t V, int64_t n_free,
-                            const int32_t* free_id, const int64_t* ff_scan, const int64_t* fc_scan, int64_t nnz_ff,
-                            int64_t nnz_fc, int64_t* dest, int32_t* ff_col, int32_t* fc_col, hipStream_t s) {
-    if (n_slots <= 0) return hipSuccess;
-    k_slot_dest<<<blocks_for(n_slots), 256, 0, s>>>(slot_key, n_slots, V, n_free, free_id, ff_scan, fc_scan, nnz_ff,
-                                                    nnz_fc, dest, ff_col, fc_col);
+        k_pattern<false><<<(unsigned)n_outer, 256, sh, s>>>(tets, n_outer, pair_off, pair_m, hash_cap, ucount,
+                                                           ve_off, ve_ids, err);
     return hipGetLastError();
 }
 

@@ -97,8 +97,9 @@ void nlfem_rule_constants(double *alpha, double *beta);
 /* Validates the mesh, builds the device mesh layout and a uniform-grid cell
  * list, classifies every (outer quadrature point, tet) pair against the open
  * ball exactly in FP64 (IN / CUT(n_in) / OUT; Def. "simplex's dividing
- * strategy"), and builds the CSR pattern of the free rows and the sorted-key
- * reduction plan.  Mesh and mask are read during the call only.             */
+ * strategy"), and builds the local vertex set of every outer tet, the
+ * vertex-keyed lists that gather each matrix row, and the CSR pattern of the
+ * free rows.  Mesh and mask are read during the call only.                  */
 nlfem_status nlfem_plan_create(nlfem_ctx *ctx, const nlfem_mesh *mesh, const nlfem_params *params,
                                nlfem_plan **plan);
 
@@ -192,9 +193,75 @@ nlfem_status nlfem_batch_destroy(nlfem_batch *batch);
 
 /* Device kernel timing of the last nlfem_assemble / nlfem_plan_create on the
  * plan, measured with HIP events on the context's stream (milliseconds):
- * times[0] plan total, [1] classify, [2] pattern+sort, [3] integrate,
- * [4] reduction (G + segmented sums + rhs), [5] assemble total.             */
+ * times[0] plan total, [1] classify, [2] local vertex sets + row lists + CSR
+ * pattern, [3] integrate, [4] row assembly (inner-element terms, rows, rhs),
+ * [5] assemble total.                                                        */
 nlfem_status nlfem_plan_timings(const nlfem_plan *plan, double times[6]);
+
+/* ---- serving -----------------------------------------------------------------
+ * A request loop for assemble-and-solve requests of different meshes,
+ * horizons, sample counts and precisions (the solve of the linear system of
+ * Sec. 4.3 for each request, by CG).  The server owns n_slots slots, each a
+ * worker thread with its own HIP stream, and one device memory pool of
+ * pool_bytes (0 = half of the free device memory) from which every request
+ * takes all of its device buffers: mesh, pair lists, workspace, CSR and CG
+ * vectors stay on the device for the whole request.  Queued requests are
+ * admitted in arrival order, first fit, when a slot is free and their
+ * estimated footprint fits in the pool next to the running ones (a request
+ * passed over 16 times holds the others back until it fits).  A request that
+ * runs out of pool memory is re-queued with its measured need, and fails with
+ * NLFEM_E_OOM only when it does not fit alone.  Requests overlap on the
+ * device (continuous batching); each request's solution is bitwise the one it
+ * gets alone.                                                                  */
+typedef struct nlfem_server nlfem_server;
+
+typedef struct {
+    double rtol;       /* CG stop: ||r||_2 <= rtol ||b||_2                       */
+    int32_t max_iter;  /* CG iteration cap; 0 = 10 n_free + 100                  */
+} nlfem_solve_params;
+
+typedef struct {
+    int32_t state;            /* 0 queued, 1 running, 2 done, 3 failed                      */
+    int32_t status;           /* nlfem_status of a finished request                          */
+    int64_t n_free, nnz_ff, nnz_fc;
+    int64_t pair_counts[5];   /* as nlfem_plan_info                                          */
+    int32_t cg_iters;
+    int32_t attempts;         /* admissions (more than 1 after an out-of-pool re-queue)      */
+    double cg_rel_residual;
+    double queue_s, plan_s, assemble_s, solve_s;  /* arrival->admission, plan, assembly, CG + copy */
+    double latency_s;         /* arrival (submit) -> solution in host memory                 */
+    size_t est_bytes;         /* admission estimate of the device footprint                  */
+    size_t peak_bytes;        /* measured peak of pool memory held by the request            */
+} nlfem_request_info;
+
+typedef struct {
+    int64_t queued, running, done, failed;
+    int32_t max_running;      /* most requests that ran at once                              */
+    int32_t n_slots;
+    size_t pool_bytes, pool_used, pool_peak;
+} nlfem_server_counters;
+
+nlfem_status nlfem_server_create(int device, int32_t n_slots, size_t pool_bytes, nlfem_server **server);
+/* Queues one request.  mesh arrays (mem_kind must be 0), params.outer_mask,
+ * f_qp [n_tets][4] and g_nodal [n_vertices] are HOST memory (f_qp, g_nodal
+ * NULL = 0), copied before the call returns.  solve NULL = rtol 1e-10,
+ * default cap.  The arrival time of the request is the time of the call.      */
+nlfem_status nlfem_server_submit(nlfem_server *server, const nlfem_mesh *mesh, const nlfem_params *params,
+                                 const double *f_qp, const double *g_nodal, const nlfem_solve_params *solve,
+                                 uint64_t *ticket);
+nlfem_status nlfem_server_poll(nlfem_server *server, uint64_t ticket, nlfem_request_info *info);
+/* Waits until the request is done or failed (timeout_s < 0: no limit), then
+ * fills info (NULL allowed).                                                  */
+nlfem_status nlfem_server_wait(nlfem_server *server, uint64_t ticket, double timeout_s,
+                               nlfem_request_info *info);
+/* Copies a finished request's solution x [n_free] and free_to_vertex [n_free]
+ * (HOST, either NULL to skip) and forgets the request.                        */
+nlfem_status nlfem_server_take(nlfem_server *server, uint64_t ticket, double *x, int32_t *free_to_vertex);
+nlfem_status nlfem_server_stats(nlfem_server *server, nlfem_server_counters *stats);
+/* Message of the last failed request (owned by the server).                  */
+const char *nlfem_server_last_error(nlfem_server *server);
+/* Drops queued requests, waits for the running ones, frees the pool.         */
+nlfem_status nlfem_server_destroy(nlfem_server *server);
 
 #ifdef __cplusplus
 }

@@ -47,11 +47,36 @@ class nlfem_pair_record(C.Structure):
                 ("S", C.c_double * 15)]
 
 
+class nlfem_solve_params(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32)]
+
+
+class nlfem_request_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("n_free", C.c_int64), ("nnz_ff", C.c_int64),
+                ("nnz_fc", C.c_int64), ("pair_counts", C.c_int64 * 5), ("cg_iters", C.c_int32),
+                ("attempts", C.c_int32), ("cg_rel_residual", C.c_double), ("queue_s", C.c_double),
+                ("plan_s", C.c_double), ("assemble_s", C.c_double), ("solve_s", C.c_double),
+                ("latency_s", C.c_double), ("est_bytes", C.c_size_t), ("peak_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["pair_counts"] = list(self.pair_counts)
+        return d
+
+
+class nlfem_server_counters(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("running", C.c_int64), ("done", C.c_int64), ("failed", C.c_int64),
+                ("max_running", C.c_int32), ("n_slots", C.c_int32), ("pool_bytes", C.c_size_t),
+                ("pool_used", C.c_size_t), ("pool_peak", C.c_size_t)]
+
+
 EXPORTS = ["nlfem_create", "nlfem_destroy", "nlfem_last_error", "nlfem_memory_in_use", "nlfem_trim",
            "nlfem_rule_constants", "nlfem_plan_create", "nlfem_plan_info", "nlfem_assemble", "nlfem_cg",
            "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings",
            "nlfem_batch_create", "nlfem_batch_info", "nlfem_batch_assemble", "nlfem_batch_system",
-           "nlfem_batch_tuning", "nlfem_batch_destroy"]
+           "nlfem_batch_tuning", "nlfem_batch_destroy",
+           "nlfem_server_create", "nlfem_server_submit", "nlfem_server_poll", "nlfem_server_wait",
+           "nlfem_server_take", "nlfem_server_stats", "nlfem_server_last_error", "nlfem_server_destroy"]
 
 _lib = None
 
@@ -90,8 +115,18 @@ def load():
     L.nlfem_batch_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
     L.nlfem_batch_destroy.argtypes = [P]
+    L.nlfem_server_create.argtypes = [C.c_int, C.c_int32, C.c_size_t, C.POINTER(P)]
+    L.nlfem_server_submit.argtypes = [P, C.POINTER(nlfem_mesh), C.POINTER(nlfem_params), P, P,
+                                      C.POINTER(nlfem_solve_params), C.POINTER(C.c_uint64)]
+    L.nlfem_server_poll.argtypes = [P, C.c_uint64, C.POINTER(nlfem_request_info)]
+    L.nlfem_server_wait.argtypes = [P, C.c_uint64, C.c_double, C.POINTER(nlfem_request_info)]
+    L.nlfem_server_take.argtypes = [P, C.c_uint64, P, P]
+    L.nlfem_server_stats.argtypes = [P, C.POINTER(nlfem_server_counters)]
+    L.nlfem_server_last_error.argtypes = [P]
+    L.nlfem_server_last_error.restype = C.c_char_p
+    L.nlfem_server_destroy.argtypes = [P]
     for name in EXPORTS:
-        if name != "nlfem_rule_constants" and name != "nlfem_last_error":
+        if name not in ("nlfem_rule_constants", "nlfem_last_error", "nlfem_server_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -410,6 +445,80 @@ class Batch:
             pass
 
 
+class Server:
+    """Request loop (include/nlfem.h, serving): submit problems, wait for
+    their solutions; the library runs each request on one of its slots."""
+
+    def __init__(self, device: int = 0, n_slots: int = 4, pool_bytes: int = 0):
+        h = C.c_void_p()
+        st = load().nlfem_server_create(device, n_slots, pool_bytes, C.byref(h))
+        if st != NLFEM_OK:
+            raise NlfemError(st, "nlfem_server_create failed")
+        self.handle = h
+        _OPEN_SERVERS.add(self)
+
+    def _err(self, st):
+        if st != NLFEM_OK:
+            raise NlfemError(st, load().nlfem_server_last_error(self.handle).decode())
+
+    def submit(self, pb, rtol: float = 1e-10, max_iter: int = 0, outer_mask=None) -> int:
+        mesh = pb.mesh
+        coords = np.ascontiguousarray(mesh.coords, dtype=np.float64)
+        tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+        vfree = np.ascontiguousarray(pb.vertex_free, dtype=np.uint8)
+        f = None if pb.f_qp is None else np.ascontiguousarray(pb.f_qp, dtype=np.float64)
+        g = None if pb.g_nodal is None else np.ascontiguousarray(pb.g_nodal, dtype=np.float64)
+        om = None if outer_mask is None else np.ascontiguousarray(outer_mask, dtype=np.uint8)
+        m = nlfem_mesh(mesh.n_vertices, mesh.n_tets, coords.ctypes.data, tets.ctypes.data, vfree.ctypes.data,
+                       None, 0)
+        prm = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
+                           NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
+                           None if om is None else om.ctypes.data)
+        sp = nlfem_solve_params(rtol, max_iter)
+        t = C.c_uint64()
+        self._err(load().nlfem_server_submit(self.handle, C.byref(m), C.byref(prm),
+                                             None if f is None else f.ctypes.data,
+                                             None if g is None else g.ctypes.data, C.byref(sp), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        info = nlfem_request_info()
+        self._err(load().nlfem_server_poll(self.handle, ticket, C.byref(info)))
+        return info.as_dict()
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> dict:
+        info = nlfem_request_info()
+        self._err(load().nlfem_server_wait(self.handle, ticket, timeout, C.byref(info)))
+        return info.as_dict()
+
+    def take(self, ticket: int):
+        """Solution x [n_free] and free_to_vertex [n_free] of a finished request."""
+        info = self.poll(ticket)
+        nf = int(info["n_free"])
+        x = np.empty(nf, dtype=np.float64)
+        f2v = np.empty(nf, dtype=np.int32)
+        self._err(load().nlfem_server_take(self.handle, ticket, x.ctypes.data, f2v.ctypes.data))
+        return x, f2v, info
+
+    def stats(self) -> dict:
+        c = nlfem_server_counters()
+        self._err(load().nlfem_server_stats(self.handle, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in c._fields_}
+
+    def close(self):
+        if self.handle is not None:
+            load().nlfem_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_OPEN_SERVERS = weakref.WeakSet()
+
 _hip = None
 
 
@@ -427,6 +536,11 @@ def _hip_d2h(arr, dev_ptr):
 
 @atexit.register
 def _close_all():
+    for sv in list(_OPEN_SERVERS):
+        try:
+            sv.close()
+        except Exception:
+            pass
     for d in list(_OPEN_DEVICES):
         try:
             d.close()

@@ -19,7 +19,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["k_sort.hip", "k_plan.hip", "k_numeric.hip", "k_rows.hip", "k_cg.hip", "capi.hip"]
+SOURCES = ["k_sort.hip", "k_plan.hip", "k_numeric.hip", "k_rows.hip", "k_cg.hip", "runtime.hip", "capi.hip", "server.hip"]
 EXTRA = os.environ.get("NLFEM_EXTRA_FLAGS", "").split()
 
 

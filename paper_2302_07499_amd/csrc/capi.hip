@@ -1,7 +1,8 @@
-// Host runtime behind the C ABI of include/nlfem.h: contexts with a caching
-// device allocator and an HBM budget, the symbolic plan (mesh layout, cell
-// list, classification, local vertex sets, vertex-keyed sorted lists, CSR
-// pattern), the numeric assembly and the CG solver loop.
+// Host runtime behind the C ABI of include/nlfem.h: contexts, the symbolic
+// plan (mesh layout, cell list, classification, local vertex sets,
+// vertex-keyed sorted lists, CSR pattern), the numeric assembly, batches and
+// the CG solver loop.  Device memory management is in runtime.hip, the
+// request server in server.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,87 +14,12 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/nlfem.h"
 #include "common.hpp"
+#include "runtime.hpp"
 
 using namespace nlfem;
 
-struct nlfem_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    size_t budget = 0;  // 0 = unlimited
-    size_t live = 0, cached = 0;
-    std::multimap<size_t, void*> cache;
-    std::unordered_map<void*, size_t> sizes;
-    std::string err;
-    size_t lds_max = 65536;
-    double* pinned = nullptr;  // host scratch for readbacks
-    int64_t* pinned_i = nullptr;
-};
-
 namespace {
-
-struct Status {
-    nlfem_status code = NLFEM_OK;
-};
-
-nlfem_status fail(nlfem_ctx* c, nlfem_status s, const std::string& msg) {
-    if (c) c->err = msg;
-    return s;
-}
-
-size_t round_up(size_t b) { return (b + 255) & ~(size_t)255; }
-
-void release_cache(nlfem_ctx* c) {
-    for (auto& kv : c->cache) hipFree(kv.second);
-    c->cache.clear();
-    c->cached = 0;
-}
-
-// returns nullptr on failure (c->err set)
-void* dalloc(nlfem_ctx* c, size_t bytes) {
-    bytes = round_up(bytes ? bytes : 1);
-    auto it = c->cache.lower_bound(bytes);
-    if (it != c->cache.end() && it->first <= 2 * bytes) {
-        void* p = it->second;
-        size_t sz = it->first;
-        c->cache.erase(it);
-        c->cached -= sz;
-        c->live += sz;
-        c->sizes[p] = sz;
-        return p;
-    }
-    if (c->budget && c->live + c->cached + bytes > c->budget) release_cache(c);
-    if (c->budget && c->live + bytes > c->budget) {
-        c->err = "HBM budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
-                 std::to_string(c->live) + " in use, budget " + std::to_string(c->budget);
-        return nullptr;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        hipGetLastError();
-        release_cache(c);
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            hipGetLastError();
-            c->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
-            return nullptr;
-        }
-    }
-    c->live += bytes;
-    c->sizes[p] = bytes;
-    return p;
-}
-
-void dfree(nlfem_ctx* c, void* p) {
-    if (!p) return;
-    auto it = c->sizes.find(p);
-    if (it == c->sizes.end()) return;
-    size_t sz = it->second;
-    c->sizes.erase(it);
-    c->live -= sz;
-    c->cache.emplace(sz, p);
-    c->cached += sz;
-}
 
 int bits_for(uint64_t x) {  // number of bits needed to represent values in [0, x]
     int b = 0;
@@ -209,6 +135,7 @@ struct Timer {
 int64_t read_i64(nlfem_ctx* c, const int64_t* dev) {
     hipMemcpyAsync(c->pinned_i, dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
+    drain_pending(c);
     return c->pinned_i[0];
 }
 
@@ -736,8 +663,13 @@ nlfem_status nlfem_create(nlfem_ctx** out, int device, void* hip_stream, size_t 
 nlfem_status nlfem_destroy(nlfem_ctx* c) {
     if (!c) return NLFEM_E_INVALID_ARG;
     hipStreamSynchronize(c->stream);
-    release_cache(c);
-    for (auto& kv : c->sizes) hipFree(kv.first);
+    if (c->pool) {
+        drain_pending(c);
+        for (auto& kv : c->sizes) c->pool->release(kv.first, kv.second);
+    } else {
+        release_cache(c);
+        for (auto& kv : c->sizes) hipFree(kv.first);
+    }
     c->sizes.clear();
     hipHostFree(c->pinned);
     hipHostFree(c->pinned_i);
@@ -756,6 +688,7 @@ nlfem_status nlfem_memory_in_use(const nlfem_ctx* c, size_t* bytes) {
 nlfem_status nlfem_trim(nlfem_ctx* c) {
     if (!c) return NLFEM_E_INVALID_ARG;
     hipStreamSynchronize(c->stream);
+    drain_pending(c);
     release_cache(c);
     return NLFEM_OK;
 }

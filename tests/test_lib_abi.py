@@ -46,3 +46,17 @@ def test_null_and_no_device_errors():
     if not torch.cuda.is_available():
         ctx = C.c_void_p()
         assert L.nlfem_create(C.byref(ctx), 0, None, 0) == P.NLFEM_E_DEVICE
+
+
+def test_server_null_and_no_device_errors():
+    import torch
+    import paper_2302_07499_amd as P
+    L = P.load()
+    assert L.nlfem_server_create(0, 4, 0, None) == P.NLFEM_E_INVALID_ARG
+    h = C.c_void_p()
+    assert L.nlfem_server_create(0, 0, 0, C.byref(h)) == P.NLFEM_E_INVALID_ARG
+    assert L.nlfem_server_submit(None, None, None, None, None, None, None) == P.NLFEM_E_INVALID_ARG
+    assert L.nlfem_server_poll(None, 1, None) == P.NLFEM_E_INVALID_ARG
+    assert L.nlfem_server_destroy(None) == P.NLFEM_E_INVALID_ARG
+    if not torch.cuda.is_available():
+        assert L.nlfem_server_create(0, 2, 1 << 20, C.byref(h)) == P.NLFEM_E_DEVICE

@@ -1,15 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark: assembled (point, element) pairs per second of the fullcaps
-assembly on one MI355X, FP64 and FP32-local.
+assembly on one MI355X, FP64 and FP32-local, with the batched and served
+forms beside it.
 
-Workload: 32^3 Kuhn-split cubes of [0,1]^3 (196,608 tets, 35,937 vertices),
-interior vertices jittered uniformly by +-0.2h (seed 1), delta = 3h,
-psi = 15/(4 pi delta^5), N = 64 Monte Carlo samples per cut pair, f = -2,
-g = x1^2.  One step is one pass of the whole assembly path on the device:
-mesh layout, cell list, exact classification, local vertex sets and the
-sorted-key reduction plan (plan_create), then pair integration, reductions
-and the right-hand side (assemble).  Inputs are resident in HBM when the
-timed region starts; the CG solve is timed separately.
+Main workload (the JSON line's value): 32^3 Kuhn-split cubes of [0,1]^3
+(196,608 tets, 35,937 vertices), interior vertices jittered uniformly by
++-0.2h (seed 1), delta = 3h, psi = 15/(4 pi delta^5), N = 64 Monte Carlo
+samples per cut pair, f = -2, g = x1^2.  One step is one pass of the whole
+assembly path on the device: mesh layout, cell list, exact classification,
+local vertex sets, row lists and CSR pattern (plan_create), then pair
+integration, inner-element terms, row assembly and the right-hand side
+(assemble).  Inputs are resident in HBM when the timed region starts; the CG
+solve is timed separately.
+
+Batched: 256 meshes (n ~ U{8..24}, delta/h in {2,3,4}, jitter 0.15h, N = 32,
+FP32-local), one persistent fused integration launch per graph replay.
+
+Serving: requests (n ~ U{8..40}, delta/h ~ U[2,5], N in {32,64}, FP64 /
+FP32-local 50/50) through the request server: saturation throughput with all
+requests queued at once, then a Poisson stream at 0.9x that rate for the
+latency percentiles (arrival -> solution in host memory).
 
 Prints one JSON line.
 """
@@ -17,7 +27,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -39,30 +48,14 @@ def log(msg):
     sys.stderr.flush()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-fraction", type=float, default=0.0008)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is not part "
-              "of this build", file=sys.stderr)
-        sys.exit(2)
+def pct(a, q):
+    return round(float(np.percentile(np.asarray(a), q)), 3) if len(a) else None
 
+
+def run_precision(P, mg, dev, args):
     import torch
-    import meshgen as mg
-    import paper_2302_07499_amd as P
-
-    if not torch.cuda.is_available():
-        print("no GPU available", file=sys.stderr)
-        sys.exit(1)
-    log("building inputs")
     pb = mg.precision_problem()
     mesh = pb.mesh
-    dev = P.Device(0)
     t = torch
     d_coords = dev.to_dev(mesh.coords, t.float64)
     d_tets = dev.to_dev(mesh.tets, t.int32)
@@ -98,30 +91,162 @@ def main():
                 plan = P.Plan(dev, h)
             else:
                 P.nlfem_plan_destroy(h)
-            log(f"{precision} step {i} {1e3 * (t1 - t0):.1f} ms")
+            log(f"precision {precision} step {i} {1e3 * (t1 - t0):.1f} ms")
         return times, np.array(tk), info, plan, sysm
 
     times64, tk64, info, plan64, sys64 = run("fp64", args.steps, args.warmup)
     times32, tk32, info32, plan32, sys32 = run("fp32", args.steps, args.warmup)
-    pairs = int(sum(info["pair_counts"]))
-    cut = int(sum(info["pair_counts"][1:]))
-    inn = int(info["pair_counts"][0])
-    ms64 = 1e3 * float(np.mean(times64))
-    ms32 = 1e3 * float(np.mean(times32))
-
-    # FP32-local vs FP64 per-entry difference (relative to the row scale)
     a64 = P.system_to_numpy(sys64)
     a32 = P.system_to_numpy(sys32)
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import helpers as H
     e32 = H.value_errors(a32, a64)
-
-    # CG (timed separately)
     torch.cuda.synchronize()
     c0 = time.perf_counter()
     x, it, rr, ok = plan64.solve(sys64, rtol=1e-10)
     torch.cuda.synchronize()
     cg_ms = 1e3 * (time.perf_counter() - c0)
+    x32, it32, rr32, ok32 = plan32.solve(sys32, rtol=1e-10)
+    xa, xb = x.cpu().numpy(), x32.cpu().numpy()
+    sol_err = float(np.max(np.abs(xb - xa)) / max(np.max(np.abs(xa)), 1e-300))
+    plan64.destroy()
+    plan32.destroy()
+    del sys64, sys32, x, x32
+    return {"pb": pb, "times64": times64, "tk64": tk64, "times32": times32, "tk32": tk32, "info": info,
+            "e32": e32, "sol_err32": sol_err, "cg": {"iters": it, "rel_residual": rr, "converged": bool(ok),
+                                                     "ms": round(cg_ms, 2)}}
+
+
+def run_batched(P, mg, dev, args):
+    import torch
+    pbs = mg.batched_problems(args.batched_count)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = P.Batch(dev, pbs)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    pairs = int(sum(sum(i["pair_counts"]) for i in b.infos))
+    b.set_inputs([p.f_qp for p in pbs], [p.g_nodal for p in pbs])
+    t0 = time.perf_counter()
+    b.assemble()  # first call: autotune + graph capture + replay
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    ts = []
+    for r in range(args.batched_replays):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.assemble()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        log(f"batched replay {r} {1e3 * ts[-1]:.1f} ms")
+    tune = b.tuning()
+    mem = P.nlfem_memory_in_use(dev.ctx)
+    b.destroy()
+    P.nlfem_trim(dev.ctx)
+    ms = 1e3 * float(np.mean(ts))
+    return {"value": round(pairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_replay": round(ms, 2),
+            "meshes": len(pbs), "tets": int(sum(p.mesh.n_tets for p in pbs)), "pairs": pairs,
+            "dtype": "fp32-local/f64-accumulate", "plan_create_s": round(t_create, 2),
+            "first_call_s": round(t_first, 2), "tuned": tune, "device_bytes": int(mem)}
+
+
+def run_serving(P, mg, args, count, fractions):
+    t0 = time.perf_counter()
+    reqs = mg.serving_requests(count, rate_per_s=1.0, n_max=40)
+    log(f"serving: {count} requests generated in {time.perf_counter() - t0:.1f} s")
+    pbs = [r.problem for r in reqs]
+    unit_gaps = np.diff([r.arrival_s for r in reqs], prepend=0.0)  # exponential gaps at rate 1/s
+    sv = P.Server(0, n_slots=args.slots, pool_bytes=args.pool_gb << 30)
+    out = {"requests": count, "slots": args.slots, "pool_gb": args.pool_gb}
+
+    def collect(tickets):
+        infos = [sv.wait(tk, 600.0) for tk in tickets]
+        for tk in tickets:
+            sv.take(tk)
+        return infos
+
+    # saturation: everything queued at once
+    t0 = time.perf_counter()
+    tickets = [sv.submit(pb) for pb in pbs]
+    infos = collect(tickets)
+    makespan = time.perf_counter() - t0
+    pairs = sum(sum(i["pair_counts"]) for i in infos)
+    ok = [i for i in infos if i["state"] == 2]
+    sat_rate = len(ok) / makespan
+    out["saturation"] = {"requests_per_s": round(sat_rate, 3), "pairs_per_s": round(pairs / makespan, 1),
+                         "makespan_s": round(makespan, 2), "failed": len(infos) - len(ok)}
+    est = np.array([i["est_bytes"] for i in infos], dtype=float)
+    peak = np.array([max(i["peak_bytes"], 1) for i in infos], dtype=float)
+    out["footprint_est_over_peak"] = {"min": round(float(np.min(est / peak)), 2),
+                                      "p50": round(float(np.median(est / peak)), 2),
+                                      "max": round(float(np.max(est / peak)), 2)}
+    log(f"serving saturation {sat_rate:.2f} req/s, makespan {makespan:.1f} s")
+    for frac in fractions:
+        rate = frac * sat_rate
+        gaps = unit_gaps / rate
+        tickets = []
+        t0 = time.perf_counter()
+        due = t0
+        for pb, g in zip(pbs, gaps):
+            due += float(g)
+            dt = due - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(sv.submit(pb))
+        infos = collect(tickets)
+        wall = time.perf_counter() - t0
+        lat = [1e3 * i["latency_s"] for i in infos if i["state"] == 2]
+        pairs = sum(sum(i["pair_counts"]) for i in infos)
+        st = sv.stats()
+        out[f"poisson_{frac:g}x"] = {
+            "rate_per_s": round(rate, 3), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "mean_queue_ms": round(1e3 * float(np.mean([i["queue_s"] for i in infos])), 2),
+            "requests_per_s": round(len(lat) / wall, 3), "pairs_per_s": round(pairs / wall, 1),
+            "max_running": st["max_running"], "failed": len(infos) - len(lat)}
+        log(f"serving {frac}x: p50 {pct(lat, 50)} ms p99 {pct(lat, 99)} ms")
+    out["pool_peak_gb"] = round(sv.stats()["pool_peak"] / 2**30, 2)
+    sv.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fraction", type=float, default=0.0008)
+    ap.add_argument("--batched-count", type=int, default=256)
+    ap.add_argument("--batched-replays", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serving-count", type=int, default=48)
+    ap.add_argument("--serving-full", action="store_true", help="500 requests at 0.5x and 0.9x saturation")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--pool-gb", type=int, default=160)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is not part "
+              "of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import meshgen as mg
+    import paper_2302_07499_amd as P
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+    log("precision workload")
+    dev = P.Device(0)
+    pr = run_precision(P, mg, dev, args)
+    pb, info = pr["pb"], pr["info"]
+    pairs = int(sum(info["pair_counts"]))
+    cut = int(sum(info["pair_counts"][1:]))
+    inn = int(info["pair_counts"][0])
+    ms64 = 1e3 * float(np.mean(pr["times64"]))
+    ms32 = 1e3 * float(np.mean(pr["times32"]))
+    tk64, tk32 = pr["tk64"], pr["tk32"]
 
     # roofline of the dominant kernel (pair integration), from HIP events on the library's stream
     t_int = float(np.mean(tk64[:, 3])) * 1e-3
@@ -131,12 +256,25 @@ def main():
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
                 "kernel": "k_integrate<double>", "kernel_ms": round(t_int * 1e3, 3)}
 
+    batched = None
+    if not args.no_batched:
+        log("batched workload")
+        batched = run_batched(P, mg, dev, args)
+    P.nlfem_trim(dev.ctx)
+    dev.close()
+
+    serving = None
+    if not args.no_serving:
+        count = 500 if args.serving_full else args.serving_count
+        fractions = [0.5, 0.9] if args.serving_full else [0.9]
+        serving = run_serving(P, mg, args, count, fractions)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        mask = mg.outer_subset_mask(mesh.n_tets, args.cpu_fraction, seed=13)
-        region = np.array([pb.vertex_free[tt].any() for tt in mesh.tets])
+        mask = mg.outer_subset_mask(pb.mesh.n_tets, args.cpu_fraction, seed=13)
+        region = np.array([pb.vertex_free[tt].any() for tt in pb.mesh.tets])
         n_outer = int((mask.astype(bool) & region).sum())
         log(f"oracle on {n_outer} outer tets")
         c0 = time.perf_counter()
@@ -147,7 +285,8 @@ def main():
                "sample": f"precision workload, {n_outer} of {int(region.sum())} outer tets "
                          f"(seeded subset), {opairs} pairs in {dt:.1f} s, serial FP64 brute force"}
 
-    lat = np.array(times64) * 1e3
+    lat = np.array(pr["times64"]) * 1e3
+    e32 = pr["e32"]
     out = {
         "metric": "assembled element-pairs/s (FP32-local vs FP64) at stated err; p50/p99 latency",
         "value": round(pairs / (ms64 * 1e-3), 1),
@@ -166,24 +305,24 @@ def main():
                    "pairs_per_step": pairs, "cut_pairs": cut, "in_pairs": inn,
                    "mc_samples_per_step": cut * pb.mc_samples, "n_free": info["n_free"],
                    "nnz_ff": info["nnz_ff"], "nnz_fc": info["nnz_fc"]},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "fp32_local": {"value": round(pairs / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 3),
                        "max_entry_err_vs_fp64_rowscale": max(e32["ff_abs"], e32["fc_abs"]),
-                       "rhs_err_vs_fp64": e32["rhs"],
+                       "rhs_err_vs_fp64": e32["rhs"], "solution_err_vs_fp64": pr["sol_err32"],
                        "kernel_ms": round(float(np.mean(tk32[:, 3])), 3)},
-        "phases_ms_fp64": {"plan": round(float(np.mean(tk64[:, 0])), 3), "classify": round(float(np.mean(tk64[:, 1])), 3),
-                           "pattern_sort": round(float(np.mean(tk64[:, 2])), 3),
+        "phases_ms_fp64": {"plan": round(float(np.mean(tk64[:, 0])), 3),
+                           "classify": round(float(np.mean(tk64[:, 1])), 3),
+                           "pattern": round(float(np.mean(tk64[:, 2])), 3),
                            "integrate": round(float(np.mean(tk64[:, 3])), 3),
-                           "reduce": round(float(np.mean(tk64[:, 4])), 3),
+                           "rows": round(float(np.mean(tk64[:, 4])), 3),
                            "assemble": round(float(np.mean(tk64[:, 5])), 3)},
-        "cg": {"iters": it, "rel_residual": rr, "converged": bool(ok), "ms": round(cg_ms, 2)},
+        "cg": pr["cg"],
+        "batched": batched,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
-    plan64.destroy()
-    plan32.destroy()
-    dev.close()
 
 
 if __name__ == "__main__":

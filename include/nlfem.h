@@ -162,9 +162,10 @@ nlfem_status nlfem_debug_pairs(nlfem_plan *plan, int64_t q_begin, int64_t q_end,
  * all meshes is ONE persistent integration launch that pulls (mesh, outer
  * tet) work items, longest first, from a device queue, followed by the
  * per-mesh reductions, all captured once in a HIP graph and replayed.  The
- * workgroup size and persistent grid are picked by timing the candidates on
- * the first call (cached per shape class for the process).  Results are
- * bitwise those of nlfem_assemble on each mesh alone.                         */
+ * workgroup size and persistent grid are picked on the first call by timing
+ * each candidate on a strided sample of the work items (about 1.5e8 pairs;
+ * cached per shape class for the process).  Results are bitwise those of
+ * nlfem_assemble on each mesh alone.                                          */
 typedef struct nlfem_batch nlfem_batch;
 
 /* meshes[n], params[n] (HOST arrays of structs; the mesh arrays they point to
@@ -185,8 +186,9 @@ nlfem_status nlfem_batch_system(const nlfem_batch *batch, int32_t i, const int64
                                 const int64_t **fc_row_ptr, const int32_t **fc_col,
                                 const double **fc_val, const double **rhs,
                                 const int32_t **free_to_vertex);
-/* Chosen workgroup size and grid, the tuned integration time and the time of
- * the last graph replay (milliseconds, HIP events).                          */
+/* Chosen workgroup size and grid, the integration time of that shape on the
+ * tuning sample and the time of the last graph replay (milliseconds, HIP
+ * events).                                                                   */
 nlfem_status nlfem_batch_tuning(const nlfem_batch *batch, int32_t *block, int32_t *grid,
                                 double *tuned_integrate_ms, double *last_graph_ms);
 nlfem_status nlfem_batch_destroy(nlfem_batch *batch);

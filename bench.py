@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--pool-gb", type=int, default=160)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy kernel 3 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is not part "
@@ -237,6 +239,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB read + 256 MiB written")
+        del a, b
     log("precision workload")
     dev = P.Device(0)
     pr = run_precision(P, mg, dev, args)

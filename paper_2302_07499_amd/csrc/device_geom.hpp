@@ -173,11 +173,12 @@ __device__ __forceinline__ void lambda_u(const uint32_t* w, int h, uint32_t* L) 
 }
 
 // ---------------------------------------------------------------------------
-// Cut-pair geometry in the inner tet's barycentric space.
+// Cut-pair geometry in the inner tet's barycentric space.  Everything below
+// indexes its local arrays with compile-time constants only (runtime vertex
+// ids pick values by selects or address global memory), so it stays in
+// registers.
 struct CutGeom {
     int nin;
-    int I0, I1, I2;     // inside local vertices (ascending)
-    int O0, O1, O2;     // outside local vertices (ascending)
     int nplanes;
     double c0[4], c1[4];  // U_I = E n {c0.l >= 0} [n {c1.l >= 0}]
 };
@@ -194,236 +195,243 @@ __device__ __forceinline__ double det3_bary(const double* b0, const double* b1, 
     return ax * (by * cz - bz * cy) - ay * (bx * cz - bz * cx) + az * (bx * cy - by * cx);
 }
 
-// functional vanishing on Q1, Q2, Q3; oriented non-negative on the inside vertices
-__device__ inline void plane_through(const double* Q1, const double* Q2, const double* Q3, const CutGeom& g,
-                                     double* c) {
+// Hull point of U_I: the barycentric point (1 - t) e_a + t e_b, or the
+// vertex e_a when b < 0.
+struct HullPt {
+    int a, b;
+    double t;
+};
+
+__device__ __forceinline__ void hull_dense(const HullPt& h, double* e) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+        e[l] = (h.b < 0) ? ((l == h.a) ? 1.0 : 0.0) : ((l == h.a) ? 1.0 - h.t : ((l == h.b) ? h.t : 0.0));
+}
+
+// functional vanishing on Q1, Q2, Q3, oriented non-negative on the inside
+// vertices (bits of `inside`, summed in ascending vertex order)
+__device__ inline void plane_hull(const HullPt& h1, const HullPt& h2, const HullPt& h3, unsigned inside, double* c) {
+    double Q1[4], Q2[4], Q3[4];
+    hull_dense(h1, Q1);
+    hull_dense(h2, Q2);
+    hull_dense(h3, Q3);
     c[0] = det3m(Q1[1], Q1[2], Q1[3], Q2[1], Q2[2], Q2[3], Q3[1], Q3[2], Q3[3]);
     c[1] = -det3m(Q1[0], Q1[2], Q1[3], Q2[0], Q2[2], Q2[3], Q3[0], Q3[2], Q3[3]);
     c[2] = det3m(Q1[0], Q1[1], Q1[3], Q2[0], Q2[1], Q2[3], Q3[0], Q3[1], Q3[3]);
     c[3] = -det3m(Q1[0], Q1[1], Q1[2], Q2[0], Q2[1], Q2[2], Q3[0], Q3[1], Q3[2]);
     double s = 0.0;
-    s = s + c[g.I0];
-    if (g.nin > 1) s = s + c[g.I1];
-    if (g.nin > 2) s = s + c[g.I2];
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+        if ((inside >> l) & 1u) s = s + c[l];
     if (s < 0.0)
+#pragma unroll
         for (int l = 0; l < 4; ++l) c[l] = -c[l];
 }
 
-// sphere crossing on edge a (inside) -> b (outside)
-__device__ __forceinline__ double edge_t(const double* X, const double* p, double d2, const double* r2, int a, int b) {
-    double ea[3] = {X[3 * a] - p[0], X[3 * a + 1] - p[1], X[3 * a + 2] - p[2]};
-    double dv[3] = {X[3 * b] - X[3 * a], X[3 * b + 1] - X[3 * a + 1], X[3 * b + 2] - X[3 * a + 2]};
+// sphere crossing on edge a (inside) -> b (outside); Xg = the inner tet's
+// vertex coordinates ([4][3], global memory), r2a = |X_a - p|^2
+__device__ __forceinline__ double edge_t(const double* Xg, const double* p, double d2, double r2a, int a, int b) {
+    double ea[3] = {Xg[3 * a] - p[0], Xg[3 * a + 1] - p[1], Xg[3 * a + 2] - p[2]};
+    double dv[3] = {Xg[3 * b] - Xg[3 * a], Xg[3 * b + 1] - Xg[3 * a + 1], Xg[3 * b + 2] - Xg[3 * a + 2]};
     double A = dot3(dv, dv);
     double B = dot3(ea, dv);
-    double C = r2[a] - d2;
+    double C = r2a - d2;
     double s = sqrt(B * B - A * C);
     double t = (B <= 0.0) ? (s - B) / A : (-C) / (B + s);
     return t > 1.0 ? 1.0 : t;
 }
 
-// Hull points of U_I: (a, b, t) stands for the barycentric point
-// (1 - t) e_a + t e_b, or the vertex e_a when b < 0.
-struct HullPts {
-    int a[6], b[6];
-    double t[6];
-};
-
-__device__ __forceinline__ void hull_dense(const HullPts& H, int i, double* e) {
-    const int a = H.a[i], b = H.b[i];
-    const double t = H.t[i];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) e[l] = (b < 0) ? ((l == a) ? 1.0 : 0.0) : ((l == a) ? 1.0 - t : ((l == b) ? t : 0.0));
-}
-
-// Accumulator type for the deterministic subtet rule: T = double or float.
-template <typename T>
-struct Mom {
-    T s[15];
-};
-
-// subtet index patterns into the hull point list
-//   n_in = 1: {0,1,2,3};  n_in = 3 and n_in = 2 (first diagonal): {0,1,2,5},{0,1,4,5},{0,3,4,5};
-//   n_in = 2 (second diagonal): {0,1,2,4},{0,2,4,5},{0,3,4,5}
-__device__ __forceinline__ int subtet_vertex(int pattern, int s, int r) {
-    // pattern 0: single tet; 1: first prism split; 2: second prism split
-    const unsigned P1 = 0x543u << 0;  // unused helper (kept simple below)
-    (void)P1;
-    if (pattern == 0) return r;
-    if (r == 0) return 0;
-    if (pattern == 1) {
-        if (s == 0) return (r == 1) ? 1 : (r == 2 ? 2 : 5);
-        if (s == 1) return (r == 1) ? 1 : (r == 2 ? 4 : 5);
-        return (r == 1) ? 3 : (r == 2 ? 4 : 5);
-    }
-    if (s == 0) return (r == 1) ? 1 : (r == 2 ? 2 : 4);
-    if (s == 1) return (r == 1) ? 2 : (r == 2 ? 4 : 5);
-    return (r == 1) ? 3 : (r == 2 ? 4 : 5);
-}
-
-__device__ __forceinline__ double subtet_absdet(const HullPts& H, int pattern, int s) {
+__device__ __forceinline__ double subtet_absdet(const HullPt& h0, const HullPt& h1, const HullPt& h2,
+                                                const HullPt& h3) {
     double v0[4], v1[4], v2[4], v3[4];
-    hull_dense(H, subtet_vertex(pattern, s, 0), v0);
-    hull_dense(H, subtet_vertex(pattern, s, 1), v1);
-    hull_dense(H, subtet_vertex(pattern, s, 2), v2);
-    hull_dense(H, subtet_vertex(pattern, s, 3), v3);
+    hull_dense(h0, v0);
+    hull_dense(h1, v1);
+    hull_dense(h2, v2);
+    hull_dense(h3, v3);
     return fabs(det3_bary(v0, v1, v2, v3));
 }
 
-// 4-point rule on subtet s of the pattern, weight vol*|det|/4 per node
+// Moments of the subtet (h0, h1, h2, h3) of volume V:
+//   S0 = V, S1 = V/4 sum_a v_a, S2 = V/20 (sum_a v_a v_a^T + s s^T), s = sum_a v_a,
+// with v_a the vertices' barycentric rows.  These are the integrals of the
+// affine barycentric coordinates over the subtet; the 4-point rule of
+// Sec. 4.2.1 is exact for them (degree <= 2), so it gives the same values.
+// Evaluated in T; S0, S1 are added to D[0..4], S2 (upper triangle) to G.
 template <typename T>
-__device__ __forceinline__ void subtet_rule(const HullPts& H, int pattern, int s, double vol, Mom<T>& M) {
+__device__ __forceinline__ void subtet_moments(const HullPt& h0, const HullPt& h1, const HullPt& h2, const HullPt& h3,
+                                               double V, double* D, double* G) {
     double v0[4], v1[4], v2[4], v3[4];
-    hull_dense(H, subtet_vertex(pattern, s, 0), v0);
-    hull_dense(H, subtet_vertex(pattern, s, 1), v1);
-    hull_dense(H, subtet_vertex(pattern, s, 2), v2);
-    hull_dense(H, subtet_vertex(pattern, s, 3), v3);
-    double det = fabs(det3_bary(v0, v1, v2, v3));
-    T w = (T)((vol * det) * 0.25);
+    hull_dense(h0, v0);
+    hull_dense(h1, v1);
+    hull_dense(h2, v2);
+    hull_dense(h3, v3);
+    T sv[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) sv[l] = (T)(((v0[l] + v1[l]) + v2[l]) + v3[l]);
+    const T w4 = (T)(V * 0.25), w20 = (T)(V * 0.05);
+    D[0] += V;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) D[1 + j] += (double)(w4 * sv[j]);
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i; j < 4; ++j) {
+            const T q = (((T)v0[i] * (T)v0[j] + (T)v1[i] * (T)v1[j]) + (T)v2[i] * (T)v2[j]) + (T)v3[i] * (T)v3[j];
+            G[k++] += (double)(w20 * (q + sv[i] * sv[j]));
+        }
+}
+
+// position of the n-th set bit of m (n = 0: lowest), -1 if there is none
+__device__ __forceinline__ int nth_bit(unsigned m, int n) {
+    for (int i = 0; i < n; ++i) m &= m - 1u;
+    return __ffs(m) - 1;
+}
+
+// Build U_I = conv(I u P) (fullcaps construction), add the moments of its
+// subdivision T_I to M, and set the half-space form of U_I used by the
+// sample test.  With I and O the inside / outside vertices in ascending
+// order and P_xy the sphere crossing on edge x -> y, the hull points are
+//   n_in = 1: h0 = I0, h1 = P_I0O0, h2 = P_I0O1, h5 = P_I0O2 (h3 = h4 = I0);
+//             T_I = the corner tet {0,1,2,5}; plane through (1,2,5)
+//   n_in = 3: h0..h2 = I0..I2, h3 = P_I0O0, h4 = P_I1O0, h5 = P_I2O0;
+//             T_I = {0,1,2,5}, {0,1,4,5}, {0,3,4,5}; plane through (3,4,5)
+//   n_in = 2: h0 = I0, h1 = P_I0O0, h2 = P_I0O1, h3 = I1, h4 = P_I1O0, h5 = P_I1O1;
+//             the quad (1,2,4,5) is split along the diagonal that gives the
+//             larger (convex) volume, ties to the first:
+//             T_I = {0,1,2,5}, {0,1,4,5}, {0,3,4,5}, planes (1,2,5), (1,4,5), or
+//             T_I = {0,1,2,4}, {0,2,4,5}, {0,3,4,5}, planes (1,2,4), (2,4,5).
+// Every lane runs the same instruction stream: the three subtets are always
+// evaluated (zero-volume ones for n_in = 1 and n_in = 0), the hull points and
+// planes are picked by selects.
+template <typename T>
+__device__ inline void cut_setup(const double* Xg, const double* p, double d2, const double* r2, double vol,
+                                 CutGeom& g, double* D, double* G) {
+    unsigned in = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+        if (r2[l] < d2) in |= 1u << l;
+    const unsigned out = (~in) & 15u;
+    const int ni = __popc(in);
+    const int I0 = nth_bit(in, 0), I1 = nth_bit(in, 1), I2 = nth_bit(in, 2);
+    const int O0 = nth_bit(out, 0), O1 = nth_bit(out, 1), O2 = nth_bit(out, 2);
+    auto r2of = [&](int a) { return a == 0 ? r2[0] : (a == 1 ? r2[1] : (a == 2 ? r2[2] : r2[3])); };
+    // sphere crossings; an edge a lane does not use is replaced by (0, 1) and
+    // its result is never selected
+    auto cross = [&](bool used, int a, int b) {
+        const int aa = used ? a : 0, bb = used ? b : 1;
+        return HullPt{aa, bb, edge_t(Xg, p, d2, r2of(aa), aa, bb)};
+    };
+    const bool c1 = ni == 1, c2 = ni == 2, c3 = ni == 3, any = ni > 0;
+    const HullPt x1 = cross(any, I0, O0);                          // P_I0O0
+    const HullPt x2 = cross(any, c3 ? I1 : I0, c3 ? O0 : O1);      // P_I0O1 | P_I1O0 (n_in = 3)
+    const HullPt x3 = cross(any, c1 ? I0 : (c2 ? I1 : I2), c1 ? O2 : (c2 ? O1 : O0));  // h5
+    const HullPt x4 = cross(c2, I1, O0);                           // P_I1O0 (n_in = 2)
+    const int v0 = any ? I0 : 0;
+    const HullPt h0{v0, -1, 0.0};
+    // (n_in = 0 lanes take h0 everywhere: their dummy crossings may be NaN)
+    const HullPt h1 = c3 ? HullPt{I1, -1, 0.0} : (any ? x1 : h0);
+    const HullPt h2 = c3 ? HullPt{I2, -1, 0.0} : (any ? x2 : h0);
+    const HullPt h3 = c3 ? x1 : HullPt{c2 ? I1 : v0, -1, 0.0};
+    const HullPt h4 = c3 ? x2 : (c2 ? x4 : h0);
+    const HullPt h5 = any ? x3 : h0;
+    // |det| of the five candidate subtets (rolled: one subtet's vertices live at a time)
+    //   t: 0 (0,1,2,5)  1 (0,1,4,5)  2 (0,3,4,5)  3 (0,1,2,4)  4 (0,2,4,5)
+    double d125 = 0.0, d145 = 0.0, d345 = 0.0, d124 = 0.0, d245 = 0.0;
 #pragma unroll 1
+    for (int t = 0; t < 5; ++t) {
+        const HullPt A = (t == 2) ? h3 : ((t == 4) ? h2 : h1);
+        const HullPt B = (t == 0 || t == 3) ? h2 : h4;
+        const HullPt C = (t == 3) ? h4 : h5;
+        const double d = subtet_absdet(h0, A, B, C);
+        d125 = (t == 0) ? d : d125;
+        d145 = (t == 1) ? d : d145;
+        d345 = (t == 2) ? d : d345;
+        d124 = (t == 3) ? d : d124;
+        d245 = (t == 4) ? d : d245;
+    }
+    const double v1 = (d125 + d145) + d345, v2 = (d124 + d245) + d345;
+    const bool alt = c2 && !(v1 >= v2);  // second diagonal
+    // subtets of T_I (rolled):
+    //   0: (h0, h1, h2, alt ? h4 : h5)   1: (h0, alt ? h2 : h1, h4, h5)   2: (h0, h3, h4, h5)
+#pragma unroll 1
+    for (int t = 0; t < 3; ++t) {
+        const HullPt A = (t == 0) ? h1 : ((t == 1) ? (alt ? h2 : h1) : h3);
+        const HullPt B = (t == 0) ? h2 : h4;
+        const HullPt C = (t == 0 && alt) ? h4 : h5;
+        const double dv = (t == 0) ? (alt ? d124 : d125) : ((t == 1) ? (alt ? d245 : d145) : d345);
+        subtet_moments<T>(h0, A, B, C, vol * dv, D, G);
+    }
+    g.nin = ni;
+    g.nplanes = any ? (c2 ? 2 : 1) : 0;
+    plane_hull(c3 ? h3 : h1, c3 ? h4 : h2, alt ? h4 : h5, in, g.c0);
+    plane_hull(alt ? h2 : h1, h4, h5, in, g.c1);
+    // sample test: a missing plane is replaced by one that holds everywhere
+    // (c = (1,1,1,1): c.lambda = 1 >= 0), and for n_in = 0 by one that never holds.
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        if (!c2) g.c1[l] = 1.0;
+        if (!any) g.c0[l] = -1.0;
+    }
+}
+
+// Moments S = S0, S1[4], S2 upper triangle (00,01,02,03,11,12,13,22,23,33)
+// of one pair, in three pieces that the integration kernel folds into its
+// sums one at a time (so that only one piece's state is live at once):
+//   in_moments   the 4-point rule on the whole inner tet (class IN);
+//   cut_det      the fullcaps construction of U_I and the 4-point rule on its
+//                subtets (deterministic part of a cut pair); fills g;
+//   cut_mc       the Monte Carlo part over E_m minus U_I inside the ball.
+// T = accumulation type of the local integrals.  Sample acceptance is always
+// decided in double.
+__device__ inline void in_moments(double vol, double* S) {
+    double w = vol * 0.25;
+    for (int i = 0; i < 15; ++i) S[i] = 0.0;
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
-        T xi[4];
+        S[0] += w;
 #pragma unroll
-        for (int l = 0; l < 4; ++l)
-            xi[l] = (T)(((rule_w(r, 0) * v0[l] + rule_w(r, 1) * v1[l]) + rule_w(r, 2) * v2[l]) + rule_w(r, 3) * v3[l]);
-        M.s[0] += w;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) M.s[1 + j] += w * xi[j];
+        for (int j = 0; j < 4; ++j) S[1 + j] += w * rule_w(r, j);
         int k = 5;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = i; j < 4; ++j) M.s[k++] += (w * xi[i]) * xi[j];
+            for (int j = i; j < 4; ++j) S[k++] += (w * rule_w(r, i)) * rule_w(r, j);
     }
 }
 
-__device__ __forceinline__ void plane_hull(const HullPts& H, int i1, int i2, int i3, const CutGeom& g, double* c) {
-    double Q1[4], Q2[4], Q3[4];
-    hull_dense(H, i1, Q1);
-    hull_dense(H, i2, Q2);
-    hull_dense(H, i3, Q3);
-    plane_through(Q1, Q2, Q3, g, c);
-}
-
-// Build U_I = conv(I u P) (fullcaps construction) as hull points, add the
-// 4-point rule on its subdivision T_I to M, and set the half-space form of
-// U_I used by the sample test.
-//   n_in = 1: corner tet (a; P_ab, P_ac, P_ad), plane (P_ab, P_ac, P_ad)
-//   n_in = 3: prism (a, b, c | P_ad, P_bd, P_cd), plane (P_ad, P_bd, P_cd)
-//   n_in = 2: prism (a, P_ac, P_ad | b, P_bc, P_bd); its interior quad
-//             (P_ac, P_ad, P_bd, P_bc) is split along the diagonal giving the
-//             larger (convex) volume, ties to P_ac-P_bd.
 template <typename T>
-__device__ inline void cut_setup(const double* X, const double* p, double d2, const double* r2, double vol,
-                                 CutGeom& g, Mom<T>& M) {
-    int I[4], O[4], ni = 0, no = 0;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-        if (r2[l] < d2) I[ni++] = l;
-        else O[no++] = l;
-    }
-    g.nin = ni;
-    g.I0 = I[0]; g.I1 = I[1]; g.I2 = I[2];
-    g.O0 = O[0]; g.O1 = O[1]; g.O2 = O[2];
-    g.nplanes = 0;
-    HullPts H;
-    int pattern = -1, nsub = 0;
-    if (ni == 1) {
-        H.a[0] = I[0]; H.b[0] = -1; H.t[0] = 0.0;
-        for (int j = 0; j < 3; ++j) {
-            H.a[1 + j] = I[0];
-            H.b[1 + j] = O[j];
-            H.t[1 + j] = edge_t(X, p, d2, r2, I[0], O[j]);
-        }
-        pattern = 0;
-        nsub = 1;
-        plane_hull(H, 1, 2, 3, g, g.c0);
-        g.nplanes = 1;
-    } else if (ni == 3) {
-        for (int j = 0; j < 3; ++j) {
-            H.a[j] = I[j]; H.b[j] = -1; H.t[j] = 0.0;
-            H.a[3 + j] = I[j]; H.b[3 + j] = O[0];
-            H.t[3 + j] = edge_t(X, p, d2, r2, I[j], O[0]);
-        }
-        pattern = 1;
-        nsub = 3;
-        plane_hull(H, 3, 4, 5, g, g.c0);
-        g.nplanes = 1;
-    } else if (ni == 2) {
-        H.a[0] = I[0]; H.b[0] = -1; H.t[0] = 0.0;
-        H.a[1] = I[0]; H.b[1] = O[0]; H.t[1] = edge_t(X, p, d2, r2, I[0], O[0]);
-        H.a[2] = I[0]; H.b[2] = O[1]; H.t[2] = edge_t(X, p, d2, r2, I[0], O[1]);
-        H.a[3] = I[1]; H.b[3] = -1; H.t[3] = 0.0;
-        H.a[4] = I[1]; H.b[4] = O[0]; H.t[4] = edge_t(X, p, d2, r2, I[1], O[0]);
-        H.a[5] = I[1]; H.b[5] = O[1]; H.t[5] = edge_t(X, p, d2, r2, I[1], O[1]);
-        double v1 = subtet_absdet(H, 1, 0) + subtet_absdet(H, 1, 1) + subtet_absdet(H, 1, 2);
-        double v2 = subtet_absdet(H, 2, 0) + subtet_absdet(H, 2, 1) + subtet_absdet(H, 2, 2);
-        nsub = 3;
-        if (v1 >= v2) {
-            pattern = 1;
-            plane_hull(H, 1, 2, 5, g, g.c0);
-            plane_hull(H, 1, 4, 5, g, g.c1);
-        } else {
-            pattern = 2;
-            plane_hull(H, 1, 2, 4, g, g.c0);
-            plane_hull(H, 2, 4, 5, g, g.c1);
-        }
-        g.nplanes = 2;
-    }
-#pragma unroll 1
-    for (int s = 0; s < nsub; ++s) subtet_rule<T>(H, pattern, s, vol, M);
-    // sample test: a missing plane is replaced by one that holds everywhere
-    // (c = (1,1,1,1): c.lambda = 1 >= 0), and for n_in = 0 by one that never holds.
-    if (g.nplanes < 2) {
-        for (int l = 0; l < 4; ++l) g.c1[l] = 1.0;
-    }
-    if (g.nplanes == 0) {
-        for (int l = 0; l < 4; ++l) g.c0[l] = -1.0;
-    }
-}
-
-// Moments of one pair (IN or CUT), T = accumulation type of the local
-// integrals.  Sample acceptance is always decided in double.
-// S = S0, S1[4], S2 upper triangle (00,01,02,03,11,12,13,22,23,33).
-template <typename T>
-__device__ inline void pair_moments(const double* X, double vol, const double* p, double d2, int code, int N,
-                                    uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
-    if (code == C_IN) {
-        double w = vol * 0.25;
-        double s[15];
-        for (int i = 0; i < 15; ++i) s[i] = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            s[0] += w;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) s[1 + j] += w * rule_w(r, j);
-            int k = 5;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = i; j < 4; ++j) s[k++] += (w * rule_w(r, i)) * rule_w(r, j);
-        }
-        for (int i = 0; i < 15; ++i) S[i] = s[i];
-        return;
-    }
+__device__ inline void cut_det(const double* X, double vol, const double* p, double d2, CutGeom& g, double* D,
+                               double* G) {
+    // X: the inner tet's vertex coordinates [4][3] in global memory; S0, S1
+    // of the subdivision go to D[0..4] (overwritten), S2 is added to G[0..9]
     double r2[4];
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
         double dx = X[3 * l] - p[0], dy = X[3 * l + 1] - p[1], dz = X[3 * l + 2] - p[2];
         r2[l] = (dx * dx + dy * dy) + dz * dz;
     }
-    Mom<T> M;
 #pragma unroll
-    for (int i = 0; i < 15; ++i) M.s[i] = (T)0;
-    CutGeom g;
-    cut_setup<T>(X, p, d2, r2, vol, g, M);
+    for (int i = 0; i < 5; ++i) D[i] = 0.0;
+    cut_setup<T>(X, p, d2, r2, vol, g, D, G);
+}
+
+template <typename T>
+__device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
+                              uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
     // relative vertex coordinates e_l = X_l - p
     double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
     double e1x = X[3] - p[0], e1y = X[4] - p[1], e1z = X[5] - p[2];
     double e2x = X[6] - p[0], e2y = X[7] - p[1], e2z = X[8] - p[2];
     double e3x = X[9] - p[0], e3y = X[10] - p[1], e3z = X[11] - p[2];
-    // Monte Carlo sums: count, sum lambda_j (j = 1..3), sum lambda_i lambda_j (1 <= i <= j <= 3);
-    // the lambda_0 terms follow from sum_l lambda_l = 1.
-    T cnt = 0, a1 = 0, a2 = 0, a3 = 0, b11 = 0, b12 = 0, b13 = 0, b22 = 0, b23 = 0, b33 = 0;
+    // Monte Carlo sums over the accepted samples.  In double: count, sum
+    // lambda_j (j = 1..3), sum lambda_i lambda_j (1 <= i <= j <= 3); the
+    // lambda_0 terms follow from sum_l lambda_l = 1 exactly (the lambdas are
+    // 21-bit dyadics, so every sum is exact for N <= 2048).  In float that
+    // completion would cancel, so all 15 sums are accumulated directly.
+    constexpr bool kF32 = sizeof(T) == 4;
+    T cnt = 0, a0 = 0, a1 = 0, a2 = 0, a3 = 0, b00 = 0, b01 = 0, b02 = 0, b03 = 0, b11 = 0, b12 = 0, b13 = 0,
+      b22 = 0, b23 = 0, b33 = 0;
     const double sc = 1.0 / 2097152.0;
     for (int s = 0; s < N; s += 2) {
         uint32_t w[4];
@@ -447,22 +455,56 @@ __device__ inline void pair_moments(const double* X, double vol, const double* p
                 a1 += x1; a2 += x2; a3 += x3;
                 b11 = fma(x1, (T)l1, b11); b12 = fma(x1, (T)l2, b12); b13 = fma(x1, (T)l3, b13);
                 b22 = fma(x2, (T)l2, b22); b23 = fma(x2, (T)l3, b23); b33 = fma(x3, (T)l3, b33);
+                if (kF32) {
+                    T x0 = acc ? (T)l0 : (T)0;
+                    a0 += x0;
+                    b00 = fma(x0, (T)l0, b00); b01 = fma(x0, (T)l1, b01);
+                    b02 = fma(x0, (T)l2, b02); b03 = fma(x0, (T)l3, b03);
+                }
             }
         }
     }
-    // complete the sums with the lambda_0 terms (exact in double for N <= 2048)
     double dc = (double)cnt, d1 = (double)a1, d2s = (double)a2, d3 = (double)a3;
     double c11 = (double)b11, c12 = (double)b12, c13 = (double)b13, c22 = (double)b22, c23 = (double)b23,
            c33 = (double)b33;
-    double d0 = ((dc - d1) - d2s) - d3;
-    double c01 = ((d1 - c11) - c12) - c13;
-    double c02 = ((d2s - c12) - c22) - c23;
-    double c03 = ((d3 - c13) - c23) - c33;
-    double c00 = ((d0 - c01) - c02) - c03;
-    double mc[15] = {dc, d0, d1, d2s, d3, c00, c01, c02, c03, c11, c12, c13, c22, c23, c33};
-    double scale = vol / (double)N;
+    double d0, c00, c01, c02, c03;
+    if (kF32) {
+        d0 = (double)a0;
+        c00 = (double)b00;
+        c01 = (double)b01;
+        c02 = (double)b02;
+        c03 = (double)b03;
+    } else {
+        d0 = ((dc - d1) - d2s) - d3;
+        c01 = ((d1 - c11) - c12) - c13;
+        c02 = ((d2s - c12) - c22) - c23;
+        c03 = ((d3 - c13) - c23) - c33;
+        c00 = ((d0 - c01) - c02) - c03;
+    }
+    const double scale = vol / (double)N;
+    S[0] = scale * dc; S[1] = scale * d0; S[2] = scale * d1; S[3] = scale * d2s; S[4] = scale * d3;
+    S[5] = scale * c00; S[6] = scale * c01; S[7] = scale * c02; S[8] = scale * c03; S[9] = scale * c11;
+    S[10] = scale * c12; S[11] = scale * c13; S[12] = scale * c22; S[13] = scale * c23; S[14] = scale * c33;
+}
+
+// whole-pair moments (the sum of the pieces), as the oracle reports them
+template <typename T>
+__device__ inline void pair_moments(const double* X, double vol, const double* p, double d2, int code, int N,
+                                    uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
+    if (code == C_IN) {
+        in_moments(vol, S);
+        return;
+    }
+    CutGeom g;
+    double D[5], G[10];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) S[i] = (double)M.s[i] + scale * mc[i];
+    for (int i = 0; i < 10; ++i) G[i] = 0.0;
+    cut_det<T>(X, vol, p, d2, g, D, G);
+    cut_mc<T>(X, vol, p, d2, g, N, key0, key1, q, m, S);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
+#pragma unroll
+    for (int i = 0; i < 10; ++i) S[5 + i] = G[i] + S[5 + i];
 }
 
 }  // namespace nlfem

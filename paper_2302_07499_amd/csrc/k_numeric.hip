@@ -103,8 +103,6 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
     for (int64_t p = p0 + t; p < p1; p += BLOCK) {
         const int m = a.pair_m[p];
         const uint32_t code = a.pair_cls[p];
-        double X[12];
-        for (int i = 0; i < 12; ++i) X[i] = a.tetX[12 * (int64_t)m + i];
         const double volm = a.vol[m];
         const bool omega = a.region[m] != 0;
         const double fm = omega ? 1.0 : 2.0;
@@ -113,23 +111,33 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
         double g[10];
         for (int i = 0; i < 10; ++i) g[i] = 0.0;
         int n_in = 0, n_cut = 0;
+        // folds S0, S1 of outer point k's moments into T0 and R
+        auto fold = [&](int k, const double* S) {
+            fx_add(&T0[k], &T0l[k], fm * S[0], fx);
+            for (int j = 0; j < 4; ++j)
+                if (lv[j] < U)  // always true: Ve holds every vertex of the pair list's tets
+                    fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
+        };
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
             const int c = (int)((code >> (3 * k)) & 7u);
             if (c == C_OUT) continue;
             double S[15];
-            pair_moments<T>(X, volm, P[k], d2, c, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k), (uint32_t)m,
-                            S);
-            fx_add(&T0[k], &T0l[k], fm * S[0], fx);
-            for (int j = 0; j < 4; ++j)
-                if (lv[j] < U)  // always true: Ve holds every vertex of the pair list's tets
-                    fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
             if (c == C_IN) {
+                in_moments(volm, S);
+                fold(k, S);
                 ++n_in;
-            } else {
-                ++n_cut;
-                for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
+                continue;
             }
+            ++n_cut;
+            const double* X = a.tetX + 12 * (int64_t)m;
+            CutGeom cg;
+            double D[5];
+            cut_det<T>(X, volm, P[k], d2, cg, D, g);
+            cut_mc<T>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k), (uint32_t)m, S);
+            for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
+            fold(k, S);
+            for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
         }
         if (omega) {
             unsigned long long* ga = a.gacc + 22 * (int64_t)m;
@@ -208,8 +216,7 @@ __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_
     for (int64_t p = a.pair_off[oi] + threadIdx.x; p < a.pair_off[oi + 1]; p += 256) {
         const int m = a.pair_m[p];
         const uint32_t code = a.pair_cls[p];
-        double X[12];
-        for (int i = 0; i < 12; ++i) X[i] = a.tetX[12 * (int64_t)m + i];
+        const double* X = a.tetX + 12 * (int64_t)m;
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
             const int c = (int)((code >> (3 * k)) & 7u);

@@ -494,6 +494,7 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.cblk = pl->cblk;
     a.oblk = pl->oblk;
     a.gacc = pl->gacc;
+    a.gstride = pl->K;
     return a;
 }
 

@@ -104,7 +104,8 @@ struct IntegrateArgs {
     int umax;
     double* cblk;              // [sum |Ve|][4] cross blocks, at 4 * ve_off
     double* oblk;              // [n_outer][20]: 4x4 outer-outer block, then 4 load-vector terms
-    unsigned long long* gacc;  // [K][22] two-word sums: 10 cut S2 sums, then the inside weight
+    unsigned long long* gacc;  // [22][gstride] two-word sums: 10 cut S2 sums, then the inside weight
+    int64_t gstride;           // = K
 };
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 // persistent integration over work items (mesh index, outer position); block 128 or 256

@@ -208,13 +208,10 @@ __device__ __forceinline__ void hull_dense(const HullPt& h, double* e) {
         e[l] = (h.b < 0) ? ((l == h.a) ? 1.0 : 0.0) : ((l == h.a) ? 1.0 - h.t : ((l == h.b) ? h.t : 0.0));
 }
 
-// functional vanishing on Q1, Q2, Q3, oriented non-negative on the inside
-// vertices (bits of `inside`, summed in ascending vertex order)
-__device__ inline void plane_hull(const HullPt& h1, const HullPt& h2, const HullPt& h3, unsigned inside, double* c) {
-    double Q1[4], Q2[4], Q3[4];
-    hull_dense(h1, Q1);
-    hull_dense(h2, Q2);
-    hull_dense(h3, Q3);
+// functional vanishing on the barycentric points Q1, Q2, Q3, oriented
+// non-negative on the inside vertices (bits of `inside`, summed in ascending
+// vertex order)
+__device__ inline void plane_dense(const double* Q1, const double* Q2, const double* Q3, unsigned inside, double* c) {
     c[0] = det3m(Q1[1], Q1[2], Q1[3], Q2[1], Q2[2], Q2[3], Q3[1], Q3[2], Q3[3]);
     c[1] = -det3m(Q1[0], Q1[2], Q1[3], Q2[0], Q2[2], Q2[3], Q3[0], Q3[2], Q3[3]);
     c[2] = det3m(Q1[0], Q1[1], Q1[3], Q2[0], Q2[1], Q2[3], Q3[0], Q3[1], Q3[3]);
@@ -241,30 +238,15 @@ __device__ __forceinline__ double edge_t(const double* Xg, const double* p, doub
     return t > 1.0 ? 1.0 : t;
 }
 
-__device__ __forceinline__ double subtet_absdet(const HullPt& h0, const HullPt& h1, const HullPt& h2,
-                                                const HullPt& h3) {
-    double v0[4], v1[4], v2[4], v3[4];
-    hull_dense(h0, v0);
-    hull_dense(h1, v1);
-    hull_dense(h2, v2);
-    hull_dense(h3, v3);
-    return fabs(det3_bary(v0, v1, v2, v3));
-}
-
-// Moments of the subtet (h0, h1, h2, h3) of volume V:
-//   S0 = V, S1 = V/4 sum_a v_a, S2 = V/20 (sum_a v_a v_a^T + s s^T), s = sum_a v_a,
-// with v_a the vertices' barycentric rows.  These are the integrals of the
-// affine barycentric coordinates over the subtet; the 4-point rule of
-// Sec. 4.2.1 is exact for them (degree <= 2), so it gives the same values.
-// Evaluated in T; S0, S1 are added to D[0..4], S2 (upper triangle) to G.
+// Moments of the subtet with barycentric vertex rows v0..v3 and volume V:
+//   S0 = V, S1 = V/4 sum_a v_a, S2 = V/20 (sum_a v_a v_a^T + s s^T), s = sum_a v_a.
+// These are the integrals of the affine barycentric coordinates over the
+// subtet; the 4-point rule of Sec. 4.2.1 is exact for them (degree <= 2), so
+// it gives the same values.  Evaluated in T; S0, S1 are added to D[0..4],
+// S2 (upper triangle) to G.
 template <typename T>
-__device__ __forceinline__ void subtet_moments(const HullPt& h0, const HullPt& h1, const HullPt& h2, const HullPt& h3,
+__device__ __forceinline__ void subtet_moments(const double* v0, const double* v1, const double* v2, const double* v3,
                                                double V, double* D, double* G) {
-    double v0[4], v1[4], v2[4], v3[4];
-    hull_dense(h0, v0);
-    hull_dense(h1, v1);
-    hull_dense(h2, v2);
-    hull_dense(h3, v3);
     T sv[4];
 #pragma unroll
     for (int l = 0; l < 4; ++l) sv[l] = (T)(((v0[l] + v1[l]) + v2[l]) + v3[l]);
@@ -335,37 +317,41 @@ __device__ inline void cut_setup(const double* Xg, const double* p, double d2, c
     const HullPt h3 = c3 ? x1 : HullPt{c2 ? I1 : v0, -1, 0.0};
     const HullPt h4 = c3 ? x2 : (c2 ? x4 : h0);
     const HullPt h5 = any ? x3 : h0;
-    // |det| of the five candidate subtets (rolled: one subtet's vertices live at a time)
-    //   t: 0 (0,1,2,5)  1 (0,1,4,5)  2 (0,3,4,5)  3 (0,1,2,4)  4 (0,2,4,5)
-    double d125 = 0.0, d145 = 0.0, d345 = 0.0, d124 = 0.0, d245 = 0.0;
-#pragma unroll 1
-    for (int t = 0; t < 5; ++t) {
-        const HullPt A = (t == 2) ? h3 : ((t == 4) ? h2 : h1);
-        const HullPt B = (t == 0 || t == 3) ? h2 : h4;
-        const HullPt C = (t == 3) ? h4 : h5;
-        const double d = subtet_absdet(h0, A, B, C);
-        d125 = (t == 0) ? d : d125;
-        d145 = (t == 1) ? d : d145;
-        d345 = (t == 2) ? d : d345;
-        d124 = (t == 3) ? d : d124;
-        d245 = (t == 4) ? d : d245;
-    }
+    // dense barycentric rows of the six hull points, built once
+    double H0[4], H1[4], H2[4], H3[4], H4[4], H5[4];
+    hull_dense(h0, H0);
+    hull_dense(h1, H1);
+    hull_dense(h2, H2);
+    hull_dense(h3, H3);
+    hull_dense(h4, H4);
+    hull_dense(h5, H5);
+    const double d125 = fabs(det3_bary(H0, H1, H2, H5)), d145 = fabs(det3_bary(H0, H1, H4, H5));
+    const double d345 = fabs(det3_bary(H0, H3, H4, H5));
+    const double d124 = fabs(det3_bary(H0, H1, H2, H4)), d245 = fabs(det3_bary(H0, H2, H4, H5));
     const double v1 = (d125 + d145) + d345, v2 = (d124 + d245) + d345;
     const bool alt = c2 && !(v1 >= v2);  // second diagonal
-    // subtets of T_I (rolled):
-    //   0: (h0, h1, h2, alt ? h4 : h5)   1: (h0, alt ? h2 : h1, h4, h5)   2: (h0, h3, h4, h5)
-#pragma unroll 1
-    for (int t = 0; t < 3; ++t) {
-        const HullPt A = (t == 0) ? h1 : ((t == 1) ? (alt ? h2 : h1) : h3);
-        const HullPt B = (t == 0) ? h2 : h4;
-        const HullPt C = (t == 0 && alt) ? h4 : h5;
-        const double dv = (t == 0) ? (alt ? d124 : d125) : ((t == 1) ? (alt ? d245 : d145) : d345);
-        subtet_moments<T>(h0, A, B, C, vol * dv, D, G);
+    // subtets of T_I: (h0, h1, h2, alt ? h4 : h5), (h0, alt ? h2 : h1, h4, h5), (h0, h3, h4, h5)
+    double XA[4], YB[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        XA[l] = alt ? H4[l] : H5[l];
+        YB[l] = alt ? H2[l] : H1[l];
     }
+    subtet_moments<T>(H0, H1, H2, XA, vol * (alt ? d124 : d125), D, G);
+    subtet_moments<T>(H0, YB, H4, H5, vol * (alt ? d245 : d145), D, G);
+    subtet_moments<T>(H0, H3, H4, H5, vol * d345, D, G);
     g.nin = ni;
     g.nplanes = any ? (c2 ? 2 : 1) : 0;
-    plane_hull(c3 ? h3 : h1, c3 ? h4 : h2, alt ? h4 : h5, in, g.c0);
-    plane_hull(alt ? h2 : h1, h4, h5, in, g.c1);
+    // planes: c0 through (h3, h4, h5) for n_in = 3, else (h1, h2, alt ? h4 : h5);
+    // c1 (n_in = 2) through (alt ? h2 : h1, h4, h5)
+    double PA[4], PB[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        PA[l] = c3 ? H3[l] : H1[l];
+        PB[l] = c3 ? H4[l] : H2[l];
+    }
+    plane_dense(PA, PB, XA, in, g.c0);
+    plane_dense(YB, H4, H5, in, g.c1);
     // sample test: a missing plane is replaced by one that holds everywhere
     // (c = (1,1,1,1): c.lambda = 1 >= 0), and for n_in = 0 by one that never holds.
 #pragma unroll
@@ -419,20 +405,27 @@ __device__ inline void cut_det(const double* X, double vol, const double* p, dou
 template <typename T>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
-    // relative vertex coordinates e_l = X_l - p
-    double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
-    double e1x = X[3] - p[0], e1y = X[4] - p[1], e1z = X[5] - p[2];
-    double e2x = X[6] - p[0], e2y = X[7] - p[1], e2z = X[8] - p[2];
-    double e3x = X[9] - p[0], e3y = X[10] - p[1], e3z = X[11] - p[2];
-    // Monte Carlo sums over the accepted samples.  In double: count, sum
-    // lambda_j (j = 1..3), sum lambda_i lambda_j (1 <= i <= j <= 3); the
-    // lambda_0 terms follow from sum_l lambda_l = 1 exactly (the lambdas are
-    // 21-bit dyadics, so every sum is exact for N <= 2048).  In float that
-    // completion would cancel, so all 15 sums are accumulated directly.
+    // The sample barycentrics are lambda = L * 2^-21 with integer L (spacings
+    // of 21-bit uniforms).  The loop works with L itself: the relative vertex
+    // coordinates e_l = X_l - p and the plane coefficients are prescaled by
+    // 2^-21 (exact), so every product lambda * e equals L * e' exactly and all
+    // roundings are those of the lambda form.  The sums are scaled back at the
+    // end (exact powers of two).
+    const double u = 1.0 / 2097152.0;
+    double e0x = (X[0] - p[0]) * u, e0y = (X[1] - p[1]) * u, e0z = (X[2] - p[2]) * u;
+    double e1x = (X[3] - p[0]) * u, e1y = (X[4] - p[1]) * u, e1z = (X[5] - p[2]) * u;
+    double e2x = (X[6] - p[0]) * u, e2y = (X[7] - p[1]) * u, e2z = (X[8] - p[2]) * u;
+    double e3x = (X[9] - p[0]) * u, e3y = (X[10] - p[1]) * u, e3z = (X[11] - p[2]) * u;
+    const double p00 = g.c0[0] * u, p01 = g.c0[1] * u, p02 = g.c0[2] * u, p03 = g.c0[3] * u;
+    const double p10 = g.c1[0] * u, p11 = g.c1[1] * u, p12 = g.c1[2] * u, p13 = g.c1[3] * u;
+    // Monte Carlo sums over the accepted samples, in units of 2^-21 (first
+    // moments) and 2^-42 (second moments).  In double: count, sum L_j (j = 1..3),
+    // sum L_i L_j (1 <= i <= j <= 3), all exact integers for N <= 2048; the
+    // L_0 terms follow exactly from sum_l L_l = 2^21.  In float that completion
+    // would cancel, so all 15 sums are accumulated directly.
     constexpr bool kF32 = sizeof(T) == 4;
     T cnt = 0, a0 = 0, a1 = 0, a2 = 0, a3 = 0, b00 = 0, b01 = 0, b02 = 0, b03 = 0, b11 = 0, b12 = 0, b13 = 0,
       b22 = 0, b23 = 0, b33 = 0;
-    const double sc = 1.0 / 2097152.0;
     for (int s = 0; s < N; s += 2) {
         uint32_t w[4];
         philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
@@ -441,13 +434,13 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
             if (s + h < N) {
                 uint32_t L[4];
                 lambda_u(w, h, L);
-                double l0 = (double)L[0] * sc, l1 = (double)L[1] * sc, l2 = (double)L[2] * sc, l3 = (double)L[3] * sc;
+                double l0 = (double)L[0], l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
                 double dx = fma(l3, e3x, fma(l2, e2x, fma(l1, e1x, l0 * e0x)));
                 double dy = fma(l3, e3y, fma(l2, e2y, fma(l1, e1y, l0 * e0y)));
                 double dz = fma(l3, e3z, fma(l2, e2z, fma(l1, e1z, l0 * e0z)));
                 double rr = fma(dz, dz, fma(dy, dy, dx * dx));
-                double h0 = fma(g.c0[3], l3, fma(g.c0[2], l2, fma(g.c0[1], l1, g.c0[0] * l0)));
-                double h1 = fma(g.c1[3], l3, fma(g.c1[2], l2, fma(g.c1[1], l1, g.c1[0] * l0)));
+                double h0 = fma(p03, l3, fma(p02, l2, fma(p01, l1, p00 * l0)));
+                double h1 = fma(p13, l3, fma(p12, l2, fma(p11, l1, p10 * l0)));
                 bool inU = (h0 >= 0.0) && (h1 >= 0.0);
                 bool acc = (rr < d2) && !inU;
                 T x1 = acc ? (T)l1 : (T)0, x2 = acc ? (T)l2 : (T)0, x3 = acc ? (T)l3 : (T)0;
@@ -464,16 +457,17 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
             }
         }
     }
-    double dc = (double)cnt, d1 = (double)a1, d2s = (double)a2, d3 = (double)a3;
-    double c11 = (double)b11, c12 = (double)b12, c13 = (double)b13, c22 = (double)b22, c23 = (double)b23,
-           c33 = (double)b33;
+    const double u2 = u * u;
+    double dc = (double)cnt, d1 = (double)a1 * u, d2s = (double)a2 * u, d3 = (double)a3 * u;
+    double c11 = (double)b11 * u2, c12 = (double)b12 * u2, c13 = (double)b13 * u2, c22 = (double)b22 * u2,
+           c23 = (double)b23 * u2, c33 = (double)b33 * u2;
     double d0, c00, c01, c02, c03;
     if (kF32) {
-        d0 = (double)a0;
-        c00 = (double)b00;
-        c01 = (double)b01;
-        c02 = (double)b02;
-        c03 = (double)b03;
+        d0 = (double)a0 * u;
+        c00 = (double)b00 * u2;
+        c01 = (double)b01 * u2;
+        c02 = (double)b02 * u2;
+        c03 = (double)b03 * u2;
     } else {
         d0 = ((dc - d1) - d2s) - d3;
         c01 = ((d1 - c11) - c12) - c13;

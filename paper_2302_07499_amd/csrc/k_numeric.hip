@@ -140,10 +140,12 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
             for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
         }
         if (omega) {
-            unsigned long long* ga = a.gacc + 22 * (int64_t)m;
-            if (n_in) fxs_add_global(&ga[20], &ga[21], pw * (double)n_in, wfx);
+            // word-major accumulators: lanes with nearby m update nearby addresses
+            unsigned long long* ga = a.gacc + (int64_t)m;
+            const int64_t ks = a.gstride;
+            if (n_in) fxs_add_global(&ga[20 * ks], &ga[21 * ks], pw * (double)n_in, wfx);
             if (n_cut)
-                for (int i = 0; i < 10; ++i) fxs_add_global(&ga[2 * i], &ga[2 * i + 1], pw * g[i], gfx);
+                for (int i = 0; i < 10; ++i) fxs_add_global(&ga[(2 * i) * ks], &ga[(2 * i + 1) * ks], pw * g[i], gfx);
         }
     }
     __syncthreads();

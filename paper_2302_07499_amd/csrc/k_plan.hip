@@ -267,31 +267,56 @@ __global__ __launch_bounds__(256) void k_classify(const double* tetX, const int3
         for (int bb = 0; bb < 5; ++bb) cnt[oi * 5 + bb] = c[bb];
 }
 
-// One wave per outer tet: the hits, grouped by cut count (4 first) and in
-// candidate order within a group, to the final pair arrays.
+// which of the 4 outer points cut the tet (bit k set: class of point k is CUT)
+__device__ __forceinline__ int cut_mask(uint32_t code) {
+    int mk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mk |= ((((code >> (3 * k)) & 7u) >= (uint32_t)C_CUT0) ? 1 : 0) << k;
+    return mk;
+}
+
+// One wave per outer tet: the hits, grouped by their cut mask (more cut
+// points first, then the larger mask) and in candidate order within a group,
+// to the final pair arrays.  Lanes of a wave then see the same cut points, so
+// the sample loops of a wave are not run for points that only some lanes cut.
 __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cnt,
                                                       const int64_t* pair_off, const int32_t* hit_m,
                                                       const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
-    int64_t base[5];
-    int64_t run = pair_off[oi];
-    for (int b = 4; b >= 0; --b) {
-        base[b] = run;
-        run += cnt[oi * 5 + b];
-    }
-    const int64_t n = run - pair_off[oi];
+    (void)cnt;
+    const int64_t n = pair_off[oi + 1] - pair_off[oi];
     const int64_t src = cand_off[oi];
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    int64_t c[5] = {0, 0, 0, 0, 0};
+    int64_t c[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) c[b] = 0;
+    for (int64_t j = 0; j < n; j += 64) {
+        const bool valid = j + lane < n;
+        const int mk = valid ? cut_mask(hit_cls[src + j + lane]) : -1;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) c[b] += __popcll(__ballot(mk == b));
+    }
+    // group order: 15 | 14 13 11 7 | 12 10 9 6 5 3 | 8 4 2 1 | 0
+    const int order[16] = {15, 14, 13, 11, 7, 12, 10, 9, 6, 5, 3, 8, 4, 2, 1, 0};
+    int64_t base[16];
+    int64_t run = pair_off[oi];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        base[order[i]] = run;
+        run += c[order[i]];
+    }
+#pragma unroll
+    for (int b = 0; b < 16; ++b) c[b] = 0;
     for (int64_t j = 0; j < n; j += 64) {
         const bool valid = j + lane < n;
         const uint32_t code = valid ? hit_cls[src + j + lane] : 0u;
         const int m = valid ? hit_m[src + j + lane] : 0;
-        const int nc = (int)(code >> 12);
-        for (int b = 0; b <= 4; ++b) {
-            const bool mine = valid && nc == b;
+        const int mk = valid ? cut_mask(code) : -1;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const bool mine = mk == b;
             const uint64_t mask = __ballot(mine);
             if (mine) {
                 const int64_t pos = base[b] + c[b] + __popcll(mask & lt);

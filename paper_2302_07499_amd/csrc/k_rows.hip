@@ -279,8 +279,8 @@ __global__ void k_g_finalize(int64_t K, const uint8_t* region, const int32_t* in
                              const unsigned long long* gacc, int g_shift, int w_shift, double* gvals) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= K || !region[e] || inner_cnt[e] == 0) return;
-    const unsigned long long* a = gacc + 22 * e;
-    const double win = fxs_value(a[20], a[21], w_shift);
+    const unsigned long long* a = gacc + e;  // word i of tet e at a[i * K]
+    const double win = fxs_value(a[20 * K], a[21 * K], w_shift);
     // S2 = sum_r (|E|/4) K_r K_r^T, K_r = barycentric coordinates of node r
     const double w = vol[e] * 0.25;
     double s2[10];
@@ -293,7 +293,8 @@ __global__ void k_g_finalize(int64_t K, const uint8_t* region, const int32_t* in
                 s2[k++] += (w * ki) * kj;
             }
     }
-    for (int i = 0; i < 10; ++i) gvals[10 * e + i] = fxs_value(a[2 * i], a[2 * i + 1], g_shift) + win * s2[i];
+    for (int i = 0; i < 10; ++i)
+        gvals[10 * e + i] = fxs_value(a[2 * i * K], a[(2 * i + 1) * K], g_shift) + win * s2[i];
 }
 
 // One block per free row.

@@ -64,15 +64,16 @@ hipError_t launch_cell_keys(const double* tet_min, int64_t K, Grid g, uint64_t* 
 hipError_t launch_cell_start(const uint64_t* sorted_keys, int64_t K, int64_t n_cells, int64_t* cell_start,
                              hipStream_t s);
 // ball query: candidate count per outer tet (upper bound of its pairs), then
-// one classification pass writing hits to each outer tet's candidate region
-// (cnt[n_outer*5] = hits per cut-count bucket), then the grouped compaction.
+// the classification of every candidate (cand_code: one class byte per outer
+// point; cnt[n_outer*5] = hits per cut-count bucket), then the grouped
+// compaction of the hits into the pair arrays.
 hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                              const int64_t* cell_start, Grid g, double delta, int64_t* cand, hipStream_t s);
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
                            const uint32_t* cell_tets, Grid g, double delta, const int64_t* cand_off, int64_t* cnt,
-                           int32_t* hit_m, uint16_t* hit_cls, hipStream_t s);
-hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cnt, const int64_t* pair_off,
-                               const int32_t* hit_m, const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls,
+                           int32_t* cand_m, uint32_t* cand_code, hipStream_t s);
+hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* pair_off,
+                               const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls,
                                hipStream_t s);
 hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s);
 // local vertex sets Ve of the outer tets: count pass writes ucount[oi], fill

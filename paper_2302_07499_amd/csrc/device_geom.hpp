@@ -103,11 +103,62 @@ __device__ inline bool meets_ball(const double* X, const double* p, double d2) {
     return false;
 }
 
+// True if a face plane of the tet separates p from it by more than sqrt(lim):
+// the distance from p to that plane bounds its distance to the closed tet
+// from below.  Only used to skip the exact test for tets that are surely apart.
+__device__ inline bool separated(const double* X, const double* p, double lim) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        // face opposite vertex f: (A, B, C) = the other three, D = vertex f
+        const double* A = X + 3 * (f == 0 ? 1 : 0);
+        const double* B = X + 3 * (f <= 1 ? 2 : 1);
+        const double* C = X + 3 * (f <= 2 ? 3 : 2);
+        const double* D = X + 3 * f;
+        const double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        const double v[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+        const double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+        const double sp = n[0] * (p[0] - A[0]) + n[1] * (p[1] - A[1]) + n[2] * (p[2] - A[2]);
+        const double sd = n[0] * (D[0] - A[0]) + n[1] * (D[1] - A[1]) + n[2] * (D[2] - A[2]);
+        if (sp * sd < 0.0 && sp * sp > lim * (n[0] * n[0] + n[1] * n[1] + n[2] * n[2])) return true;
+    }
+    return false;
+}
+
 // Classification against the open ball: 4 vertices inside -> IN, 1..3 ->
 // CUT(n_in), none -> CUT(0) if the tet still meets the ball, else OUT.
-// A bounding-box distance test first discards tets that are surely apart
-// (margin 1e-9 relative, far above rounding), which leaves the result equal
-// to the exact test.
+// A bounding-box distance test and a separating-face-plane test first discard
+// tets that are surely apart (margin 1e-9 relative, far above rounding), which
+// leaves the result equal to the exact test.
+// Fast part of the classification: the class, or -1 when only the exact
+// closed-tet test can decide between CUT(0) and OUT.
+__device__ inline int classify_fast(const double* X, const double* p, double d2) {
+    int nin = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        double dx = X[3 * l] - p[0], dy = X[3 * l + 1] - p[1], dz = X[3 * l + 2] - p[2];
+        double r2 = (dx * dx + dy * dy) + dz * dz;
+        nin += (r2 < d2) ? 1 : 0;
+    }
+    if (nin == 4) return C_IN;
+    if (nin > 0) return C_CUT0 + nin;
+    double bd = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double lo = fmin(fmin(X[i], X[3 + i]), fmin(X[6 + i], X[9 + i]));
+        double hi = fmax(fmax(X[i], X[3 + i]), fmax(X[6 + i], X[9 + i]));
+        double g = fmax(fmax(lo - p[i], p[i] - hi), 0.0);
+        bd += g * g;
+    }
+    if (bd > d2 * (1.0 + 1e-9)) return C_OUT;
+    return -1;
+}
+
+// Exact part for a tet with no vertex inside the open ball.
+__device__ inline int classify_exact(const double* X, const double* p, double d2) {
+    if (separated(X, p, d2 * (1.0 + 1e-9))) return C_OUT;
+    return meets_ball(X, p, d2) ? C_CUT0 : C_OUT;
+}
+
 __device__ inline int classify(const double* X, const double* p, double d2, double* r2) {
     int nin = 0;
 #pragma unroll
@@ -127,6 +178,7 @@ __device__ inline int classify(const double* X, const double* p, double d2, doub
         bd += g * g;
     }
     if (bd > d2 * (1.0 + 1e-9)) return C_OUT;
+    if (separated(X, p, d2 * (1.0 + 1e-9))) return C_OUT;
     return meets_ball(X, p, d2) ? C_CUT0 : C_OUT;
 }
 
@@ -234,7 +286,9 @@ __device__ __forceinline__ double edge_t(const double* Xg, const double* p, doub
     double B = dot3(ea, dv);
     double C = r2a - d2;
     double s = sqrt(B * B - A * C);
-    double t = (B <= 0.0) ? (s - B) / A : (-C) / (B + s);
+    // the stable root form picked by the sign of B, with a single division
+    const bool neg = B <= 0.0;
+    double t = (neg ? (s - B) : (-C)) / (neg ? A : (B + s));
     return t > 1.0 ? 1.0 : t;
 }
 

@@ -206,13 +206,23 @@ __global__ void k_cand_count(const double* tetX, const int32_t* outer_ids, int64
     cand[oi] = tot;
 }
 
-// One wave per outer tet: exact classification of every candidate for the
-// four outer points; hits go to the tet's candidate region in candidate
-// order, with their count per "number of cut points" bucket.
-__global__ __launch_bounds__(256) void k_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
-                                                  const int64_t* cell_start, const uint32_t* cell_tets, Grid g,
-                                                  double delta, const int64_t* cand_off, int64_t* cnt, int32_t* hit_m,
-                                                  uint16_t* hit_cls) {
+// Classification in three passes over the candidate regions of the outer
+// tets (region of outer tet oi: [cand_off[oi], cand_off[oi+1]), candidates
+// in (cell row, cell, cell list) order):
+//   k_classify_fast   one wave per outer tet writes every candidate's tet and
+//                     one class byte per outer point: IN / CUT(n_in) / OUT,
+//                     or kPending when only the exact closed-tet test can
+//                     decide between CUT(0) and OUT;
+//   k_classify_exact  one block per outer tet queues the pending (candidate,
+//                     point) cases in LDS and tests them densely, patches the
+//                     codes, and counts the hits per "number of cut points";
+//   k_pair_compact    (below) gathers the hits into the pair arrays.
+constexpr uint32_t kPending = 0xFFu;
+
+__global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
+                                                       const int64_t* cell_start, const uint32_t* cell_tets, Grid g,
+                                                       double delta, const int64_t* cand_off, int32_t* cand_m,
+                                                       uint32_t* cand_code) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
@@ -223,78 +233,173 @@ __global__ __launch_bounds__(256) void k_classify(const double* tetX, const int3
     int y0, y1, z0, z1;
     axis_range(b, 1, g, y0, y1);
     axis_range(b, 2, g, z0, z1);
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    const int64_t base = cand_off[oi];
-    int64_t nhit = 0;
-    int64_t c[5] = {0, 0, 0, 0, 0};
+    int64_t pos0 = cand_off[oi];
     for (int cz = z0; cz <= z1; ++cz) {
         for (int cy = y0; cy <= y1; ++cy) {
             int x0, x1;
             if (!row_range(b, g, cy, cz, x0, x1)) continue;
             const int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
             const int64_t beg = cell_start[row + x0], end = cell_start[row + x1 + 1];
-            for (int64_t j = beg; j < end; j += 64) {
-                const int64_t idx = j + lane;
-                const bool valid = idx < end;
+            for (int64_t j = beg + lane; j < end; j += 64) {
+                const int m = (int)cell_tets[j];
+                double X[12];
+                for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
                 uint32_t code = 0;
-                int ncut = 0;
-                bool hit = false;
-                int m = 0;
-                if (valid) {
-                    m = (int)cell_tets[idx];
-                    double X[12];
-                    for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
-                    for (int k = 0; k < 4; ++k) {
-                        double r2[4];
-                        const int cl = classify(X, P[k], d2, r2);
-                        code |= (uint32_t)cl << (3 * k);
-                        hit = hit || (cl != C_OUT);
-                        ncut += (cl >= C_CUT0) ? 1 : 0;
-                    }
+                for (int k = 0; k < 4; ++k) {
+                    const int cl = classify_fast(X, P[k], d2);
+                    code |= (cl < 0 ? kPending : (uint32_t)cl) << (8 * k);
                 }
-                const uint64_t mask = __ballot(hit);
-                if (hit) {
-                    const int64_t pos = base + nhit + __popcll(mask & lt);
-                    hit_m[pos] = m;
-                    hit_cls[pos] = (uint16_t)(code | ((uint32_t)ncut << 12));
-                }
-                nhit += __popcll(mask);
-                for (int bb = 0; bb <= 4; ++bb) c[bb] += __popcll(__ballot(hit && ncut == bb));
+                const int64_t pos = pos0 + (j - beg);
+                cand_m[pos] = m;
+                cand_code[pos] = code;
             }
+            pos0 += end - beg;
         }
     }
-    if (lane == 0)
-        for (int bb = 0; bb < 5; ++bb) cnt[oi * 5 + bb] = c[bb];
 }
 
-// which of the 4 outer points cut the tet (bit k set: class of point k is CUT)
-__device__ __forceinline__ int cut_mask(uint32_t code) {
-    int mk = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) mk |= ((((code >> (3 * k)) & 7u) >= (uint32_t)C_CUT0) ? 1 : 0) << k;
-    return mk;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave per outer tet: the hits, grouped by their cut mask (more cut
-// points first, then the larger mask) and in candidate order within a group,
-// to the final pair arrays.  Lanes of a wave then see the same cut points, so
-// the sample loops of a wave are not run for points that only some lanes cut.
-__global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cnt,
-                                                      const int64_t* pair_off, const int32_t* hit_m,
-                                                      const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls) {
+// One wave per outer tet: the pending (candidate, point) cases are queued in
+// the wave's LDS slice across candidate chunks and tested in full rounds of
+// 64; each result replaces its pending byte (one atomic AND: CUT(0) = 2,
+// OUT = 0 both fit under the 0xFF mask).
+constexpr int kQueue = 320;  // < 64 left over + 4 * 64 appended per chunk
+
+__global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
+                                                        double delta, const int64_t* cand_off, const int32_t* cand_m,
+                                                        uint32_t* cand_code) {
+    __shared__ int64_t qp[4][kQueue];
+    __shared__ uint8_t qk[4][kQueue];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
-    (void)cnt;
-    const int64_t n = pair_off[oi + 1] - pair_off[oi];
-    const int64_t src = cand_off[oi];
+    double P[4][3];
+    load_outer_points(tetX, outer_ids[oi], P);
+    const double d2 = delta * delta;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int64_t* Q = qp[wave];
+    uint8_t* K = qk[wave];
+    auto run = [&](int j) {  // test queue item j (lane-private)
+        const int64_t pos = Q[j];
+        const int k = K[j];
+        const double* Xg = tetX + 12 * (int64_t)cand_m[pos];
+        double X[12];
+        for (int e = 0; e < 12; ++e) X[e] = Xg[e];
+        const uint32_t res = (uint32_t)classify_exact(X, P[k], d2);
+        atomicAnd(&cand_code[pos], ~(0xFFu << (8 * k)) | (res << (8 * k)));
+    };
+    const int64_t src = cand_off[oi], n = cand_off[oi + 1] - src;
+    int nq = 0;
+    for (int64_t j = 0; j < n; j += 64) {
+        const int64_t pos = src + j + lane;
+        const uint32_t code = (j + lane < n) ? cand_code[pos] : 0u;
+        for (int k = 0; k < 4; ++k) {
+            const bool pend = ((code >> (8 * k)) & 0xFFu) == kPending;
+            const uint64_t bal = __ballot(pend);
+            if (pend) {
+                const int idx = nq + __popcll(bal & lt);
+                Q[idx] = pos;
+                K[idx] = (uint8_t)k;
+            }
+            nq += __popcll(bal);
+        }
+        wave_sync();
+        while (nq >= 64) {
+            run(lane);
+            // move the rest of the queue down by 64
+            int64_t keep_p[4];
+            uint8_t keep_k[4];
+            const int rest = nq - 64;
+            for (int r = 0; r < 4; ++r) {
+                const int from = 64 + lane + 64 * r;
+                if (from < nq) {
+                    keep_p[r] = Q[from];
+                    keep_k[r] = K[from];
+                }
+            }
+            wave_sync();
+            for (int r = 0; r < 4; ++r) {
+                const int to = lane + 64 * r;
+                if (to < rest) {
+                    Q[to] = keep_p[r];
+                    K[to] = keep_k[r];
+                }
+            }
+            wave_sync();
+            nq = rest;
+        }
+    }
+    if (lane < nq) run(lane);
+}
+
+// Per outer tet: hits per "number of cut points" bucket (cnt[oi*5 + b]).
+__global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off,
+                                                    const uint32_t* cand_code, int64_t* cnt) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
+    if (oi >= n_outer) return;
+    const int64_t src = cand_off[oi], n = cand_off[oi + 1] - src;
+    int64_t c[5] = {0, 0, 0, 0, 0};
+    for (int64_t j = 0; j < n; j += 64) {
+        const uint32_t code = (j + lane < n) ? cand_code[src + j + lane] : 0u;
+        int ncut = 0;
+        bool hit = false;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t cl = (code >> (8 * k)) & 7u;
+            hit = hit || cl != (uint32_t)C_OUT;
+            ncut += cl >= (uint32_t)C_CUT0 ? 1 : 0;
+        }
+        for (int b = 0; b <= 4; ++b) c[b] += __popcll(__ballot(hit && ncut == b));
+    }
+    if (lane < 5) {
+        int64_t v = 0;
+        for (int b = 0; b <= 4; ++b)
+            if (b == lane) v = c[b];
+        cnt[oi * 5 + lane] = v;
+    }
+}
+
+// packed per-point class bytes -> 3-bit-per-point pair code
+__device__ __forceinline__ uint32_t code12(uint32_t code) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c |= ((code >> (8 * k)) & 7u) << (3 * k);
+    return c;
+}
+
+// which of the 4 outer points cut the tet (bit k set: class of point k is CUT)
+__device__ __forceinline__ int cut_mask(uint32_t c12) {
+    int mk = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mk |= ((((c12 >> (3 * k)) & 7u) >= (uint32_t)C_CUT0) ? 1 : 0) << k;
+    return mk;
+}
+
+// One wave per outer tet: the hits among its candidates, grouped by their cut
+// mask (more cut points first, then the larger mask) and in candidate order
+// within a group, to the final pair arrays.  Lanes of a wave then see the same
+// cut points, so the sample loops of a wave are not run for points that only
+// some lanes cut.
+__global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* pair_off,
+                                                      const int32_t* cand_m, const uint32_t* cand_code,
+                                                      int32_t* pair_m, uint16_t* pair_cls) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
+    if (oi >= n_outer) return;
+    const int64_t src = cand_off[oi], n = cand_off[oi + 1] - src;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     int64_t c[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
     for (int64_t j = 0; j < n; j += 64) {
         const bool valid = j + lane < n;
-        const int mk = valid ? cut_mask(hit_cls[src + j + lane]) : -1;
+        const uint32_t cc = valid ? code12(cand_code[src + j + lane]) : 0u;
+        const int mk = cc ? cut_mask(cc) : -1;
 #pragma unroll
         for (int b = 0; b < 16; ++b) c[b] += __popcll(__ballot(mk == b));
     }
@@ -311,9 +416,9 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     for (int b = 0; b < 16; ++b) c[b] = 0;
     for (int64_t j = 0; j < n; j += 64) {
         const bool valid = j + lane < n;
-        const uint32_t code = valid ? hit_cls[src + j + lane] : 0u;
-        const int m = valid ? hit_m[src + j + lane] : 0;
-        const int mk = valid ? cut_mask(code) : -1;
+        const uint32_t cc = valid ? code12(cand_code[src + j + lane]) : 0u;
+        const int mk = cc ? cut_mask(cc) : -1;
+        const int m = mk >= 0 ? cand_m[src + j + lane] : 0;
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
             const bool mine = mk == b;
@@ -321,7 +426,7 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
             if (mine) {
                 const int64_t pos = base[b] + c[b] + __popcll(mask & lt);
                 pair_m[pos] = m;
-                pair_cls[pos] = (uint16_t)(code & 0xFFFu);
+                pair_cls[pos] = (uint16_t)cc;
             }
             c[b] += __popcll(mask);
         }
@@ -344,21 +449,87 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 }
 
 // One block per outer tet: the sorted set Ve of vertices of the inner tets of
-// its pair list (LDS hash set, then bitonic sort).  The count pass writes |Ve|,
-// the fill pass the set itself at ve_off.
+// its pair list.  When the vertex ids span at most 32 * kBitmapWords values
+// (spatially ordered meshes: always), the set is a bitmap over that range,
+// read out in ascending order through a block prefix sum of word popcounts;
+// otherwise an LDS hash set sorted by a bitonic network.  The count pass
+// writes |Ve|, the fill pass the set itself at ve_off.
+constexpr int kBitmapWords = 2048;
+
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
                                                  const int32_t* pair_m, int hash_cap, int64_t* ucount,
                                                  const int64_t* ve_off, int32_t* ve_ids, unsigned* err) {
     extern __shared__ uint32_t hs[];
-    __shared__ int sU;
+    __shared__ int sU, sLo, sHi;
+    __shared__ int wsum[256];
     const uint32_t EMPTY = 0xFFFFFFFFu;
     const int64_t oi = blockIdx.x;
     const int t = threadIdx.x;
-    for (int i = t; i < hash_cap; i += 256) hs[i] = EMPTY;
-    if (t == 0) sU = 0;
+    if (t == 0) {
+        sU = 0;
+        sLo = 0x7FFFFFFF;
+        sHi = -1;
+    }
     __syncthreads();
     const int64_t p0 = pair_off[oi], p1 = pair_off[oi + 1];
+    int lo = 0x7FFFFFFF, hi = -1;
+    for (int64_t p = p0 + t; p < p1; p += 256) {
+        const int m = pair_m[p];
+        for (int j = 0; j < 4; ++j) {
+            const int v = tets[4 * (int64_t)m + j];
+            lo = min(lo, v);
+            hi = max(hi, v);
+        }
+    }
+    atomicMin(&sLo, lo);
+    atomicMax(&sHi, hi);
+    __syncthreads();
+    const int vlo = sLo;
+    const int64_t range = (int64_t)sHi - (int64_t)vlo + 1;
+    if (range > 0 && range <= 32 * (int64_t)kBitmapWords) {
+        const int nw = (int)((range + 31) >> 5);
+        for (int i = t; i < nw; i += 256) hs[i] = 0u;
+        __syncthreads();
+        for (int64_t p = p0 + t; p < p1; p += 256) {
+            const int m = pair_m[p];
+            for (int j = 0; j < 4; ++j) {
+                const int r = tets[4 * (int64_t)m + j] - vlo;
+                atomicOr(&hs[r >> 5], 1u << (r & 31));
+            }
+        }
+        __syncthreads();
+        // thread t owns words [t * cw, (t + 1) * cw)
+        const int cw = (nw + 255) / 256;
+        const int w0 = min(nw, t * cw), w1 = min(nw, (t + 1) * cw);
+        int c = 0;
+        for (int w = w0; w < w1; ++w) c += __popc(hs[w]);
+        wsum[t] = c;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int add = t >= off ? wsum[t - off] : 0;
+            __syncthreads();
+            wsum[t] += add;
+            __syncthreads();
+        }
+        if (!FILL) {
+            if (t == 0) ucount[oi] = wsum[255];
+            return;
+        }
+        int pos = wsum[t] - c;
+        const int64_t vb = ve_off[oi];
+        for (int w = w0; w < w1; ++w) {
+            uint32_t bits = hs[w];
+            while (bits) {
+                const int bb = __ffs(bits) - 1;
+                ve_ids[vb + pos++] = vlo + 32 * w + bb;
+                bits &= bits - 1u;
+            }
+        }
+        return;
+    }
+    for (int i = t; i < hash_cap; i += 256) hs[i] = EMPTY;
+    __syncthreads();
     const uint32_t hmask = (uint32_t)hash_cap - 1u;
     for (int64_t p = p0 + t; p < p1; p += 256) {
         int m = pair_m[p];
@@ -464,19 +635,22 @@ hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64
 
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
                            const uint32_t* cell_tets, Grid g, double delta, const int64_t* cand_off, int64_t* cnt,
-                           int32_t* hit_m, uint16_t* hit_cls, hipStream_t s) {
+                           int32_t* cand_m, uint32_t* cand_code, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    k_classify<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g, delta,
-                                                             cand_off, cnt, hit_m, hit_cls);
+    k_classify_fast<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g,
+                                                                  delta, cand_off, cand_m, cand_code);
+    k_classify_exact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, delta, cand_off, cand_m,
+                                                                    cand_code);
+    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_code, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cnt, const int64_t* pair_off,
-                               const int32_t* hit_m, const uint16_t* hit_cls, int32_t* pair_m, uint16_t* pair_cls,
+hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* pair_off,
+                               const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls,
                                hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cnt, pair_off, hit_m, hit_cls,
-                                                                 pair_m, pair_cls);
+    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, pair_off, cand_m, cand_code, pair_m,
+                                                                 pair_cls);
     return hipGetLastError();
 }
 
@@ -490,7 +664,7 @@ hipError_t launch_pattern(bool fill, const int32_t* tets, int64_t n_outer, const
                           const int32_t* pair_m, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
                           unsigned* err, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    size_t sh = (size_t)hash_cap * sizeof(uint32_t);
+    size_t sh = (size_t)(hash_cap > kBitmapWords ? hash_cap : kBitmapWords) * sizeof(uint32_t);
     if (fill)
         k_pattern<true><<<(unsigned)n_outer, 256, sh, s>>>(tets, n_outer, pair_off, pair_m, hash_cap, ucount, ve_off,
                                                           ve_ids, err);

@@ -32,9 +32,13 @@ extern "C" {
 typedef struct nlfem_ctx nlfem_ctx;
 typedef struct nlfem_plan nlfem_plan;
 
+/* Largest N: the sample sums are exact integers (count and sum L_j in 32 bits,
+ * sum L_i L_j in 64 bits), which needs N * 2^21 < 2^32.                       */
+#define NLFEM_MAX_MC_SAMPLES 2047
+
 typedef enum {
     NLFEM_OK = 0,
-    NLFEM_E_INVALID_ARG = 1,   /* null required pointer, delta <= 0, N < 1, negative size     */
+    NLFEM_E_INVALID_ARG = 1,   /* null required pointer, delta <= 0, N outside [1, 2047], negative size */
     NLFEM_E_MESH = 2,          /* index out of range, zero-volume tet, free vertex in a T_OmegaI tet */
     NLFEM_E_OOM = 3,           /* allocation failed or would exceed the context's HBM budget  */
     NLFEM_E_DEVICE = 4,        /* a HIP runtime call failed                                  */
@@ -44,8 +48,8 @@ typedef enum {
 
 typedef enum {
     NLFEM_FP64 = 0,       /* every step in IEEE double                                        */
-    NLFEM_FP32_LOCAL = 1  /* per-pair inner integrals (subtet rule + Monte Carlo sums) in float;
-                             classification, sample acceptance and all global sums in double */
+    NLFEM_FP32_LOCAL = 1  /* per-pair subtet rule in float; classification, sample acceptance,
+                             the (exact, integer) sample sums and all global sums as in FP64  */
 } nlfem_precision;
 
 /* Tetrahedral mesh of Omega u Omega_I (Sec. 3.1: coinciding triangulations of
@@ -66,7 +70,7 @@ typedef struct {
 typedef struct {
     double delta;                /* horizon > 0                                                       */
     double psi;                  /* kernel constant; the operator is L u = 2 int_B (u(y)-u(x)) psi dy */
-    int32_t mc_samples;          /* N >= 1 uniform samples per cut pair (exact sums for N <= 2048)    */
+    int32_t mc_samples;          /* N uniform samples per cut pair, 1 <= N <= NLFEM_MAX_MC_SAMPLES  */
     uint64_t seed;               /* Philox4x32-10 key                                                 */
     int32_t precision;           /* nlfem_precision                                                   */
     const uint8_t *outer_mask;   /* optional [n_tets], same memory kind as the mesh: 1 = use this tet

@@ -26,6 +26,7 @@ NLFEM_E_NOT_CONVERGED = 5
 NLFEM_E_UNSUPPORTED = 6
 NLFEM_FP64 = 0
 NLFEM_FP32_LOCAL = 1
+NLFEM_MAX_MC_SAMPLES = 2047  # sample sums stay exact 32/64-bit integers
 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_MESH", 3: "E_OOM", 4: "E_DEVICE",
                 5: "E_NOT_CONVERGED", 6: "E_UNSUPPORTED"}

@@ -704,7 +704,8 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
         return fail(c, NLFEM_E_INVALID_ARG, "null mesh array");
     if (mesh->mem_kind != 0 && mesh->mem_kind != 1) return fail(c, NLFEM_E_INVALID_ARG, "mem_kind must be 0 or 1");
     if (!(prm->delta > 0.0) || !std::isfinite(prm->delta)) return fail(c, NLFEM_E_INVALID_ARG, "delta must be > 0");
-    if (prm->mc_samples < 1) return fail(c, NLFEM_E_INVALID_ARG, "mc_samples must be >= 1");
+    if (prm->mc_samples < 1 || prm->mc_samples > NLFEM_MAX_MC_SAMPLES)
+        return fail(c, NLFEM_E_INVALID_ARG, "mc_samples must be in [1, " + std::to_string(NLFEM_MAX_MC_SAMPLES) + "]");
     if (prm->precision != NLFEM_FP64 && prm->precision != NLFEM_FP32_LOCAL)
         return fail(c, NLFEM_E_INVALID_ARG, "unknown precision");
     if (mesh->n_tets >= (int64_t)1 << 31 || mesh->n_vertices >= (int64_t)1 << 31)

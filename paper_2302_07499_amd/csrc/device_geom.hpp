@@ -465,6 +465,13 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
     // 2^-21 (exact), so every product lambda * e equals L * e' exactly and all
     // roundings are those of the lambda form.  The sums are scaled back at the
     // end (exact powers of two).
+    //
+    // Sums over the accepted samples are integers: the count and sum L_j
+    // (j = 1..3) in 32 bits, sum L_i L_j (1 <= i <= j <= 3) in 64 bits (one
+    // multiply-add each), exact for N <= 2047.  The L_0 terms follow exactly
+    // from sum_l L_l = 2^21, in integers or, equally exactly, in double (every
+    // partial sum is a multiple of 2^-42 below 2^11).  Both precisions of the
+    // local integrals therefore get the same, exact Monte Carlo moments.
     const double u = 1.0 / 2097152.0;
     double e0x = (X[0] - p[0]) * u, e0y = (X[1] - p[1]) * u, e0z = (X[2] - p[2]) * u;
     double e1x = (X[3] - p[0]) * u, e1y = (X[4] - p[1]) * u, e1z = (X[5] - p[2]) * u;
@@ -472,14 +479,9 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
     double e3x = (X[9] - p[0]) * u, e3y = (X[10] - p[1]) * u, e3z = (X[11] - p[2]) * u;
     const double p00 = g.c0[0] * u, p01 = g.c0[1] * u, p02 = g.c0[2] * u, p03 = g.c0[3] * u;
     const double p10 = g.c1[0] * u, p11 = g.c1[1] * u, p12 = g.c1[2] * u, p13 = g.c1[3] * u;
-    // Monte Carlo sums over the accepted samples, in units of 2^-21 (first
-    // moments) and 2^-42 (second moments).  In double: count, sum L_j (j = 1..3),
-    // sum L_i L_j (1 <= i <= j <= 3), all exact integers for N <= 2048; the
-    // L_0 terms follow exactly from sum_l L_l = 2^21.  In float that completion
-    // would cancel, so all 15 sums are accumulated directly.
     constexpr bool kF32 = sizeof(T) == 4;
-    T cnt = 0, a0 = 0, a1 = 0, a2 = 0, a3 = 0, b00 = 0, b01 = 0, b02 = 0, b03 = 0, b11 = 0, b12 = 0, b13 = 0,
-      b22 = 0, b23 = 0, b33 = 0;
+    uint32_t icnt = 0, ia1 = 0, ia2 = 0, ia3 = 0;
+    uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
     for (int s = 0; s < N; s += 2) {
         uint32_t w[4];
         philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
@@ -497,20 +499,23 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
                 double h1 = fma(p13, l3, fma(p12, l2, fma(p11, l1, p10 * l0)));
                 bool inU = (h0 >= 0.0) && (h1 >= 0.0);
                 bool acc = (rr < d2) && !inU;
-                T x1 = acc ? (T)l1 : (T)0, x2 = acc ? (T)l2 : (T)0, x3 = acc ? (T)l3 : (T)0;
-                cnt += acc ? (T)1 : (T)0;
-                a1 += x1; a2 += x2; a3 += x3;
-                b11 = fma(x1, (T)l1, b11); b12 = fma(x1, (T)l2, b12); b13 = fma(x1, (T)l3, b13);
-                b22 = fma(x2, (T)l2, b22); b23 = fma(x2, (T)l3, b23); b33 = fma(x3, (T)l3, b33);
-                if (kF32) {
-                    T x0 = acc ? (T)l0 : (T)0;
-                    a0 += x0;
-                    b00 = fma(x0, (T)l0, b00); b01 = fma(x0, (T)l1, b01);
-                    b02 = fma(x0, (T)l2, b02); b03 = fma(x0, (T)l3, b03);
-                }
+                const uint32_t x1 = acc ? L[1] : 0u, x2 = acc ? L[2] : 0u, x3 = acc ? L[3] : 0u;
+                icnt += acc ? 1u : 0u;
+                ia1 += x1; ia2 += x2; ia3 += x3;
+                B11 += (uint64_t)x1 * x1; B12 += (uint64_t)x1 * x2; B13 += (uint64_t)x1 * x3;
+                B22 += (uint64_t)x2 * x2; B23 += (uint64_t)x2 * x3; B33 += (uint64_t)x3 * x3;
             }
         }
     }
+    // L_0 terms in integers (used by the float form below)
+    const uint64_t TT = 2097152ull;
+    const uint64_t A1 = ia1, A2 = ia2, A3 = ia3;
+    const uint64_t A0 = (uint64_t)icnt * TT - A1 - A2 - A3;
+    const uint64_t B01 = A1 * TT - B11 - B12 - B13, B02 = A2 * TT - B12 - B22 - B23, B03 = A3 * TT - B13 - B23 - B33;
+    const uint64_t B00 = A0 * TT - B01 - B02 - B03;
+    double cnt = (double)icnt, a0 = (double)A0, a1 = (double)A1, a2 = (double)A2, a3 = (double)A3;
+    double b00 = (double)B00, b01 = (double)B01, b02 = (double)B02, b03 = (double)B03, b11 = (double)B11,
+           b12 = (double)B12, b13 = (double)B13, b22 = (double)B22, b23 = (double)B23, b33 = (double)B33;
     const double u2 = u * u;
     double dc = (double)cnt, d1 = (double)a1 * u, d2s = (double)a2 * u, d3 = (double)a3 * u;
     double c11 = (double)b11 * u2, c12 = (double)b12 * u2, c13 = (double)b13 * u2, c22 = (double)b22 * u2,

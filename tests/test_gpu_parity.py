@@ -219,7 +219,7 @@ def test_single_tet_and_tiny_meshes(dev, orc):
     assert e["ff_abs"] <= FP64_TOL and e["fc_abs"] <= FP64_TOL and e["rhs"] <= FP64_TOL
 
 
-def test_error_paths(dev):
+def test_error_paths(dev, orc):
     import paper_2302_07499_amd as P
     m = mg.kuhn_cube_mesh(2)
     vf = mg.free_mask_box(m.coords, 0.3)
@@ -239,6 +239,18 @@ def test_error_paths(dev):
     with pytest.raises(P.NlfemError) as ei:
         dev.plan(m.coords, m.tets, vf, 0.3, 1.0, 0, 0)
     assert ei.value.status == P.NLFEM_E_INVALID_ARG
+    with pytest.raises(P.NlfemError) as ei:
+        dev.plan(m.coords, m.tets, vf, 0.3, 1.0, P.NLFEM_MAX_MC_SAMPLES + 1, 0)
+    assert ei.value.status == P.NLFEM_E_INVALID_ARG
+    # the largest sample count is accepted and its sums stay exact: the oracle agrees
+    pb = mg.make_problem("maxn", 4, delta_over_h=1.5, jitter=0.1, jitter_seed=2,
+                         mc_samples=P.NLFEM_MAX_MC_SAMPLES, seed=4)
+    plan = dev.plan_problem(pb)
+    g = P.system_to_numpy(plan.assemble(pb.f_qp, pb.g_nodal))
+    o = orc.problem_assemble(pb)
+    e = H.value_errors(g, o)
+    assert e["ff_abs"] <= FP64_TOL and e["fc_abs"] <= FP64_TOL and e["rhs"] <= FP64_TOL, e
+    plan.destroy()
     tiny = P.Device(0, hbm_budget_bytes=4096)
     with pytest.raises(P.NlfemError) as ei:
         tiny.plan(m.coords, m.tets, vf, 0.3, 1.0, 8, 0)

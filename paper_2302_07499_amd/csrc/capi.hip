@@ -266,8 +266,12 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     const int64_t n_cand = read_i64(c, t_cand_off.as<int64_t>() + no);
     TMP(t_cand_m, (size_t)(n_cand + 1) * 4);
     TMP(t_cand_c, (size_t)(n_cand + 1) * 4);
-    HIPCHK(launch_classify(pl->tetX, pl->outer_ids, no, cell_start, cell_tets, g, prm->delta, t_cand_off.as<int64_t>(),
-                           t_cnt.as<int64_t>(), t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), s));
+    TMP(t_cand_n, (size_t)(no + 1) * 8);
+    TMP(t_box, (size_t)(K + 1) * 32);
+    HIPCHK(launch_sorted_boxes(pl->tetX, cell_tets, K, (float4*)t_box.p, s));
+    HIPCHK(launch_classify(pl->tetX, pl->outer_ids, no, cell_start, cell_tets, (const float4*)t_box.p, g, prm->delta,
+                           t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), t_cnt.as<int64_t>(),
+                           t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), s));
     HIPCHK(launch_pair_totals(t_cnt.as<int64_t>(), no, t_tot.as<int64_t>(), s));
     HIPCHK(exclusive_scan_i64(t_tot.as<int64_t>(), pl->pair_off, no, t_scan2.p, s));
     HIPCHK(reduce_max_i64(t_tot.as<int64_t>(), no, (int64_t*)(small + 8), s));
@@ -280,8 +284,8 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
         return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^15 interacting tets for one outer tet");
     ALLOC(pl->pair_m, int32_t, P + 1);
     ALLOC(pl->pair_cls, uint16_t, P + 1);
-    HIPCHK(launch_pair_compact(no, t_cand_off.as<int64_t>(), pl->pair_off, t_cand_m.as<int32_t>(),
-                               t_cand_c.as<uint32_t>(), pl->pair_m, pl->pair_cls, s));
+    HIPCHK(launch_pair_compact(no, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), pl->pair_off,
+                               t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), pl->pair_m, pl->pair_cls, s));
     {
         TMP(t_cc, 64);
         HIPCHK(hipMemsetAsync(t_cc.p, 0, 64, s));

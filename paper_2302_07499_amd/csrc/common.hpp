@@ -63,16 +63,21 @@ hipError_t launch_cell_keys(const double* tet_min, int64_t K, Grid g, uint64_t* 
                             hipStream_t s);
 hipError_t launch_cell_start(const uint64_t* sorted_keys, int64_t K, int64_t n_cells, int64_t* cell_start,
                              hipStream_t s);
-// ball query: candidate count per outer tet (upper bound of its pairs), then
-// the classification of every candidate (cand_code: one class byte per outer
-// point; cnt[n_outer*5] = hits per cut-count bucket), then the grouped
-// compaction of the hits into the pair arrays.
+// ball query: candidate count per outer tet (upper bound of its pairs), the
+// tets' bounding boxes in cell order, then the classification of the
+// candidates (the cand_n[oi] hits of each region compacted at its start,
+// cand_code: one class byte per outer point; cnt[n_outer*5] = hits per
+// cut-count bucket), then the grouped compaction of the hits into the pair
+// arrays.
 hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                              const int64_t* cell_start, Grid g, double delta, int64_t* cand, hipStream_t s);
+hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box,
+                               hipStream_t s);
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
-                           const uint32_t* cell_tets, Grid g, double delta, const int64_t* cand_off, int64_t* cnt,
-                           int32_t* cand_m, uint32_t* cand_code, hipStream_t s);
-hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* pair_off,
+                           const uint32_t* cell_tets, const float4* box, Grid g, double delta,
+                           const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, int32_t* cand_m,
+                           uint32_t* cand_code, hipStream_t s);
+hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n, const int64_t* pair_off,
                                const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls,
                                hipStream_t s);
 hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s);

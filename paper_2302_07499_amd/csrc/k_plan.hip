@@ -184,6 +184,32 @@ __device__ __forceinline__ void load_outer_points(const double* tetX, int n, dou
     for (int k = 0; k < 4; ++k) outer_point(Xn, k, P[k]);
 }
 
+// Bounding boxes of the tets in cell order (box[2j], box[2j+1] = lower and
+// upper corner of tet cell_tets[j]), in float rounded outward, so that the
+// classification can drop far candidates with one coalesced 32-byte read
+// instead of gathering their 96-byte vertex block.
+__global__ void k_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= K) return;
+    const double* X = tetX + 12 * (int64_t)cell_tets[j];
+    float lo[3], hi[3];
+    for (int i = 0; i < 3; ++i) {
+        lo[i] = __double2float_rd(fmin(fmin(X[i], X[3 + i]), fmin(X[6 + i], X[9 + i])));
+        hi[i] = __double2float_ru(fmax(fmax(X[i], X[3 + i]), fmax(X[6 + i], X[9 + i])));
+    }
+    box[2 * j] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    box[2 * j + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+}
+
+// squared distance from p to a box, computed in double from the (outward
+// rounded) float corners: never above the distance to the tet's own box
+__device__ __forceinline__ double box_dist2(const float4& lo, const float4& hi, const double* p) {
+    const double gx = fmax(fmax((double)lo.x - p[0], p[0] - (double)hi.x), 0.0);
+    const double gy = fmax(fmax((double)lo.y - p[1], p[1] - (double)hi.y), 0.0);
+    const double gz = fmax(fmax((double)lo.z - p[2], p[2] - (double)hi.z), 0.0);
+    return (gx * gx + gy * gy) + gz * gz;
+}
+
 // candidates per outer tet (an upper bound of its pair count)
 __global__ void k_cand_count(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
                              Grid g, double delta, int64_t* cand) {
@@ -209,10 +235,13 @@ __global__ void k_cand_count(const double* tetX, const int32_t* outer_ids, int64
 // Classification in three passes over the candidate regions of the outer
 // tets (region of outer tet oi: [cand_off[oi], cand_off[oi+1]), candidates
 // in (cell row, cell, cell list) order):
-//   k_classify_fast   one wave per outer tet writes every candidate's tet and
-//                     one class byte per outer point: IN / CUT(n_in) / OUT,
-//                     or kPending when only the exact closed-tet test can
-//                     decide between CUT(0) and OUT;
+//   k_classify_fast   one wave per outer tet drops candidates whose (sorted,
+//                     float) bounding box is beyond delta of all four points,
+//                     classifies the rest (one class byte per outer point:
+//                     IN / CUT(n_in) / OUT, or kPending when only the exact
+//                     closed-tet test can decide between CUT(0) and OUT) and
+//                     writes those not OUT for every point compacted at the
+//                     start of the region (count in cand_n);
 //   k_classify_exact  one block per outer tet queues the pending (candidate,
 //                     point) cases in LDS and tests them densely, patches the
 //                     codes, and counts the hits per "number of cut points";
@@ -220,8 +249,9 @@ __global__ void k_cand_count(const double* tetX, const int32_t* outer_ids, int64
 constexpr uint32_t kPending = 0xFFu;
 
 __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
-                                                       const int64_t* cell_start, const uint32_t* cell_tets, Grid g,
-                                                       double delta, const int64_t* cand_off, int32_t* cand_m,
+                                                       const int64_t* cell_start, const uint32_t* cell_tets,
+                                                       const float4* box, Grid g, double delta,
+                                                       const int64_t* cand_off, int64_t* cand_n, int32_t* cand_m,
                                                        uint32_t* cand_code) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
@@ -229,33 +259,54 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
     double P[4][3];
     load_outer_points(tetX, outer_ids[oi], P);
     const double d2 = delta * delta;
+    // a box farther than this from a point is certainly OUT for it (the same
+    // bound the vertex-based test uses, so the classes are unchanged)
+    const double far2 = d2 * (1.0 + 1e-9);
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const CandBall b = cand_ball(P, delta);
     int y0, y1, z0, z1;
     axis_range(b, 1, g, y0, y1);
     axis_range(b, 2, g, z0, z1);
-    int64_t pos0 = cand_off[oi];
+    // the candidates with a class other than OUT for some point are written
+    // compacted, in candidate order, from the start of the region
+    const int64_t base = cand_off[oi];
+    int64_t n_hit = 0;
     for (int cz = z0; cz <= z1; ++cz) {
         for (int cy = y0; cy <= y1; ++cy) {
             int x0, x1;
             if (!row_range(b, g, cy, cz, x0, x1)) continue;
             const int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
             const int64_t beg = cell_start[row + x0], end = cell_start[row + x1 + 1];
-            for (int64_t j = beg + lane; j < end; j += 64) {
-                const int m = (int)cell_tets[j];
-                double X[12];
-                for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
+            for (int64_t j0 = beg; j0 < end; j0 += 64) {
+                const int64_t j = j0 + lane;
                 uint32_t code = 0;
-                for (int k = 0; k < 4; ++k) {
-                    const int cl = classify_fast(X, P[k], d2);
-                    code |= (cl < 0 ? kPending : (uint32_t)cl) << (8 * k);
+                int m = 0;
+                if (j < end) {
+                    const float4 lo = box[2 * j], hi = box[2 * j + 1];
+                    bool near = false;
+                    for (int k = 0; k < 4; ++k) near = near || !(box_dist2(lo, hi, P[k]) > far2);
+                    if (near) {
+                        m = (int)cell_tets[j];
+                        double X[12];
+                        for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
+                        for (int k = 0; k < 4; ++k) {
+                            const int cl = classify_fast(X, P[k], d2);
+                            code |= (cl < 0 ? kPending : (uint32_t)cl) << (8 * k);
+                        }
+                    }
                 }
-                const int64_t pos = pos0 + (j - beg);
-                cand_m[pos] = m;
-                cand_code[pos] = code;
+                const bool hit = code != 0u;
+                const uint64_t bal = __ballot(hit);
+                if (hit) {
+                    const int64_t pos = base + n_hit + __popcll(bal & lt);
+                    cand_m[pos] = m;
+                    cand_code[pos] = code;
+                }
+                n_hit += __popcll(bal);
             }
-            pos0 += end - beg;
         }
     }
+    if (lane == 0) cand_n[oi] = n_hit;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -271,8 +322,8 @@ __device__ __forceinline__ void wave_sync() {
 constexpr int kQueue = 320;  // < 64 left over + 4 * 64 appended per chunk
 
 __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
-                                                        double delta, const int64_t* cand_off, const int32_t* cand_m,
-                                                        uint32_t* cand_code) {
+                                                        double delta, const int64_t* cand_off, const int64_t* cand_n,
+                                                        const int32_t* cand_m, uint32_t* cand_code) {
     __shared__ int64_t qp[4][kQueue];
     __shared__ uint8_t qk[4][kQueue];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -293,7 +344,7 @@ __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, cons
         const uint32_t res = (uint32_t)classify_exact(X, P[k], d2);
         atomicAnd(&cand_code[pos], ~(0xFFu << (8 * k)) | (res << (8 * k)));
     };
-    const int64_t src = cand_off[oi], n = cand_off[oi + 1] - src;
+    const int64_t src = cand_off[oi], n = cand_n[oi];
     int nq = 0;
     for (int64_t j = 0; j < n; j += 64) {
         const int64_t pos = src + j + lane;
@@ -338,12 +389,12 @@ __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, cons
 }
 
 // Per outer tet: hits per "number of cut points" bucket (cnt[oi*5 + b]).
-__global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off,
+__global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
                                                     const uint32_t* cand_code, int64_t* cnt) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
-    const int64_t src = cand_off[oi], n = cand_off[oi + 1] - src;
+    const int64_t src = cand_off[oi], n = cand_n[oi];
     int64_t c[5] = {0, 0, 0, 0, 0};
     for (int64_t j = 0; j < n; j += 64) {
         const uint32_t code = (j + lane < n) ? cand_code[src + j + lane] : 0u;
@@ -385,13 +436,13 @@ __device__ __forceinline__ int cut_mask(uint32_t c12) {
 // within a group, to the final pair arrays.  Lanes of a wave then see the same
 // cut points, so the sample loops of a wave are not run for points that only
 // some lanes cut.
-__global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* pair_off,
-                                                      const int32_t* cand_m, const uint32_t* cand_code,
-                                                      int32_t* pair_m, uint16_t* pair_cls) {
+__global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
+                                                      const int64_t* pair_off, const int32_t* cand_m,
+                                                      const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
-    const int64_t src = cand_off[oi], n = cand_off[oi + 1] - src;
+    const int64_t src = cand_off[oi], n = cand_n[oi];
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     int64_t c[16];
 #pragma unroll
@@ -633,24 +684,32 @@ hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64
     return hipGetLastError();
 }
 
-hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
-                           const uint32_t* cell_tets, Grid g, double delta, const int64_t* cand_off, int64_t* cnt,
-                           int32_t* cand_m, uint32_t* cand_code, hipStream_t s) {
-    if (n_outer <= 0) return hipSuccess;
-    k_classify_fast<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, g,
-                                                                  delta, cand_off, cand_m, cand_code);
-    k_classify_exact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, delta, cand_off, cand_m,
-                                                                    cand_code);
-    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_code, cnt);
+hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box,
+                               hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    k_sorted_boxes<<<blocks_for(K), 256, 0, s>>>(tetX, cell_tets, K, box);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* pair_off,
+hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
+                           const uint32_t* cell_tets, const float4* box, Grid g, double delta,
+                           const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, int32_t* cand_m,
+                           uint32_t* cand_code, hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    k_classify_fast<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, box,
+                                                                  g, delta, cand_off, cand_n, cand_m, cand_code);
+    k_classify_exact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, delta, cand_off, cand_n,
+                                                                    cand_m, cand_code);
+    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, cand_code, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n, const int64_t* pair_off,
                                const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls,
                                hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, pair_off, cand_m, cand_code, pair_m,
-                                                                 pair_cls);
+    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, pair_off, cand_m, cand_code,
+                                                                 pair_m, pair_cls);
     return hipGetLastError();
 }
 

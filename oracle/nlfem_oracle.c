@@ -393,12 +393,14 @@ static void cut_geometry(const double X[4][3], const double p[3], double d2, con
         g->subdet[s] = fabs(det3_bary(g->sub[s][0], g->sub[s][1], g->sub[s][2], g->sub[s][3]));
 }
 
-/* lambda in U_I (closed) */
+/* lambda in U_I (closed).  The plane value c . lambda is evaluated with
+ * lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3 substituted:
+ * c_0 + sum_{l=1..3} lambda_l (c_l - c_0), as an FMA chain over l = 1, 2, 3. */
 static int in_UI(const cutgeom *g, const double lam[4]) {
     if (g->n_planes == 0) return 0;
     for (int i = 0; i < g->n_planes; ++i) {
         const double *c = g->plane[i];
-        double h = fma(c[3], lam[3], fma(c[2], lam[2], fma(c[1], lam[1], c[0] * lam[0])));
+        double h = fma(lam[3], c[3] - c[0], fma(lam[2], c[2] - c[0], fma(lam[1], c[1] - c[0], c[0])));
         if (!(h >= 0.0)) return 0;
     }
     return 1;
@@ -450,16 +452,21 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
             fn(user, lam, w, 0);
         }
     }
+    /* sample point relative to p: y - p = (X_0 - p) + sum_{l=1..3} lambda_l (X_l - X_0),
+     * with X_l - X_0 taken as (X_l - p) - (X_0 - p), as an FMA chain over l = 1, 2, 3 */
     double e[4][3];
     for (int l = 0; l < 4; ++l)
         for (int i = 0; i < 3; ++i) e[l][i] = c->X[l][i] - c->p[i];
+    double f[4][3];
+    for (int l = 1; l < 4; ++l)
+        for (int i = 0; i < 3; ++i) f[l][i] = e[l][i] - e[0][i];
     double wmc = c->vol / (double)c->N;
     for (int s = 0; s < c->N; ++s) {
         double lam[4];
         or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, lam);
         double d[3];
         for (int i = 0; i < 3; ++i)
-            d[i] = fma(lam[3], e[3][i], fma(lam[2], e[2][i], fma(lam[1], e[1][i], lam[0] * e[0][i])));
+            d[i] = fma(lam[3], f[3][i], fma(lam[2], f[2][i], fma(lam[1], f[1][i], e[0][i])));
         double rr = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
         if (rr < c->d2 && !in_UI(g, lam)) fn(user, lam, wmc, 1);
     }

@@ -460,11 +460,14 @@ template <typename T>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
     // The sample barycentrics are lambda = L * 2^-21 with integer L (spacings
-    // of 21-bit uniforms).  The loop works with L itself: the relative vertex
-    // coordinates e_l = X_l - p and the plane coefficients are prescaled by
-    // 2^-21 (exact), so every product lambda * e equals L * e' exactly and all
-    // roundings are those of the lambda form.  The sums are scaled back at the
-    // end (exact powers of two).
+    // of 21-bit uniforms).  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3
+    // substituted, the sample point relative to p is
+    //   y - p = (X_0 - p) + sum_{l=1..3} lambda_l ((X_l - p) - (X_0 - p))
+    // and a plane value c . lambda = c_0 + sum_{l=1..3} lambda_l (c_l - c_0),
+    // both as FMA chains over l = 1, 2, 3.  The loop works with L itself: the
+    // differences are prescaled by 2^-21 (exact), so every product L * f'
+    // equals lambda * f exactly and all roundings are those of the lambda
+    // form.  The sums are scaled back at the end (exact powers of two).
     //
     // Sums over the accepted samples are integers: the count and sum L_j
     // (j = 1..3) in 32 bits, sum L_i L_j (1 <= i <= j <= 3) in 64 bits (one
@@ -473,12 +476,14 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
     // partial sum is a multiple of 2^-42 below 2^11).  Both precisions of the
     // local integrals therefore get the same, exact Monte Carlo moments.
     const double u = 1.0 / 2097152.0;
-    double e0x = (X[0] - p[0]) * u, e0y = (X[1] - p[1]) * u, e0z = (X[2] - p[2]) * u;
-    double e1x = (X[3] - p[0]) * u, e1y = (X[4] - p[1]) * u, e1z = (X[5] - p[2]) * u;
-    double e2x = (X[6] - p[0]) * u, e2y = (X[7] - p[1]) * u, e2z = (X[8] - p[2]) * u;
-    double e3x = (X[9] - p[0]) * u, e3y = (X[10] - p[1]) * u, e3z = (X[11] - p[2]) * u;
-    const double p00 = g.c0[0] * u, p01 = g.c0[1] * u, p02 = g.c0[2] * u, p03 = g.c0[3] * u;
-    const double p10 = g.c1[0] * u, p11 = g.c1[1] * u, p12 = g.c1[2] * u, p13 = g.c1[3] * u;
+    const double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
+    const double f1x = ((X[3] - p[0]) - e0x) * u, f1y = ((X[4] - p[1]) - e0y) * u, f1z = ((X[5] - p[2]) - e0z) * u;
+    const double f2x = ((X[6] - p[0]) - e0x) * u, f2y = ((X[7] - p[1]) - e0y) * u, f2z = ((X[8] - p[2]) - e0z) * u;
+    const double f3x = ((X[9] - p[0]) - e0x) * u, f3y = ((X[10] - p[1]) - e0y) * u, f3z = ((X[11] - p[2]) - e0z) * u;
+    const double p00 = g.c0[0], p01 = (g.c0[1] - g.c0[0]) * u, p02 = (g.c0[2] - g.c0[0]) * u,
+                 p03 = (g.c0[3] - g.c0[0]) * u;
+    const double p10 = g.c1[0], p11 = (g.c1[1] - g.c1[0]) * u, p12 = (g.c1[2] - g.c1[0]) * u,
+                 p13 = (g.c1[3] - g.c1[0]) * u;
     constexpr bool kF32 = sizeof(T) == 4;
     uint32_t icnt = 0, ia1 = 0, ia2 = 0, ia3 = 0;
     uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
@@ -490,13 +495,13 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
             if (s + h < N) {
                 uint32_t L[4];
                 lambda_u(w, h, L);
-                double l0 = (double)L[0], l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
-                double dx = fma(l3, e3x, fma(l2, e2x, fma(l1, e1x, l0 * e0x)));
-                double dy = fma(l3, e3y, fma(l2, e2y, fma(l1, e1y, l0 * e0y)));
-                double dz = fma(l3, e3z, fma(l2, e2z, fma(l1, e1z, l0 * e0z)));
+                double l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
+                double dx = fma(l3, f3x, fma(l2, f2x, fma(l1, f1x, e0x)));
+                double dy = fma(l3, f3y, fma(l2, f2y, fma(l1, f1y, e0y)));
+                double dz = fma(l3, f3z, fma(l2, f2z, fma(l1, f1z, e0z)));
                 double rr = fma(dz, dz, fma(dy, dy, dx * dx));
-                double h0 = fma(p03, l3, fma(p02, l2, fma(p01, l1, p00 * l0)));
-                double h1 = fma(p13, l3, fma(p12, l2, fma(p11, l1, p10 * l0)));
+                double h0 = fma(l3, p03, fma(l2, p02, fma(l1, p01, p00)));
+                double h1 = fma(l3, p13, fma(l2, p12, fma(l1, p11, p10)));
                 bool inU = (h0 >= 0.0) && (h1 >= 0.0);
                 bool acc = (rr < d2) && !inU;
                 const uint32_t x1 = acc ? L[1] : 0u, x2 = acc ? L[2] : 0u, x3 = acc ? L[3] : 0u;

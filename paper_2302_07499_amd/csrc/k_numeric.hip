@@ -42,12 +42,19 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t 
 // fine word keeps small contributions (thin cut slivers) relatively exact.
 constexpr int FX_LO_BITS = 48;
 
-__device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long long* lo, double x, double fx) {
+__device__ __forceinline__ void fx_split(double x, double fx, unsigned long long& hi, unsigned long long& lo) {
     const double xs = x * fx;  // exact: fx is a power of two
     const double h = floor(xs);
     const double r = xs - h;   // exact, in [0, 1)
-    atomicAdd(hi, (unsigned long long)h);
-    atomicAdd(lo, (unsigned long long)__double2ull_rn(r * 281474976710656.0));  // r * 2^48
+    hi = (unsigned long long)h;
+    lo = (unsigned long long)__double2ull_rn(r * 281474976710656.0);  // r * 2^48
+}
+
+__device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long long* lo, double x, double fx) {
+    unsigned long long h, l;
+    fx_split(x, fx, h, l);
+    atomicAdd(hi, h);
+    atomicAdd(lo, l);
 }
 
 // carry-normalised: the fine word is reduced below 2^48 first, so both
@@ -69,7 +76,10 @@ __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned 
 
 // One workgroup of BLOCK threads integrates one outer tet.  LDS: R [4][umax]
 // and T0 [4] as two-word fixed-point sums (coarse words, then fine words),
-// Ve [umax], and the 4 outer points.
+// each thread's own T0 words [4][2][BLOCK] (every fold of a wave targets the
+// same T0[k], so the threads sum privately and the block adds the slots up at
+// the end: the same integers, without same-address atomics), Ve [umax], and
+// the 4 outer points.
 template <typename T, int BLOCK>
 __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
@@ -78,16 +88,16 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
     unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax]
     unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
     unsigned long long* T0l = T0 + 4;           // fine   [4]
-    int32_t* ve = (int32_t*)(T0l + 4);
+    unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
+    int32_t* ve = (int32_t*)(T0p + 8 * BLOCK);
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
     const int U = (int)(a.ve_off[oi + 1] - vb);
     const int t = threadIdx.x;
     for (int i = t; i < U; i += BLOCK) ve[i] = a.ve_ids[vb + i];
     for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
+    for (int i = 0; i < 8; ++i) T0p[i * BLOCK + t] = 0ull;
     if (t < 4) {
-        T0[t] = 0ull;
-        T0l[t] = 0ull;
         double Xn[12];
         for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
         outer_point(Xn, t, P[t]);
@@ -113,7 +123,12 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
         int n_in = 0, n_cut = 0;
         // folds S0, S1 of outer point k's moments into T0 and R
         auto fold = [&](int k, const double* S) {
-            fx_add(&T0[k], &T0l[k], fm * S[0], fx);
+            {
+                unsigned long long h, l;
+                fx_split(fm * S[0], fx, h, l);
+                T0p[(2 * k) * BLOCK + t] += h;
+                T0p[(2 * k + 1) * BLOCK + t] += l;
+            }
             for (int j = 0; j < 4; ++j)
                 if (lv[j] < U)  // always true: Ve holds every vertex of the pair list's tets
                     fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
@@ -134,7 +149,12 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
             CutGeom cg;
             double D[5];
             cut_det<T>(X, volm, P[k], d2, cg, D, g);
-            cut_mc<T>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k), (uint32_t)m, S);
+            if (a.caps) {
+                cut_mc<T>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k), (uint32_t)m,
+                          S);
+            } else {
+                for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
+            }
             for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
             fold(k, S);
             for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
@@ -147,6 +167,13 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
             if (n_cut)
                 for (int i = 0; i < 10; ++i) fxs_add_global(&ga[(2 * i) * ks], &ga[(2 * i + 1) * ks], pw * g[i], gfx);
         }
+    }
+    __syncthreads();
+    if (t < 8) {
+        unsigned long long v = 0ull;
+        for (int i = 0; i < BLOCK; ++i) v += T0p[t * BLOCK + i];
+        if (t & 1) T0l[t >> 1] = v;
+        else T0[t >> 1] = v;
     }
     __syncthreads();
     const int sh = a.fx_shift;
@@ -228,7 +255,7 @@ __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_
             out_qm[3 * idx + 2] = c;
             if (c == C_OUT) continue;
             double S[15];
-            pair_moments<T>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
+            pair_moments<T>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1, (uint32_t)(4 * n + k),
                             (uint32_t)m, S);
             for (int i = 0; i < 15; ++i) out_S[15 * idx + i] = S[i];
         }
@@ -271,7 +298,7 @@ inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 
 }  // namespace
 
-size_t integrate_lds_bytes(int umax) { return (size_t)umax * 68 + 64; }
+size_t integrate_lds_bytes(int umax) { return (size_t)umax * 68 + 64 + 8 * 256 * sizeof(unsigned long long); }
 
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;

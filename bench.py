@@ -16,6 +16,10 @@ solve is timed separately.
 Batched: 256 meshes (n ~ U{8..24}, delta/h in {2,3,4}, jitter 0.15h, N = 32,
 FP32-local), one persistent fused integration launch per graph replay.
 
+Strategies: the same workload assembled with the other ball approximations
+(nocaps, overlap, inside, barycenter; FP64), one line each beside the main
+fullcaps value.
+
 Serving: requests (n ~ U{8..40}, delta/h ~ U[2,5], N in {32,64}, FP64 /
 FP32-local 50/50) through the request server: saturation throughput with all
 requests queued at once, then a Poisson stream at 0.9x that rate for the
@@ -101,9 +105,10 @@ def run_precision(P, mg, dev, args):
     m = P.nlfem_mesh(mesh.n_vertices, mesh.n_tets, d_coords.data_ptr(), d_tets.data_ptr(), d_free.data_ptr(),
                      None, 1)
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, strategy="fullcaps"):
         prm = P.nlfem_params(pb.delta, pb.psi, pb.mc_samples, pb.seed,
-                             P.NLFEM_FP32_LOCAL if precision == "fp32" else P.NLFEM_FP64, None)
+                             P.NLFEM_FP32_LOCAL if precision == "fp32" else P.NLFEM_FP64, None,
+                             P.strategy_id(strategy))
         # allocate outputs once (sizes are the same every step)
         plan = P.Plan(dev, P.nlfem_plan_create(dev.ctx, m, prm))
         sysm = plan.alloc_system()
@@ -127,7 +132,7 @@ def run_precision(P, mg, dev, args):
                 plan = P.Plan(dev, h)
             else:
                 P.nlfem_plan_destroy(h)
-            log(f"precision {precision} step {i} {1e3 * (t1 - t0):.1f} ms")
+            log(f"precision {precision} {strategy} step {i} {1e3 * (t1 - t0):.1f} ms")
         return times, np.array(tk), info, plan, sysm
 
     times64, tk64, info, plan64, sys64 = run("fp64", args.steps, args.warmup)
@@ -148,9 +153,21 @@ def run_precision(P, mg, dev, args):
     plan64.destroy()
     plan32.destroy()
     del sys64, sys32, x, x32
+    # the other ball approximation strategies on the same workload (FP64)
+    strategies = None
+    if not args.no_strategies:
+        strategies = {}
+        for st in ["nocaps", "overlap", "inside", "barycenter"]:
+            ts, tks, inf, pl, sm = run("fp64", 2, 1, st)
+            pl.destroy()
+            del sm
+            npairs = int(sum(inf["pair_counts"]))
+            ms = 1e3 * float(np.mean(ts))
+            strategies[st] = {"value": round(npairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
+                              "pairs_per_step": npairs, "integrate_ms": round(float(np.mean(tks[:, 3])), 3)}
     return {"pb": pb, "times64": times64, "tk64": tk64, "times32": times32, "tk32": tk32, "info": info,
             "e32": e32, "sol_err32": sol_err, "cg": {"iters": it, "rel_residual": rr, "converged": bool(ok),
-                                                     "ms": round(cg_ms, 2)}}
+                                                     "ms": round(cg_ms, 2)}, "strategies": strategies}
 
 
 def run_batched(P, mg, dev, args):
@@ -258,6 +275,7 @@ def main():
     ap.add_argument("--serving-count", type=int, default=48)
     ap.add_argument("--serving-full", action="store_true", help="500 requests at 0.5x and 0.9x saturation")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-strategies", action="store_true", help="skip the nocaps/overlap/inside/barycenter lines")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--pool-gb", type=int, default=160)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -370,6 +388,7 @@ def main():
                            "rows": round(float(np.mean(tk64[:, 4])), 3),
                            "assemble": round(float(np.mean(tk64[:, 5])), 3)},
         "cg": pr["cg"],
+        "strategies_fp64": pr["strategies"],
         "batched": batched,
         "serving": serving,
         "roofline": roofline,

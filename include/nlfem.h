@@ -38,7 +38,7 @@ typedef struct nlfem_plan nlfem_plan;
 
 typedef enum {
     NLFEM_OK = 0,
-    NLFEM_E_INVALID_ARG = 1,   /* null required pointer, delta <= 0, N outside [1, 2047], negative size */
+    NLFEM_E_INVALID_ARG = 1,   /* null pointer, delta <= 0, N outside [1, 2047], unknown strategy, negative size */
     NLFEM_E_MESH = 2,          /* index out of range, zero-volume tet, free vertex in a T_OmegaI tet */
     NLFEM_E_OOM = 3,           /* allocation failed or would exceed the context's HBM budget  */
     NLFEM_E_DEVICE = 4,        /* a HIP runtime call failed                                  */
@@ -51,6 +51,17 @@ typedef enum {
     NLFEM_FP32_LOCAL = 1  /* per-pair subtet rule in float; classification, sample acceptance,
                              the (exact, integer) sample sums and all global sums as in FP64  */
 } nlfem_precision;
+
+/* Ball approximation strategy (Sec. 4.1: which elements, or element pieces,
+ * make up the approximate ball B_delta,h(x) of an outer point x).           */
+typedef enum {
+    NLFEM_FULLCAPS = 0,   /* inside elements whole, T_I of the cut ones (subdivision of conv(I u P)),
+                             and the fullcaps (E - U_I) n B by Monte Carlo (Sec. 4.2.2); default  */
+    NLFEM_NOCAPS = 1,     /* inside elements and T_I only (Def. nocaps); no Monte Carlo          */
+    NLFEM_OVERLAP = 2,    /* every element that meets the ball, whole                           */
+    NLFEM_INSIDE = 3,     /* only the elements with all vertices inside the ball, whole          */
+    NLFEM_BARYCENTER = 4  /* the elements whose barycenter ((X0+X1)+(X2+X3))/4 lies in the ball  */
+} nlfem_strategy;
 
 /* Tetrahedral mesh of Omega u Omega_I (Sec. 3.1: coinciding triangulations of
  * Omega and Omega_I; P1 nodes on the boundary of Omega and in Omega_I carry the
@@ -75,6 +86,7 @@ typedef struct {
     int32_t precision;           /* nlfem_precision                                                   */
     const uint8_t *outer_mask;   /* optional [n_tets], same memory kind as the mesh: 1 = use this tet
                                     as an outer element (subset runs); NULL = all T_Omega tets        */
+    int32_t strategy;            /* nlfem_strategy (0 = fullcaps)                                     */
 } nlfem_params;
 
 /* ---- context ------------------------------------------------------------ */

@@ -139,6 +139,7 @@ class Problem:
     g_nodal: np.ndarray
     precision: str = "fp64"     # "fp64" or "fp32"
     info: dict = field(default_factory=dict)
+    strategy: str = "fullcaps"  # ball approximation: fullcaps, nocaps, overlap, inside, barycenter
 
 
 def make_problem(name: str, n: int, delta_over_h: float | None = None, delta: float | None = None,

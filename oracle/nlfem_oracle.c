@@ -232,6 +232,44 @@ static int classify(const double X[4][3], const double p[3], double d2, double r
     return tet_meets_ball_no_vertex_inside(X, p, d2) ? OR_CUT0 : OR_OUT;
 }
 
+/* Ball approximation strategies (Sec. 4.1: the approximate ball B_delta,h(p)
+ * as a set of whole elements or element pieces):
+ *   FULLCAPS   elements inside, T_I of the cut ones, and the fullcaps by
+ *              Monte Carlo (Sec. 4.2.2; the default);
+ *   NOCAPS     elements inside and T_I of the cut ones (Def. nocaps): the
+ *              fullcaps dropped, CUT(0) elements contribute nothing;
+ *   OVERLAP    every element that meets the ball, whole;
+ *   INSIDE     only the elements wholly inside the ball, whole;
+ *   BARYCENTER the elements whose barycenter lies in the ball, whole.
+ * The last three map a pair to IN (whole element, 4-point rule) or OUT.    */
+#define OR_FULLCAPS 0
+#define OR_NOCAPS 1
+#define OR_OVERLAP 2
+#define OR_INSIDE 3
+#define OR_BARYCENTER 4
+
+/* barycenter c = ((X_0 + X_1) + (X_2 + X_3)) / 4 in the open ball */
+static int barycenter_inside(const double X[4][3], const double p[3], double d2) {
+    double r2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double c = ((X[0][i] + X[1][i]) + (X[2][i] + X[3][i])) * 0.25;
+        double d = c - p[i];
+        r2 = (i == 0) ? d * d : r2 + d * d;
+    }
+    return r2 < d2;
+}
+
+/* class of a pair under a strategy, from its fullcaps class */
+static int strategy_class(int cls, const double X[4][3], const double p[3], double d2, int strategy) {
+    switch (strategy) {
+    case OR_NOCAPS: return cls == OR_CUT0 ? OR_OUT : cls;
+    case OR_OVERLAP: return cls == OR_OUT ? OR_OUT : OR_IN;
+    case OR_INSIDE: return cls == OR_IN ? OR_IN : OR_OUT;
+    case OR_BARYCENTER: return barycenter_inside(X, p, d2) ? OR_IN : OR_OUT;
+    default: return cls;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Cut-tet geometry in barycentric (lambda) space of the inner tet.          */
 typedef struct {
@@ -424,6 +462,7 @@ typedef struct {
     double r2[4];
     cutgeom g;
     int N;
+    int caps; /* 1: the fullcaps Monte Carlo term is part of the pair */
     uint64_t seed;
     uint32_t q, m;
 } pairctx;
@@ -454,6 +493,7 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
     }
     /* sample point relative to p: y - p = (X_0 - p) + sum_{l=1..3} lambda_l (X_l - X_0),
      * with X_l - X_0 taken as (X_l - p) - (X_0 - p), as an FMA chain over l = 1, 2, 3 */
+    if (!c->caps) return;
     double e[4][3];
     for (int l = 0; l < 4; ++l)
         for (int i = 0; i < 3; ++i) e[l][i] = c->X[l][i] - c->p[i];
@@ -499,7 +539,7 @@ static void mom_node(void *user, const double lam[4], double w, int is_mc) {
 }
 
 static void pair_setup(pairctx *c, const double X[4][3], const double p[3], double delta, int N,
-                       uint64_t seed, uint32_t q, uint32_t m) {
+                       uint64_t seed, uint32_t q, uint32_t m, int strategy) {
     c->X = X;
     for (int i = 0; i < 3; ++i) c->p[i] = p[i];
     c->d2 = delta * delta;
@@ -508,7 +548,8 @@ static void pair_setup(pairctx *c, const double X[4][3], const double p[3], doub
     c->seed = seed;
     c->q = q;
     c->m = m;
-    c->cls = classify(X, p, c->d2, c->r2);
+    c->cls = strategy_class(classify(X, p, c->d2, c->r2), X, p, c->d2, strategy);
+    c->caps = strategy == OR_FULLCAPS;
     if (c->cls >= OR_CUT0) cut_geometry(X, p, c->d2, c->r2, &c->g);
 }
 
@@ -516,7 +557,7 @@ static void pair_moments(const pairctx *c, double S[15]) {
     momacc a;
     memset(&a, 0, sizeof a);
     visit_nodes(c, mom_node, &a);
-    double sc = c->vol / (double)c->N;
+    double sc = c->caps ? c->vol / (double)c->N : 0.0;
     for (int k = 0; k < 15; ++k) S[k] = a.det[k] + sc * a.mc[k];
 }
 
@@ -557,14 +598,14 @@ void or_classify_point(const double *coords, const int32_t *tets, int64_t n_tets
 
 /* moments of pair (outer point q = 4 n + k, inner tet m); returns the class */
 int or_pair_moments(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m,
-                    double delta, int N, uint64_t seed, double S[15]) {
+                    double delta, int N, uint64_t seed, int strategy, double S[15]) {
     double Xn[4][3], Xm[4][3], p[3];
     rule_init();
     load_tet(coords, tets, n, Xn);
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m);
+    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m, strategy);
     for (int i = 0; i < 15; ++i) S[i] = 0.0;
     if (c.cls != OR_OUT) pair_moments(&c, S);
     return c.cls;
@@ -572,9 +613,10 @@ int or_pair_moments(const double *coords, const int32_t *tets, int64_t n, int k,
 
 /* all pairs of one outer point against every tet: class + moments */
 void or_point_moments(const double *coords, const int32_t *tets, int64_t n_tets, int64_t n, int k,
-                      double delta, int N, uint64_t seed, int8_t *cls, double *S /*[n_tets][15]*/) {
+                      double delta, int N, uint64_t seed, int strategy, int8_t *cls,
+                      double *S /*[n_tets][15]*/) {
     for (int64_t m = 0; m < n_tets; ++m)
-        cls[m] = (int8_t)or_pair_moments(coords, tets, n, k, m, delta, N, seed, S + 15 * m);
+        cls[m] = (int8_t)or_pair_moments(coords, tets, n, k, m, delta, N, seed, strategy, S + 15 * m);
 }
 
 /* cut geometry of a pair, for geometric pins: returns n_in (or -1 if not CUT) */
@@ -587,7 +629,7 @@ int or_pair_geometry(const double *coords, const int32_t *tets, int64_t n, int k
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, 1, 0, 0, 0);
+    pair_setup(&c, Xm, p, delta, 1, 0, 0, 0, OR_FULLCAPS);
     if (c.cls < OR_CUT0) return -1;
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) t_out[4 * a + b] = c.g.t[a][b];
@@ -617,6 +659,7 @@ typedef struct {
     const uint8_t *outer_mask; /* optional */
     const double *f_qp;        /* optional [n_tets][4] */
     const double *g_nodal;     /* optional [n_vertices] */
+    int32_t strategy;          /* OR_FULLCAPS .. OR_BARYCENTER */
 } or_problem;
 
 typedef struct {
@@ -711,6 +754,7 @@ static void local_node(void *user, const double lam[4], double w, int is_mc) {
 static int validate(const or_problem *P) {
     if (!P || P->n_vertices < 0 || P->n_tets < 0) return 1;
     if (!(P->delta > 0.0) || P->mc_samples < 1) return 1;
+    if (P->strategy < OR_FULLCAPS || P->strategy > OR_BARYCENTER) return 1;
     if (P->n_tets > 0 && (!P->coords || !P->tets || !P->vertex_free)) return 1;
     for (int64_t i = 0; i < 4 * P->n_tets; ++i)
         if (P->tets[i] < 0 || P->tets[i] >= P->n_vertices) return 2;
@@ -785,10 +829,11 @@ int or_assemble(const or_problem *P, or_system *S) {
                 c.X = Xm;
                 for (int i = 0; i < 3; ++i) c.p[i] = p[i];
                 c.d2 = d2;
-                c.cls = classify(Xm, p, d2, c.r2);
+                c.cls = strategy_class(classify(Xm, p, d2, c.r2), Xm, p, d2, P->strategy);
                 if (c.cls == OR_OUT) continue;
                 c.vol = tet_volume(Xm);
                 c.N = P->mc_samples;
+                c.caps = P->strategy == OR_FULLCAPS;
                 c.seed = P->seed;
                 c.q = (uint32_t)(4 * n + k);
                 c.m = (uint32_t)m;

@@ -27,6 +27,16 @@ NLFEM_E_UNSUPPORTED = 6
 NLFEM_FP64 = 0
 NLFEM_FP32_LOCAL = 1
 NLFEM_MAX_MC_SAMPLES = 2047  # sample sums stay exact 32/64-bit integers
+# ball approximation strategies (nlfem_strategy)
+STRATEGIES = {"fullcaps": 0, "nocaps": 1, "overlap": 2, "inside": 3, "barycenter": 4}
+
+
+def strategy_id(st):
+    if isinstance(st, str):
+        if st not in STRATEGIES:
+            raise ValueError(f"unknown strategy {st!r}")
+        return STRATEGIES[st]
+    return int(st)
 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_MESH", 3: "E_OOM", 4: "E_DEVICE",
                 5: "E_NOT_CONVERGED", 6: "E_UNSUPPORTED"}
@@ -40,7 +50,8 @@ class nlfem_mesh(C.Structure):
 
 class nlfem_params(C.Structure):
     _fields_ = [("delta", C.c_double), ("psi", C.c_double), ("mc_samples", C.c_int32),
-                ("seed", C.c_uint64), ("precision", C.c_int32), ("outer_mask", C.c_void_p)]
+                ("seed", C.c_uint64), ("precision", C.c_int32), ("outer_mask", C.c_void_p),
+                ("strategy", C.c_int32)]
 
 
 class nlfem_pair_record(C.Structure):
@@ -297,19 +308,20 @@ class Device:
         return m, keep
 
     def plan(self, coords, tets, vertex_free, delta, psi, mc_samples, seed, precision="fp64", tet_region=None,
-             outer_mask=None):
+             outer_mask=None, strategy="fullcaps"):
         m, keep = self.mesh(coords, tets, vertex_free, tet_region)
         om = None if outer_mask is None else self.to_dev(outer_mask, self.torch.uint8)
         prm = nlfem_params(float(delta), float(psi), int(mc_samples), int(seed),
                            NLFEM_FP32_LOCAL if precision == "fp32" else NLFEM_FP64,
-                           None if om is None else om.data_ptr())
+                           None if om is None else om.data_ptr(), strategy_id(strategy))
         plan = nlfem_plan_create(self.ctx, m, prm)
         return Plan(self, plan)
 
     def plan_problem(self, pb, outer_mask=None):
         mm = pb.mesh
         return self.plan(mm.coords, mm.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
-                         precision=pb.precision, outer_mask=outer_mask)
+                         precision=pb.precision, outer_mask=outer_mask,
+                         strategy=getattr(pb, "strategy", "fullcaps"))
 
 
 class Plan:
@@ -384,7 +396,8 @@ class Batch:
             meshes[i] = m
             params[i] = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
                                      NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
-                                     None if om is None else om.data_ptr())
+                                     None if om is None else om.data_ptr(),
+                                     strategy_id(getattr(pb, "strategy", "fullcaps")))
         h = C.c_void_p()
         _check(load().nlfem_batch_create(dev.ctx, self.n, meshes, params, C.byref(h)), dev.ctx)
         self.handle = h
@@ -474,7 +487,7 @@ class Server:
                        None, 0)
         prm = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
                            NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
-                           None if om is None else om.ctypes.data)
+                           None if om is None else om.ctypes.data, strategy_id(getattr(pb, "strategy", "fullcaps")))
         sp = nlfem_solve_params(rtol, max_iter)
         t = C.c_uint64()
         self._err(load().nlfem_server_submit(self.handle, C.byref(m), C.byref(prm),

@@ -44,7 +44,7 @@ struct nlfem_plan {
     int umax = 0, max_row = 0, fx_shift = 0, g_shift = 0, w_shift = 0, row_shift = 0;
     int64_t pair_counts[5] = {0, 0, 0, 0, 0};
     double delta = 0, psi = 0;
-    int mc = 1, precision = 0;
+    int mc = 1, precision = 0, strategy = 0;
     uint64_t seed = 0;
     // device arrays: mesh and ball query
     double *tetX = nullptr, *vol = nullptr;
@@ -270,7 +270,7 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     TMP(t_box, (size_t)(K + 1) * 32);
     HIPCHK(launch_sorted_boxes(pl->tetX, cell_tets, K, (float4*)t_box.p, s));
     HIPCHK(launch_classify(pl->tetX, pl->outer_ids, no, cell_start, cell_tets, (const float4*)t_box.p, g, prm->delta,
-                           t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), t_cnt.as<int64_t>(),
+                           prm->strategy, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), t_cnt.as<int64_t>(),
                            t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), s));
     HIPCHK(launch_pair_totals(t_cnt.as<int64_t>(), no, t_tot.as<int64_t>(), s));
     HIPCHK(exclusive_scan_i64(t_tot.as<int64_t>(), pl->pair_off, no, t_scan2.p, s));
@@ -284,7 +284,7 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
         return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^15 interacting tets for one outer tet");
     ALLOC(pl->pair_m, int32_t, P + 1);
     ALLOC(pl->pair_cls, uint16_t, P + 1);
-    HIPCHK(launch_pair_compact(no, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), pl->pair_off,
+    HIPCHK(launch_pair_compact(no, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), pl->pair_off, prm->strategy,
                                t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), pl->pair_m, pl->pair_cls, s));
     {
         TMP(t_cc, 64);
@@ -489,6 +489,7 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.delta = pl->delta;
     a.psi = pl->psi;
     a.mc_samples = pl->mc;
+    a.caps = pl->strategy == NLFEM_FULLCAPS ? 1 : 0;
     a.key0 = (uint32_t)(pl->seed & 0xFFFFFFFFull);
     a.key1 = (uint32_t)(pl->seed >> 32);
     a.fx_shift = pl->fx_shift;
@@ -712,6 +713,8 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
         return fail(c, NLFEM_E_INVALID_ARG, "mc_samples must be in [1, " + std::to_string(NLFEM_MAX_MC_SAMPLES) + "]");
     if (prm->precision != NLFEM_FP64 && prm->precision != NLFEM_FP32_LOCAL)
         return fail(c, NLFEM_E_INVALID_ARG, "unknown precision");
+    if (prm->strategy < NLFEM_FULLCAPS || prm->strategy > NLFEM_BARYCENTER)
+        return fail(c, NLFEM_E_INVALID_ARG, "unknown ball approximation strategy");
     if (mesh->n_tets >= (int64_t)1 << 31 || mesh->n_vertices >= (int64_t)1 << 31)
         return fail(c, NLFEM_E_UNSUPPORTED, "mesh larger than 2^31 entities");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
@@ -722,6 +725,7 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
     pl->mc = prm->mc_samples;
     pl->seed = prm->seed;
     pl->precision = prm->precision;
+    pl->strategy = prm->strategy;
     nlfem_status st = build_plan(c, pl, mesh, prm);
     if (st != NLFEM_OK) {
         hipStreamSynchronize(c->stream);

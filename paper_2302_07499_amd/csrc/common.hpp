@@ -11,6 +11,8 @@ namespace nlfem {
 
 // pair class codes (3 bits per outer point in the packed per-pair word)
 enum : int { C_OUT = 0, C_IN = 1, C_CUT0 = 2 };
+// ball approximation strategies (nlfem_strategy)
+enum : int { S_FULLCAPS = 0, S_NOCAPS = 1, S_OVERLAP = 2, S_INSIDE = 3, S_BARYCENTER = 4 };
 
 // 4-point degree-2 rule: node r has barycentric alpha on vertex r, beta on
 // the others; alpha = (5 + 3 sqrt 5) / 20, beta = (5 - sqrt 5) / 20 rounded
@@ -74,12 +76,12 @@ hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64
 hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box,
                                hipStream_t s);
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
-                           const uint32_t* cell_tets, const float4* box, Grid g, double delta,
+                           const uint32_t* cell_tets, const float4* box, Grid g, double delta, int strategy,
                            const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, int32_t* cand_m,
                            uint32_t* cand_code, hipStream_t s);
 hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n, const int64_t* pair_off,
-                               const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls,
-                               hipStream_t s);
+                               int strategy, const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m,
+                               uint16_t* pair_cls, hipStream_t s);
 hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s);
 // local vertex sets Ve of the outer tets: count pass writes ucount[oi], fill
 // pass writes the sorted sets at ve_off
@@ -103,6 +105,7 @@ struct IntegrateArgs {
     const double* f_qp;  // may be null
     double delta, psi;
     int mc_samples;
+    int caps;  // 1: cut points add the fullcaps Monte Carlo term (strategy fullcaps)
     uint32_t key0, key1;
     int fx_shift;  // scale 2^fx_shift of the LDS sums T0 and R
     int g_shift;   // scale of the cut part of G_m (global accumulators)

@@ -153,6 +153,19 @@ __device__ inline int classify_fast(const double* X, const double* p, double d2)
     return -1;
 }
 
+// Barycenter ((X0 + X1) + (X2 + X3)) / 4 in the open ball (strategy
+// barycenter, Sec. 4.1).
+__device__ inline bool barycenter_inside(const double* X, const double* p, double d2) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double c = ((X[i] + X[3 + i]) + (X[6 + i] + X[9 + i])) * 0.25;
+        const double d = c - p[i];
+        r2 = (i == 0) ? d * d : r2 + d * d;
+    }
+    return r2 < d2;
+}
+
 // Exact part for a tet with no vertex inside the open ball.
 __device__ inline int classify_exact(const double* X, const double* p, double d2) {
     if (separated(X, p, d2 * (1.0 + 1e-9))) return C_OUT;
@@ -548,7 +561,7 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
 // whole-pair moments (the sum of the pieces), as the oracle reports them
 template <typename T>
 __device__ inline void pair_moments(const double* X, double vol, const double* p, double d2, int code, int N,
-                                    uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
+                                    bool caps, uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
     if (code == C_IN) {
         in_moments(vol, S);
         return;
@@ -558,7 +571,12 @@ __device__ inline void pair_moments(const double* X, double vol, const double* p
 #pragma unroll
     for (int i = 0; i < 10; ++i) G[i] = 0.0;
     cut_det<T>(X, vol, p, d2, g, D, G);
-    cut_mc<T>(X, vol, p, d2, g, N, key0, key1, q, m, S);
+    if (caps) {
+        cut_mc<T>(X, vol, p, d2, g, N, key0, key1, q, m, S);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 15; ++i) S[i] = 0.0;
+    }
 #pragma unroll
     for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
 #pragma unroll

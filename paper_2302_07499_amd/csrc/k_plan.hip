@@ -250,7 +250,7 @@ constexpr uint32_t kPending = 0xFFu;
 
 __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                                                        const int64_t* cell_start, const uint32_t* cell_tets,
-                                                       const float4* box, Grid g, double delta,
+                                                       const float4* box, Grid g, double delta, int strategy,
                                                        const int64_t* cand_off, int64_t* cand_n, int32_t* cand_m,
                                                        uint32_t* cand_code) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -290,7 +290,14 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
                         double X[12];
                         for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
                         for (int k = 0; k < 4; ++k) {
-                            const int cl = classify_fast(X, P[k], d2);
+                            int cl;
+                            if (strategy == S_BARYCENTER) {
+                                cl = barycenter_inside(X, P[k], d2) ? C_IN : C_OUT;
+                            } else {
+                                cl = classify_fast(X, P[k], d2);
+                                // inside: only whole-inside elements; nothing is left pending
+                                if (strategy == S_INSIDE && cl != C_IN) cl = C_OUT;
+                            }
                             code |= (cl < 0 ? kPending : (uint32_t)cl) << (8 * k);
                         }
                     }
@@ -388,16 +395,33 @@ __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, cons
     if (lane < nq) run(lane);
 }
 
+// Class bytes of a candidate under a strategy, from the fullcaps classes
+// (barycenter and inside are already final from the fast pass): nocaps
+// drops CUT(0) (no T_I, no caps), overlap takes every element that meets
+// the ball whole.
+__device__ __forceinline__ uint32_t strategy_code(uint32_t code, int strategy) {
+    if (strategy != S_NOCAPS && strategy != S_OVERLAP) return code;
+    uint32_t out = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t cl = (code >> (8 * k)) & 0xFFu;
+        if (strategy == S_NOCAPS) cl = cl == (uint32_t)C_CUT0 ? (uint32_t)C_OUT : cl;
+        else cl = cl == (uint32_t)C_OUT ? (uint32_t)C_OUT : (uint32_t)C_IN;
+        out |= cl << (8 * k);
+    }
+    return out;
+}
+
 // Per outer tet: hits per "number of cut points" bucket (cnt[oi*5 + b]).
 __global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
-                                                    const uint32_t* cand_code, int64_t* cnt) {
+                                                    int strategy, const uint32_t* cand_code, int64_t* cnt) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
     const int64_t src = cand_off[oi], n = cand_n[oi];
     int64_t c[5] = {0, 0, 0, 0, 0};
     for (int64_t j = 0; j < n; j += 64) {
-        const uint32_t code = (j + lane < n) ? cand_code[src + j + lane] : 0u;
+        const uint32_t code = (j + lane < n) ? strategy_code(cand_code[src + j + lane], strategy) : 0u;
         int ncut = 0;
         bool hit = false;
         for (int k = 0; k < 4; ++k) {
@@ -437,7 +461,7 @@ __device__ __forceinline__ int cut_mask(uint32_t c12) {
 // cut points, so the sample loops of a wave are not run for points that only
 // some lanes cut.
 __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
-                                                      const int64_t* pair_off, const int32_t* cand_m,
+                                                      const int64_t* pair_off, int strategy, const int32_t* cand_m,
                                                       const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
@@ -449,7 +473,7 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     for (int b = 0; b < 16; ++b) c[b] = 0;
     for (int64_t j = 0; j < n; j += 64) {
         const bool valid = j + lane < n;
-        const uint32_t cc = valid ? code12(cand_code[src + j + lane]) : 0u;
+        const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
         const int mk = cc ? cut_mask(cc) : -1;
 #pragma unroll
         for (int b = 0; b < 16; ++b) c[b] += __popcll(__ballot(mk == b));
@@ -467,7 +491,7 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     for (int b = 0; b < 16; ++b) c[b] = 0;
     for (int64_t j = 0; j < n; j += 64) {
         const bool valid = j + lane < n;
-        const uint32_t cc = valid ? code12(cand_code[src + j + lane]) : 0u;
+        const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
         const int mk = cc ? cut_mask(cc) : -1;
         const int m = mk >= 0 ? cand_m[src + j + lane] : 0;
 #pragma unroll
@@ -692,24 +716,25 @@ hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, in
 }
 
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
-                           const uint32_t* cell_tets, const float4* box, Grid g, double delta,
+                           const uint32_t* cell_tets, const float4* box, Grid g, double delta, int strategy,
                            const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, int32_t* cand_m,
                            uint32_t* cand_code, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
     k_classify_fast<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, box,
-                                                                  g, delta, cand_off, cand_n, cand_m, cand_code);
+                                                                  g, delta, strategy, cand_off, cand_n, cand_m,
+                                                                  cand_code);
     k_classify_exact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, delta, cand_off, cand_n,
                                                                     cand_m, cand_code);
-    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, cand_code, cnt);
+    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, strategy, cand_code, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n, const int64_t* pair_off,
-                               const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls,
-                               hipStream_t s) {
+                               int strategy, const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m,
+                               uint16_t* pair_cls, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, pair_off, cand_m, cand_code,
-                                                                 pair_m, pair_cls);
+    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, pair_off, strategy, cand_m,
+                                                                 cand_code, pair_m, pair_cls);
     return hipGetLastError();
 }
 

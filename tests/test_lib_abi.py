@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "nlfem.h")
 
 
 def _declared():
-    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)  # declarations only, not comments
     return sorted(set(re.findall(r"\b(nlfem_[a-z_]+)\s*\(", txt)))
 
 

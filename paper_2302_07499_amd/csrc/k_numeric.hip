@@ -279,19 +279,25 @@ __global__ void k_copy_i32(const int32_t* a, int32_t* b, int64_t n) {
     if (i < n) b[i] = a[i];
 }
 
+// point-pair totals per class (counts[1..5] = IN, CUT(0..3)): counted in
+// registers, summed across the wave, one atomic per class and wave
 __global__ void k_class_counts(const uint16_t* pair_cls, int64_t P, unsigned long long* counts) {
-    __shared__ unsigned long long c[6];
-    if (threadIdx.x < 6) c[threadIdx.x] = 0ull;
-    __syncthreads();
+    unsigned c[5] = {0u, 0u, 0u, 0u, 0u};
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t code = pair_cls[p];
+        const uint32_t code = pair_cls[p];
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-            unsigned cl = (code >> (3 * k)) & 7u;
-            if (cl != 0u) atomicAdd(&c[cl], 1ull);
+            const unsigned cl = (code >> (3 * k)) & 7u;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) c[q] += (cl == (unsigned)(q + 1)) ? 1u : 0u;
         }
     }
-    __syncthreads();
-    if (threadIdx.x < 6) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        for (int off = 32; off > 0; off >>= 1) c[q] += __shfl_xor(c[q], off, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 5; ++q)
+            if (c[q]) atomicAdd(&counts[1 + q], (unsigned long long)c[q]);
 }
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }

@@ -18,7 +18,8 @@ FP32-local), one persistent fused integration launch per graph replay.
 
 Strategies: the same workload assembled with the other ball approximations
 (nocaps, overlap, inside, barycenter; FP64), one line each beside the main
-fullcaps value.
+fullcaps value, and fullcaps with the n_in = 3 caps sampled on the corner tet
+E - U_I, with the seed-to-seed spread of the matrix entries in both modes.
 
 Serving: requests (n ~ U{8..40}, delta/h ~ U[2,5], N in {32,64}, FP64 /
 FP32-local 50/50) through the request server: saturation throughput with all
@@ -105,10 +106,10 @@ def run_precision(P, mg, dev, args):
     m = P.nlfem_mesh(mesh.n_vertices, mesh.n_tets, d_coords.data_ptr(), d_tets.data_ptr(), d_free.data_ptr(),
                      None, 1)
 
-    def run(precision, steps, warmup, strategy="fullcaps"):
-        prm = P.nlfem_params(pb.delta, pb.psi, pb.mc_samples, pb.seed,
+    def run(precision, steps, warmup, strategy="fullcaps", cap_sampling="whole", seed=None):
+        prm = P.nlfem_params(pb.delta, pb.psi, pb.mc_samples, pb.seed if seed is None else seed,
                              P.NLFEM_FP32_LOCAL if precision == "fp32" else P.NLFEM_FP64, None,
-                             P.strategy_id(strategy))
+                             P.strategy_id(strategy), P.cap_sampling_id(cap_sampling))
         # allocate outputs once (sizes are the same every step)
         plan = P.Plan(dev, P.nlfem_plan_create(dev.ctx, m, prm))
         sysm = plan.alloc_system()
@@ -165,6 +166,28 @@ def run_precision(P, mg, dev, args):
             ms = 1e3 * float(np.mean(ts))
             strategies[st] = {"value": round(npairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
                               "pairs_per_step": npairs, "integrate_ms": round(float(np.mean(tks[:, 3])), 3)}
+        # fullcaps with the n_in = 3 caps sampled on the corner tet E - U_I, and the
+        # seed-to-seed spread of the matrix entries in both sampling modes
+        ts, tks, inf, pl, sm = run("fp64", 2, 1, "fullcaps", "outside_ui")
+        pl.destroy()
+        del sm
+        npairs = int(sum(inf["pair_counts"]))
+        ms = 1e3 * float(np.mean(ts))
+        spread = {}
+        for mode in ["whole", "outside_ui"]:
+            vals = []
+            for seed in range(3):
+                _, _, _, pl, sm = run("fp64", 1, 0, "fullcaps", mode, seed=seed)
+                vals.append(P.system_to_numpy(sm)["ff_val"])
+                pl.destroy()
+                del sm
+            v = np.array(vals)
+            spread[mode] = float(np.median(v.std(axis=0) / np.maximum(np.abs(v.mean(axis=0)), 1e-300)))
+        strategies["fullcaps_outside_ui"] = {
+            "value": round(npairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
+            "pairs_per_step": npairs, "integrate_ms": round(float(np.mean(tks[:, 3])), 3),
+            "entry_seed_spread_median": {k: round(x, 8) for k, x in spread.items()},
+            "spread_ratio": round(spread["outside_ui"] / max(spread["whole"], 1e-300), 4)}
     return {"pb": pb, "times64": times64, "tk64": tk64, "times32": times32, "tk32": tk32, "info": info,
             "e32": e32, "sol_err32": sol_err, "cg": {"iters": it, "rel_residual": rr, "converged": bool(ok),
                                                      "ms": round(cg_ms, 2)}, "strategies": strategies}

@@ -38,7 +38,8 @@ typedef struct nlfem_plan nlfem_plan;
 
 typedef enum {
     NLFEM_OK = 0,
-    NLFEM_E_INVALID_ARG = 1,   /* null pointer, delta <= 0, N outside [1, 2047], unknown strategy, negative size */
+    NLFEM_E_INVALID_ARG = 1,   /* null pointer, delta <= 0, N outside [1, 2047], unknown strategy or
+                                  cap sampling, negative size                                    */
     NLFEM_E_MESH = 2,          /* index out of range, zero-volume tet, free vertex in a T_OmegaI tet */
     NLFEM_E_OOM = 3,           /* allocation failed or would exceed the context's HBM budget  */
     NLFEM_E_DEVICE = 4,        /* a HIP runtime call failed                                  */
@@ -62,6 +63,14 @@ typedef enum {
     NLFEM_INSIDE = 3,     /* only the elements with all vertices inside the ball, whole          */
     NLFEM_BARYCENTER = 4  /* the elements whose barycenter ((X0+X1)+(X2+X3))/4 lies in the ball  */
 } nlfem_strategy;
+
+/* Where the fullcaps Monte Carlo samples are drawn (strategy fullcaps only).  */
+typedef enum {
+    NLFEM_CAPS_WHOLE_ELEMENT = 0, /* uniform on E_m, rejecting U_I (default)                        */
+    NLFEM_CAPS_OUTSIDE_UI = 1     /* uniform on E_m minus U_I where that is one tet (n_in = 3: the
+                                     corner at the outside vertex); same expectation, every sample
+                                     in the cap region; other cases as the default                */
+} nlfem_cap_sampling;
 
 /* Tetrahedral mesh of Omega u Omega_I (Sec. 3.1: coinciding triangulations of
  * Omega and Omega_I; P1 nodes on the boundary of Omega and in Omega_I carry the
@@ -87,6 +96,7 @@ typedef struct {
     const uint8_t *outer_mask;   /* optional [n_tets], same memory kind as the mesh: 1 = use this tet
                                     as an outer element (subset runs); NULL = all T_Omega tets        */
     int32_t strategy;            /* nlfem_strategy (0 = fullcaps)                                     */
+    int32_t cap_sampling;        /* nlfem_cap_sampling (0 = whole element)                            */
 } nlfem_params;
 
 /* ---- context ------------------------------------------------------------ */

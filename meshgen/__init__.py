@@ -140,6 +140,7 @@ class Problem:
     precision: str = "fp64"     # "fp64" or "fp32"
     info: dict = field(default_factory=dict)
     strategy: str = "fullcaps"  # ball approximation: fullcaps, nocaps, overlap, inside, barycenter
+    cap_sampling: str = "whole"  # cap samples on the whole element, or on E_m minus U_I ("outside_ui")
 
 
 def make_problem(name: str, n: int, delta_over_h: float | None = None, delta: float | None = None,

@@ -34,7 +34,8 @@ class OrProblem(C.Structure):
                 ("coords", C.c_void_p), ("tets", C.c_void_p), ("vertex_free", C.c_void_p),
                 ("tet_region", C.c_void_p), ("delta", C.c_double), ("psi", C.c_double),
                 ("mc_samples", C.c_int32), ("seed", C.c_uint64), ("outer_mask", C.c_void_p),
-                ("f_qp", C.c_void_p), ("g_nodal", C.c_void_p), ("strategy", C.c_int32)]
+                ("f_qp", C.c_void_p), ("g_nodal", C.c_void_p), ("strategy", C.c_int32),
+                ("cap_sampling", C.c_int32)]
 
 
 # ball approximation strategies (Sec. 4.1), as numbered in the oracle
@@ -43,6 +44,13 @@ STRATEGIES = {"fullcaps": 0, "nocaps": 1, "overlap": 2, "inside": 3, "barycenter
 
 def _strategy(st):
     return STRATEGIES[st] if isinstance(st, str) else int(st)
+
+
+CAP_SAMPLING = {"whole": 0, "outside_ui": 1}
+
+
+def _caps(cs):
+    return CAP_SAMPLING[cs] if isinstance(cs, str) else int(cs)
 
 
 class OrSystem(C.Structure):
@@ -68,10 +76,10 @@ def lib():
         L.or_outer_point.argtypes = [P, P, C.c_int64, C.c_int, P]
         L.or_classify_point.argtypes = [P, P, C.c_int64, C.c_double, P, P]
         L.or_pair_moments.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, C.c_int,
-                                      C.c_uint64, C.c_int, P]
+                                      C.c_uint64, C.c_int, C.c_int, P]
         L.or_pair_moments.restype = C.c_int
         L.or_point_moments.argtypes = [P, P, C.c_int64, C.c_int64, C.c_int, C.c_double, C.c_int,
-                                       C.c_uint64, C.c_int, P, P]
+                                       C.c_uint64, C.c_int, C.c_int, P, P]
         L.or_pair_geometry.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, P, P, P, P,
                                        P, P, P]
         L.or_pair_geometry.restype = C.c_int
@@ -128,19 +136,21 @@ def classify_point(coords, tets, delta, p):
     return out
 
 
-def pair_moments(coords, tets, n, k, m, delta, N, seed, strategy="fullcaps"):
+def pair_moments(coords, tets, n, k, m, delta, N, seed, strategy="fullcaps", cap_sampling="whole"):
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
     S = np.zeros(15)
-    cls = lib().or_pair_moments(_p(coords), _p(tets), n, k, m, delta, N, seed, _strategy(strategy), _p(S))
+    cls = lib().or_pair_moments(_p(coords), _p(tets), n, k, m, delta, N, seed, _strategy(strategy),
+                                _caps(cap_sampling), _p(S))
     return cls, S
 
 
-def point_moments(coords, tets, n, k, delta, N, seed, strategy="fullcaps"):
+def point_moments(coords, tets, n, k, delta, N, seed, strategy="fullcaps", cap_sampling="whole"):
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
     K = tets.shape[0]
     cls = np.zeros(K, dtype=np.int8)
     S = np.zeros((K, 15))
-    lib().or_point_moments(_p(coords), _p(tets), K, n, k, delta, N, seed, _strategy(strategy), _p(cls), _p(S))
+    lib().or_point_moments(_p(coords), _p(tets), K, n, k, delta, N, seed, _strategy(strategy), _caps(cap_sampling),
+                           _p(cls), _p(S))
     return cls, S
 
 
@@ -156,13 +166,13 @@ def pair_geometry(coords, tets, n, k, m, delta):
 
 
 def assemble(coords, tets, vertex_free, delta, psi, mc_samples, seed, f_qp=None, g_nodal=None,
-             tet_region=None, outer_mask=None, strategy="fullcaps"):
+             tet_region=None, outer_mask=None, strategy="fullcaps", cap_sampling="whole"):
     """Full oracle assembly.  Returns a dict of numpy arrays (CSR blocks + rhs)."""
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
     vf = _c(vertex_free, np.uint8); tr = _c(tet_region, np.uint8); om = _c(outer_mask, np.uint8)
     fq = _c(f_qp, np.float64); gn = _c(g_nodal, np.float64)
     P = OrProblem(coords.shape[0], tets.shape[0], _p(coords), _p(tets), _p(vf), _p(tr), delta, psi,
-                  mc_samples, seed, _p(om), _p(fq), _p(gn), _strategy(strategy))
+                  mc_samples, seed, _p(om), _p(fq), _p(gn), _strategy(strategy), _caps(cap_sampling))
     S = OrSystem()
     rc = lib().or_assemble(C.byref(P), C.byref(S))
     if rc != 0:
@@ -209,4 +219,5 @@ def problem_assemble(pb, outer_mask=None):
     m = pb.mesh
     return assemble(m.coords, m.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
                     f_qp=pb.f_qp, g_nodal=pb.g_nodal, outer_mask=outer_mask,
-                    strategy=getattr(pb, "strategy", "fullcaps"))
+                    strategy=getattr(pb, "strategy", "fullcaps"),
+                    cap_sampling=getattr(pb, "cap_sampling", "whole"))

@@ -463,6 +463,7 @@ typedef struct {
     cutgeom g;
     int N;
     int caps; /* 1: the fullcaps Monte Carlo term is part of the pair */
+    int cap_sampling; /* 1: for n_in = 3 the caps are sampled on E - U_I (a corner tet) */
     uint64_t seed;
     uint32_t q, m;
 } pairctx;
@@ -494,21 +495,53 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
     /* sample point relative to p: y - p = (X_0 - p) + sum_{l=1..3} lambda_l (X_l - X_0),
      * with X_l - X_0 taken as (X_l - p) - (X_0 - p), as an FMA chain over l = 1, 2, 3 */
     if (!c->caps) return;
-    double e[4][3];
-    for (int l = 0; l < 4; ++l)
-        for (int i = 0; i < 3; ++i) e[l][i] = c->X[l][i] - c->p[i];
+    /* Sampling region: the whole E (samples in U_I rejected), or, for n_in = 3
+     * with cap sampling on, E - U_I itself: the corner tet with vertices
+     * Y_0 = X_o and Y_l = X_{a_l} + t (X_o - X_{a_l}) (o the outside vertex,
+     * a_l the inside ones ascending, t the sphere crossing on a_l -> o), of
+     * volume |E| (1 - t_0)(1 - t_1)(1 - t_2).  A sample's region coordinates
+     * mu give its barycentrics in E as lambda = sum_j mu_j row(Y_j).        */
+    int corner = c->cap_sampling && g->n_in == 3;
+    double e[4][3], row[4][4], vol_r = c->vol;
+    if (corner) {
+        int o = g->O[0];
+        for (int i = 0; i < 3; ++i) e[0][i] = c->X[o][i] - c->p[i];
+        unit(o, row[0]);
+        double rho = 1.0;
+        for (int l = 0; l < 3; ++l) {
+            int a = g->I[l];
+            double t = g->t[a][o];
+            for (int i = 0; i < 3; ++i) e[1 + l][i] = fma(t, c->X[o][i] - c->X[a][i], c->X[a][i] - c->p[i]);
+            for (int v = 0; v < 4; ++v) row[1 + l][v] = v == a ? 1.0 - t : (v == o ? t : 0.0);
+            rho = (l == 0) ? 1.0 - t : rho * (1.0 - t);
+        }
+        vol_r = c->vol * rho;
+    } else {
+        for (int l = 0; l < 4; ++l) {
+            for (int i = 0; i < 3; ++i) e[l][i] = c->X[l][i] - c->p[i];
+            unit(l, row[l]);
+        }
+    }
     double f[4][3];
     for (int l = 1; l < 4; ++l)
         for (int i = 0; i < 3; ++i) f[l][i] = e[l][i] - e[0][i];
-    double wmc = c->vol / (double)c->N;
+    double wmc = vol_r / (double)c->N;
     for (int s = 0; s < c->N; ++s) {
-        double lam[4];
-        or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, lam);
+        double mu[4];
+        or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, mu);
         double d[3];
         for (int i = 0; i < 3; ++i)
-            d[i] = fma(lam[3], f[3][i], fma(lam[2], f[2][i], fma(lam[1], f[1][i], e[0][i])));
+            d[i] = fma(mu[3], f[3][i], fma(mu[2], f[2][i], fma(mu[1], f[1][i], e[0][i])));
         double rr = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
-        if (rr < c->d2 && !in_UI(g, lam)) fn(user, lam, wmc, 1);
+        if (!(rr < c->d2)) continue;
+        if (corner) {
+            double lam[4];
+            for (int v = 0; v < 4; ++v)
+                lam[v] = ((mu[0] * row[0][v] + mu[1] * row[1][v]) + mu[2] * row[2][v]) + mu[3] * row[3][v];
+            fn(user, lam, wmc, 1);
+        } else if (!in_UI(g, mu)) {
+            fn(user, mu, wmc, 1);
+        }
     }
 }
 
@@ -519,11 +552,13 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
 typedef struct {
     double det[15];
     double mc[15];
+    double wmc; /* weight of the Monte Carlo nodes (the same for all of a pair) */
 } momacc;
 
 static void mom_node(void *user, const double lam[4], double w, int is_mc) {
     momacc *a = (momacc *)user;
     if (is_mc) {
+        a->wmc = w;
         a->mc[0] += 1.0;
         for (int j = 0; j < 4; ++j) a->mc[1 + j] += lam[j];
         int k = 5;
@@ -539,7 +574,7 @@ static void mom_node(void *user, const double lam[4], double w, int is_mc) {
 }
 
 static void pair_setup(pairctx *c, const double X[4][3], const double p[3], double delta, int N,
-                       uint64_t seed, uint32_t q, uint32_t m, int strategy) {
+                       uint64_t seed, uint32_t q, uint32_t m, int strategy, int cap_sampling) {
     c->X = X;
     for (int i = 0; i < 3; ++i) c->p[i] = p[i];
     c->d2 = delta * delta;
@@ -550,6 +585,7 @@ static void pair_setup(pairctx *c, const double X[4][3], const double p[3], doub
     c->m = m;
     c->cls = strategy_class(classify(X, p, c->d2, c->r2), X, p, c->d2, strategy);
     c->caps = strategy == OR_FULLCAPS;
+    c->cap_sampling = cap_sampling;
     if (c->cls >= OR_CUT0) cut_geometry(X, p, c->d2, c->r2, &c->g);
 }
 
@@ -557,8 +593,7 @@ static void pair_moments(const pairctx *c, double S[15]) {
     momacc a;
     memset(&a, 0, sizeof a);
     visit_nodes(c, mom_node, &a);
-    double sc = c->caps ? c->vol / (double)c->N : 0.0;
-    for (int k = 0; k < 15; ++k) S[k] = a.det[k] + sc * a.mc[k];
+    for (int k = 0; k < 15; ++k) S[k] = a.det[k] + a.wmc * a.mc[k];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -598,14 +633,14 @@ void or_classify_point(const double *coords, const int32_t *tets, int64_t n_tets
 
 /* moments of pair (outer point q = 4 n + k, inner tet m); returns the class */
 int or_pair_moments(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m,
-                    double delta, int N, uint64_t seed, int strategy, double S[15]) {
+                    double delta, int N, uint64_t seed, int strategy, int cap_sampling, double S[15]) {
     double Xn[4][3], Xm[4][3], p[3];
     rule_init();
     load_tet(coords, tets, n, Xn);
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m, strategy);
+    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m, strategy, cap_sampling);
     for (int i = 0; i < 15; ++i) S[i] = 0.0;
     if (c.cls != OR_OUT) pair_moments(&c, S);
     return c.cls;
@@ -613,10 +648,10 @@ int or_pair_moments(const double *coords, const int32_t *tets, int64_t n, int k,
 
 /* all pairs of one outer point against every tet: class + moments */
 void or_point_moments(const double *coords, const int32_t *tets, int64_t n_tets, int64_t n, int k,
-                      double delta, int N, uint64_t seed, int strategy, int8_t *cls,
+                      double delta, int N, uint64_t seed, int strategy, int cap_sampling, int8_t *cls,
                       double *S /*[n_tets][15]*/) {
     for (int64_t m = 0; m < n_tets; ++m)
-        cls[m] = (int8_t)or_pair_moments(coords, tets, n, k, m, delta, N, seed, strategy, S + 15 * m);
+        cls[m] = (int8_t)or_pair_moments(coords, tets, n, k, m, delta, N, seed, strategy, cap_sampling, S + 15 * m);
 }
 
 /* cut geometry of a pair, for geometric pins: returns n_in (or -1 if not CUT) */
@@ -629,7 +664,7 @@ int or_pair_geometry(const double *coords, const int32_t *tets, int64_t n, int k
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, 1, 0, 0, 0, OR_FULLCAPS);
+    pair_setup(&c, Xm, p, delta, 1, 0, 0, 0, OR_FULLCAPS, 0);
     if (c.cls < OR_CUT0) return -1;
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) t_out[4 * a + b] = c.g.t[a][b];
@@ -660,6 +695,7 @@ typedef struct {
     const double *f_qp;        /* optional [n_tets][4] */
     const double *g_nodal;     /* optional [n_vertices] */
     int32_t strategy;          /* OR_FULLCAPS .. OR_BARYCENTER */
+    int32_t cap_sampling;      /* 1: n_in = 3 caps sampled on the corner tet E - U_I */
 } or_problem;
 
 typedef struct {
@@ -755,6 +791,7 @@ static int validate(const or_problem *P) {
     if (!P || P->n_vertices < 0 || P->n_tets < 0) return 1;
     if (!(P->delta > 0.0) || P->mc_samples < 1) return 1;
     if (P->strategy < OR_FULLCAPS || P->strategy > OR_BARYCENTER) return 1;
+    if (P->cap_sampling != 0 && P->cap_sampling != 1) return 1;
     if (P->n_tets > 0 && (!P->coords || !P->tets || !P->vertex_free)) return 1;
     for (int64_t i = 0; i < 4 * P->n_tets; ++i)
         if (P->tets[i] < 0 || P->tets[i] >= P->n_vertices) return 2;
@@ -834,6 +871,7 @@ int or_assemble(const or_problem *P, or_system *S) {
                 c.vol = tet_volume(Xm);
                 c.N = P->mc_samples;
                 c.caps = P->strategy == OR_FULLCAPS;
+                c.cap_sampling = P->cap_sampling;
                 c.seed = P->seed;
                 c.q = (uint32_t)(4 * n + k);
                 c.m = (uint32_t)m;

@@ -29,6 +29,16 @@ NLFEM_FP32_LOCAL = 1
 NLFEM_MAX_MC_SAMPLES = 2047  # sample sums stay exact 32/64-bit integers
 # ball approximation strategies (nlfem_strategy)
 STRATEGIES = {"fullcaps": 0, "nocaps": 1, "overlap": 2, "inside": 3, "barycenter": 4}
+# where the cap samples are drawn (nlfem_cap_sampling)
+CAP_SAMPLING = {"whole": 0, "outside_ui": 1}
+
+
+def cap_sampling_id(cs):
+    if isinstance(cs, str):
+        if cs not in CAP_SAMPLING:
+            raise ValueError(f"unknown cap sampling {cs!r}")
+        return CAP_SAMPLING[cs]
+    return int(cs)
 
 
 def strategy_id(st):
@@ -51,7 +61,7 @@ class nlfem_mesh(C.Structure):
 class nlfem_params(C.Structure):
     _fields_ = [("delta", C.c_double), ("psi", C.c_double), ("mc_samples", C.c_int32),
                 ("seed", C.c_uint64), ("precision", C.c_int32), ("outer_mask", C.c_void_p),
-                ("strategy", C.c_int32)]
+                ("strategy", C.c_int32), ("cap_sampling", C.c_int32)]
 
 
 class nlfem_pair_record(C.Structure):
@@ -308,12 +318,13 @@ class Device:
         return m, keep
 
     def plan(self, coords, tets, vertex_free, delta, psi, mc_samples, seed, precision="fp64", tet_region=None,
-             outer_mask=None, strategy="fullcaps"):
+             outer_mask=None, strategy="fullcaps", cap_sampling="whole"):
         m, keep = self.mesh(coords, tets, vertex_free, tet_region)
         om = None if outer_mask is None else self.to_dev(outer_mask, self.torch.uint8)
         prm = nlfem_params(float(delta), float(psi), int(mc_samples), int(seed),
                            NLFEM_FP32_LOCAL if precision == "fp32" else NLFEM_FP64,
-                           None if om is None else om.data_ptr(), strategy_id(strategy))
+                           None if om is None else om.data_ptr(), strategy_id(strategy),
+                           cap_sampling_id(cap_sampling))
         plan = nlfem_plan_create(self.ctx, m, prm)
         return Plan(self, plan)
 
@@ -321,7 +332,8 @@ class Device:
         mm = pb.mesh
         return self.plan(mm.coords, mm.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
                          precision=pb.precision, outer_mask=outer_mask,
-                         strategy=getattr(pb, "strategy", "fullcaps"))
+                         strategy=getattr(pb, "strategy", "fullcaps"),
+                         cap_sampling=getattr(pb, "cap_sampling", "whole"))
 
 
 class Plan:
@@ -397,7 +409,8 @@ class Batch:
             params[i] = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
                                      NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
                                      None if om is None else om.data_ptr(),
-                                     strategy_id(getattr(pb, "strategy", "fullcaps")))
+                                     strategy_id(getattr(pb, "strategy", "fullcaps")),
+                                     cap_sampling_id(getattr(pb, "cap_sampling", "whole")))
         h = C.c_void_p()
         _check(load().nlfem_batch_create(dev.ctx, self.n, meshes, params, C.byref(h)), dev.ctx)
         self.handle = h
@@ -487,7 +500,8 @@ class Server:
                        None, 0)
         prm = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
                            NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
-                           None if om is None else om.ctypes.data, strategy_id(getattr(pb, "strategy", "fullcaps")))
+                           None if om is None else om.ctypes.data, strategy_id(getattr(pb, "strategy", "fullcaps")),
+                           cap_sampling_id(getattr(pb, "cap_sampling", "whole")))
         sp = nlfem_solve_params(rtol, max_iter)
         t = C.c_uint64()
         self._err(load().nlfem_server_submit(self.handle, C.byref(m), C.byref(prm),

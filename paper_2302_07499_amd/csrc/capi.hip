@@ -44,7 +44,7 @@ struct nlfem_plan {
     int umax = 0, max_row = 0, fx_shift = 0, g_shift = 0, w_shift = 0, row_shift = 0;
     int64_t pair_counts[5] = {0, 0, 0, 0, 0};
     double delta = 0, psi = 0;
-    int mc = 1, precision = 0, strategy = 0;
+    int mc = 1, precision = 0, strategy = 0, cap_sampling = 0;
     uint64_t seed = 0;
     // device arrays: mesh and ball query
     double *tetX = nullptr, *vol = nullptr;
@@ -490,6 +490,7 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.psi = pl->psi;
     a.mc_samples = pl->mc;
     a.caps = pl->strategy == NLFEM_FULLCAPS ? 1 : 0;
+    a.vr = pl->cap_sampling == NLFEM_CAPS_OUTSIDE_UI ? 1 : 0;
     a.key0 = (uint32_t)(pl->seed & 0xFFFFFFFFull);
     a.key1 = (uint32_t)(pl->seed >> 32);
     a.fx_shift = pl->fx_shift;
@@ -577,6 +578,7 @@ struct nlfem_batch {
     unsigned long long* d_head = nullptr;
     int umax_all = 1;
     bool fp32 = false;
+    bool vr = false;
     int block = 256, grid = 0, n_cu = 256;
     double tune_ms = 0.0;
     bool tuned = false;
@@ -615,7 +617,8 @@ void batch_free(nlfem_batch* b) {
 nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStream_t s, int block, int grid) {
     nlfem_ctx* c = b->ctx;
     for (nlfem_plan* pl : b->plans) HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
-    HIPCHK(launch_integrate_batch(b->d_descs, b->d_items, b->n_items, b->d_head, b->umax_all, b->fp32, block, grid, s));
+    HIPCHK(launch_integrate_batch(b->d_descs, b->d_items, b->n_items, b->d_head, b->umax_all, b->fp32, b->vr, block,
+                                  grid, s));
     for (size_t i = 0; i < b->plans.size(); ++i) {
         const nlfem_batch::Out& o = b->outs[i];
         nlfem_status st = enqueue_rows(c, b->plans[i], g_nodal ? g_nodal[i] : nullptr, o.ff_val, o.fc_val, o.rhs, s);
@@ -626,7 +629,7 @@ nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStre
 
 double time_integrate(nlfem_batch* b, int block, int grid) {
     Timer t(b->gs);
-    if (launch_integrate_batch(b->d_descs, b->d_sample, b->n_sample, b->d_head, b->umax_all, b->fp32, block, grid,
+    if (launch_integrate_batch(b->d_descs, b->d_sample, b->n_sample, b->d_head, b->umax_all, b->fp32, b->vr, block, grid,
                                b->gs) != hipSuccess)
         return 1e30;
     return t.stop();
@@ -715,6 +718,8 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
         return fail(c, NLFEM_E_INVALID_ARG, "unknown precision");
     if (prm->strategy < NLFEM_FULLCAPS || prm->strategy > NLFEM_BARYCENTER)
         return fail(c, NLFEM_E_INVALID_ARG, "unknown ball approximation strategy");
+    if (prm->cap_sampling != NLFEM_CAPS_WHOLE_ELEMENT && prm->cap_sampling != NLFEM_CAPS_OUTSIDE_UI)
+        return fail(c, NLFEM_E_INVALID_ARG, "unknown cap sampling mode");
     if (mesh->n_tets >= (int64_t)1 << 31 || mesh->n_vertices >= (int64_t)1 << 31)
         return fail(c, NLFEM_E_UNSUPPORTED, "mesh larger than 2^31 entities");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
@@ -726,6 +731,7 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
     pl->seed = prm->seed;
     pl->precision = prm->precision;
     pl->strategy = prm->strategy;
+    pl->cap_sampling = prm->cap_sampling;
     nlfem_status st = build_plan(c, pl, mesh, prm);
     if (st != NLFEM_OK) {
         hipStreamSynchronize(c->stream);
@@ -840,12 +846,16 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     if (!c) return NLFEM_E_INVALID_ARG;
     if (!out || n < 0 || (n > 0 && (!meshes || !params))) return fail(c, NLFEM_E_INVALID_ARG, "bad batch argument");
     *out = nullptr;
-    for (int32_t i = 0; i < n; ++i)
+    for (int32_t i = 0; i < n; ++i) {
         if (params[i].precision != params[0].precision)
             return fail(c, NLFEM_E_INVALID_ARG, "all meshes of a batch must use the same precision");
+        if (params[i].cap_sampling != params[0].cap_sampling)
+            return fail(c, NLFEM_E_INVALID_ARG, "all meshes of a batch must use the same cap sampling");
+    }
     nlfem_batch* b = new nlfem_batch();
     b->ctx = c;
     b->fp32 = n > 0 && params[0].precision == NLFEM_FP32_LOCAL;
+    b->vr = n > 0 && params[0].cap_sampling == NLFEM_CAPS_OUTSIDE_UI;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) b->n_cu = prop.multiProcessorCount;
     for (int32_t i = 0; i < n; ++i) {

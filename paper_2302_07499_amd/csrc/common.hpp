@@ -106,6 +106,7 @@ struct IntegrateArgs {
     double delta, psi;
     int mc_samples;
     int caps;  // 1: cut points add the fullcaps Monte Carlo term (strategy fullcaps)
+    int vr;    // 1: caps of n_in = 3 points sampled on E_m minus U_I (the corner tet)
     uint32_t key0, key1;
     int fx_shift;  // scale 2^fx_shift of the LDS sums T0 and R
     int g_shift;   // scale of the cut part of G_m (global accumulators)
@@ -119,7 +120,8 @@ struct IntegrateArgs {
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 // persistent integration over work items (mesh index, outer position); block 128 or 256
 hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
-                                  unsigned long long* head, int umax, bool fp32, int block, int grid, hipStream_t s);
+                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
+                                  hipStream_t s);
 size_t integrate_lds_bytes(int umax);
 // per-pair moments of outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k,
 // out_S [slots][15], out_qm [slots][3] = (q, m, class)

@@ -248,6 +248,16 @@ struct CutGeom {
     double c0[4], c1[4];  // U_I = E n {c0.l >= 0} [n {c1.l >= 0}]
 };
 
+// E_m minus U_I when it is a single tet (n_in = 3): the corner at the outside
+// vertex o, with vertices X_o and the sphere crossings X_a + t (X_o - X_a) on
+// the edges from the inside vertices a[0..2] (ascending).  Used when the caps
+// are sampled over E_m minus U_I instead of the whole E_m.
+struct CornerGeom {
+    bool on;
+    int o, a[3];
+    double t[3];
+};
+
 __device__ __forceinline__ double det3m(double a0, double a1, double a2, double b0, double b1, double b2, double c0,
                                         double c1, double c2) {
     return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
@@ -355,7 +365,7 @@ __device__ __forceinline__ int nth_bit(unsigned m, int n) {
 // planes are picked by selects.
 template <typename T>
 __device__ inline void cut_setup(const double* Xg, const double* p, double d2, const double* r2, double vol,
-                                 CutGeom& g, double* D, double* G) {
+                                 CutGeom& g, double* D, double* G, CornerGeom* cr = nullptr) {
     unsigned in = 0;
 #pragma unroll
     for (int l = 0; l < 4; ++l)
@@ -376,6 +386,12 @@ __device__ inline void cut_setup(const double* Xg, const double* p, double d2, c
     const HullPt x2 = cross(any, c3 ? I1 : I0, c3 ? O0 : O1);      // P_I0O1 | P_I1O0 (n_in = 3)
     const HullPt x3 = cross(any, c1 ? I0 : (c2 ? I1 : I2), c1 ? O2 : (c2 ? O1 : O0));  // h5
     const HullPt x4 = cross(c2, I1, O0);                           // P_I1O0 (n_in = 2)
+    if (cr) {
+        cr->on = c3;
+        cr->o = x1.b;
+        cr->a[0] = x1.a; cr->a[1] = x2.a; cr->a[2] = x3.a;
+        cr->t[0] = x1.t; cr->t[1] = x2.t; cr->t[2] = x3.t;
+    }
     const int v0 = any ? I0 : 0;
     const HullPt h0{v0, -1, 0.0};
     // (n_in = 0 lanes take h0 everywhere: their dummy crossings may be NaN)
@@ -455,7 +471,7 @@ __device__ inline void in_moments(double vol, double* S) {
 
 template <typename T>
 __device__ inline void cut_det(const double* X, double vol, const double* p, double d2, CutGeom& g, double* D,
-                               double* G) {
+                               double* G, CornerGeom* cr = nullptr) {
     // X: the inner tet's vertex coordinates [4][3] in global memory; S0, S1
     // of the subdivision go to D[0..4] (overwritten), S2 is added to G[0..9]
     double r2[4];
@@ -466,12 +482,13 @@ __device__ inline void cut_det(const double* X, double vol, const double* p, dou
     }
 #pragma unroll
     for (int i = 0; i < 5; ++i) D[i] = 0.0;
-    cut_setup<T>(X, p, d2, r2, vol, g, D, G);
+    cut_setup<T>(X, p, d2, r2, vol, g, D, G, cr);
 }
 
-template <typename T>
+template <typename T, bool VR = false>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
-                              uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
+                              uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
+                              const CornerGeom* cr = nullptr) {
     // The sample barycentrics are lambda = L * 2^-21 with integer L (spacings
     // of 21-bit uniforms).  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3
     // substituted, the sample point relative to p is
@@ -489,14 +506,37 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
     // partial sum is a multiple of 2^-42 below 2^11).  Both precisions of the
     // local integrals therefore get the same, exact Monte Carlo moments.
     const double u = 1.0 / 2097152.0;
-    const double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
-    const double f1x = ((X[3] - p[0]) - e0x) * u, f1y = ((X[4] - p[1]) - e0y) * u, f1z = ((X[5] - p[2]) - e0z) * u;
-    const double f2x = ((X[6] - p[0]) - e0x) * u, f2y = ((X[7] - p[1]) - e0y) * u, f2z = ((X[8] - p[2]) - e0z) * u;
-    const double f3x = ((X[9] - p[0]) - e0x) * u, f3y = ((X[10] - p[1]) - e0y) * u, f3z = ((X[11] - p[2]) - e0z) * u;
-    const double p00 = g.c0[0], p01 = (g.c0[1] - g.c0[0]) * u, p02 = (g.c0[2] - g.c0[0]) * u,
-                 p03 = (g.c0[3] - g.c0[0]) * u;
-    const double p10 = g.c1[0], p11 = (g.c1[1] - g.c1[0]) * u, p12 = (g.c1[2] - g.c1[0]) * u,
-                 p13 = (g.c1[3] - g.c1[0]) * u;
+    double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
+    double f1x = ((X[3] - p[0]) - e0x) * u, f1y = ((X[4] - p[1]) - e0y) * u, f1z = ((X[5] - p[2]) - e0z) * u;
+    double f2x = ((X[6] - p[0]) - e0x) * u, f2y = ((X[7] - p[1]) - e0y) * u, f2z = ((X[8] - p[2]) - e0z) * u;
+    double f3x = ((X[9] - p[0]) - e0x) * u, f3y = ((X[10] - p[1]) - e0y) * u, f3z = ((X[11] - p[2]) - e0z) * u;
+    double p00 = g.c0[0], p01 = (g.c0[1] - g.c0[0]) * u, p02 = (g.c0[2] - g.c0[0]) * u,
+           p03 = (g.c0[3] - g.c0[0]) * u;
+    double p10 = g.c1[0], p11 = (g.c1[1] - g.c1[0]) * u, p12 = (g.c1[2] - g.c1[0]) * u,
+           p13 = (g.c1[3] - g.c1[0]) * u;
+    if constexpr (VR) {
+        if (cr->on) {
+            // samples uniform on the corner tet Y_0 = X_o, Y_l = X_a + t (X_o - X_a);
+            // Y_l - p = (X_a - p) + t (X_o - X_a) as one FMA; no U_I test
+            const double* Xo = X + 3 * cr->o;
+            e0x = Xo[0] - p[0]; e0y = Xo[1] - p[1]; e0z = Xo[2] - p[2];
+            double fy[3][3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double* Xa = X + 3 * cr->a[l];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double e0c = c == 0 ? e0x : (c == 1 ? e0y : e0z);
+                    fy[l][c] = (fma(cr->t[l], Xo[c] - Xa[c], Xa[c] - p[c]) - e0c) * u;
+                }
+            }
+            f1x = fy[0][0]; f1y = fy[0][1]; f1z = fy[0][2];
+            f2x = fy[1][0]; f2y = fy[1][1]; f2z = fy[1][2];
+            f3x = fy[2][0]; f3y = fy[2][1]; f3z = fy[2][2];
+            p00 = -1.0; p01 = 0.0; p02 = 0.0; p03 = 0.0;
+            p10 = 1.0; p11 = 0.0; p12 = 0.0; p13 = 0.0;
+        }
+    }
     constexpr bool kF32 = sizeof(T) == 4;
     uint32_t icnt = 0, ia1 = 0, ia2 = 0, ia3 = 0;
     uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
@@ -556,10 +596,58 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
     S[0] = scale * dc; S[1] = scale * d0; S[2] = scale * d1; S[3] = scale * d2s; S[4] = scale * d3;
     S[5] = scale * c00; S[6] = scale * c01; S[7] = scale * c02; S[8] = scale * c03; S[9] = scale * c11;
     S[10] = scale * c12; S[11] = scale * c13; S[12] = scale * c22; S[13] = scale * c23; S[14] = scale * c33;
+    if constexpr (VR) {
+        if (cr->on) {
+            // moments of the corner-tet coordinates mu -> moments of lambda = A mu,
+            // A[o][0] = 1, A[o][l] = t_l, A[a_l][l] = 1 - t_l; region volume
+            // |E| (1 - t_0)(1 - t_1)(1 - t_2)
+            const double rho = ((1.0 - cr->t[0]) * (1.0 - cr->t[1])) * (1.0 - cr->t[2]);
+            double A[4][4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                A[v][0] = v == cr->o ? 1.0 : 0.0;
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    A[v][1 + l] = v == cr->a[l] ? 1.0 - cr->t[l] : (v == cr->o ? cr->t[l] : 0.0);
+            }
+            double M1[4], M2[4][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) M1[j] = rho * S[1 + j];
+            int k = 5;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = i; j < 4; ++j) {
+                    M2[i][j] = rho * S[k];
+                    M2[j][i] = M2[i][j];
+                    ++k;
+                }
+            S[0] = rho * S[0];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc = fma(A[v][j], M1[j], acc);
+                S[1 + v] = acc;
+            }
+            k = 5;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int w = v; w < 4; ++w) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) acc = fma(A[v][i] * A[w][j], M2[i][j], acc);
+                    S[k++] = acc;
+                }
+        }
+    }
 }
 
 // whole-pair moments (the sum of the pieces), as the oracle reports them
-template <typename T>
+template <typename T, bool VR = false>
 __device__ inline void pair_moments(const double* X, double vol, const double* p, double d2, int code, int N,
                                     bool caps, uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
     if (code == C_IN) {
@@ -570,9 +658,10 @@ __device__ inline void pair_moments(const double* X, double vol, const double* p
     double D[5], G[10];
 #pragma unroll
     for (int i = 0; i < 10; ++i) G[i] = 0.0;
-    cut_det<T>(X, vol, p, d2, g, D, G);
+    CornerGeom cr;
+    cut_det<T>(X, vol, p, d2, g, D, G, VR ? &cr : nullptr);
     if (caps) {
-        cut_mc<T>(X, vol, p, d2, g, N, key0, key1, q, m, S);
+        cut_mc<T, VR>(X, vol, p, d2, g, N, key0, key1, q, m, S, &cr);
     } else {
 #pragma unroll
         for (int i = 0; i < 15; ++i) S[i] = 0.0;

@@ -80,7 +80,7 @@ __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned 
 // same T0[k], so the threads sum privately and the block adds the slots up at
 // the end: the same integers, without same-address atomics), Ve [umax], and
 // the 4 outer points.
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, bool VR>
 __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
     const int umax = a.umax;
@@ -148,10 +148,11 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
             const double* X = a.tetX + 12 * (int64_t)m;
             CutGeom cg;
             double D[5];
-            cut_det<T>(X, volm, P[k], d2, cg, D, g);
+            CornerGeom cr;
+            cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
             if (a.caps) {
-                cut_mc<T>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k), (uint32_t)m,
-                          S);
+                cut_mc<T, VR>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
+                              (uint32_t)m, S, &cr);
             } else {
                 for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
             }
@@ -201,17 +202,18 @@ __device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t 
     }
 }
 
-template <typename T>
+// VR: the caps of n_in = 3 pairs are sampled on E_m minus U_I (a corner tet)
+template <typename T, bool VR>
 __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
-    integrate_outer<T, 256>(a, (int64_t)blockIdx.x, smem64, P);
+    integrate_outer<T, 256, VR>(a, (int64_t)blockIdx.x, smem64, P);
 }
 
 // Persistent batched integration: every workgroup takes work items (mesh,
 // outer tet) from a device queue until it is empty.  Items are ordered by
 // decreasing estimated cost; each item's results depend on the item only.
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, bool VR>
 __global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batch(const IntegrateArgs* descs, const int2* items,
                                                            int64_t n_items, unsigned long long* head) {
     extern __shared__ unsigned long long smem64[];
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batc
         __syncthreads();
         if (it >= n_items) break;
         const int2 item = items[it];
-        integrate_outer<T, BLOCK>(descs[item.x], (int64_t)item.y, smem64, P);
+        integrate_outer<T, BLOCK, VR>(descs[item.x], (int64_t)item.y, smem64, P);
         __syncthreads();
     }
 }
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batc
 __global__ void k_reset_u64(unsigned long long* p) { *p = 0ull; }
 
 // per-pair moments for outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k
-template <typename T>
+template <typename T, bool VR>
 __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_lo, double* out_S, int32_t* out_qm) {
     const int64_t oi = o_lo + blockIdx.x;
     const int n = a.outer_ids[oi];
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_
             out_qm[3 * idx + 2] = c;
             if (c == C_OUT) continue;
             double S[15];
-            pair_moments<T>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1, (uint32_t)(4 * n + k),
+            pair_moments<T, VR>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1, (uint32_t)(4 * n + k),
                             (uint32_t)m, S);
             for (int i = 0; i < 15; ++i) out_S[15 * idx + i] = S[i];
         }
@@ -309,22 +311,39 @@ size_t integrate_lds_bytes(int umax) { return (size_t)umax * 68 + 64 + 8 * 256 *
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;
     size_t sh = integrate_lds_bytes(a.umax);
-    if (fp32) k_integrate<float><<<(unsigned)a.n_outer, 256, sh, s>>>(a);
-    else k_integrate<double><<<(unsigned)a.n_outer, 256, sh, s>>>(a);
+    const unsigned g = (unsigned)a.n_outer;
+    if (a.vr) {
+        if (fp32) k_integrate<float, true><<<g, 256, sh, s>>>(a);
+        else k_integrate<double, true><<<g, 256, sh, s>>>(a);
+    } else {
+        if (fp32) k_integrate<float, false><<<g, 256, sh, s>>>(a);
+        else k_integrate<double, false><<<g, 256, sh, s>>>(a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
-                                  unsigned long long* head, int umax, bool fp32, int block, int grid, hipStream_t s) {
+                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
+                                  hipStream_t s) {
     size_t sh = integrate_lds_bytes(umax);
     k_reset_u64<<<1, 1, 0, s>>>(head);
     if (n_items <= 0) return hipGetLastError();
     if (block == 128) {
-        if (fp32) k_integrate_batch<float, 128><<<grid, 128, sh, s>>>(descs, items, n_items, head);
-        else k_integrate_batch<double, 128><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+        if (vr) {
+            if (fp32) k_integrate_batch<float, 128, true><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 128, true><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+        } else {
+            if (fp32) k_integrate_batch<float, 128, false><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 128, false><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+        }
     } else {
-        if (fp32) k_integrate_batch<float, 256><<<grid, 256, sh, s>>>(descs, items, n_items, head);
-        else k_integrate_batch<double, 256><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+        if (vr) {
+            if (fp32) k_integrate_batch<float, 256, true><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 256, true><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+        } else {
+            if (fp32) k_integrate_batch<float, 256, false><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 256, false><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+        }
     }
     return hipGetLastError();
 }
@@ -332,8 +351,14 @@ hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items,
 hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, int64_t o_hi, double* out_S,
                               int32_t* out_qm, hipStream_t s) {
     if (o_hi <= o_lo) return hipSuccess;
-    if (fp32) k_debug_pairs<float><<<(unsigned)(o_hi - o_lo), 256, 0, s>>>(a, o_lo, out_S, out_qm);
-    else k_debug_pairs<double><<<(unsigned)(o_hi - o_lo), 256, 0, s>>>(a, o_lo, out_S, out_qm);
+    const unsigned g = (unsigned)(o_hi - o_lo);
+    if (a.vr) {
+        if (fp32) k_debug_pairs<float, true><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
+        else k_debug_pairs<double, true><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
+    } else {
+        if (fp32) k_debug_pairs<float, false><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
+        else k_debug_pairs<double, false><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
+    }
     return hipGetLastError();
 }
 

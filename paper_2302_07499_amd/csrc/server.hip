@@ -354,6 +354,8 @@ nlfem_status nlfem_server_submit(nlfem_server* s, const nlfem_mesh* mesh, const 
     if (!(prm->delta > 0.0) || prm->mc_samples < 1 || prm->mc_samples > NLFEM_MAX_MC_SAMPLES)
         return NLFEM_E_INVALID_ARG;
     if (prm->strategy < NLFEM_FULLCAPS || prm->strategy > NLFEM_BARYCENTER) return NLFEM_E_INVALID_ARG;
+    if (prm->cap_sampling != NLFEM_CAPS_WHOLE_ELEMENT && prm->cap_sampling != NLFEM_CAPS_OUTSIDE_UI)
+        return NLFEM_E_INVALID_ARG;
     std::unique_ptr<Request> r(new Request());
     r->t_arrival = Clock::now();
     r->V = mesh->n_vertices;

@@ -14,7 +14,7 @@ integration, inner-element terms, row assembly and the right-hand side
 solve is timed separately.
 
 Batched: 256 meshes (n ~ U{8..24}, delta/h in {2,3,4}, jitter 0.15h, N = 32,
-FP32-local), one persistent fused integration launch per graph replay.
+FP32-local), one integration launch per LDS-footprint group of meshes per graph replay.
 
 Strategies: the same workload assembled with the other ball approximations
 (nocaps, overlap, inside, barycenter; FP64), one line each beside the main

@@ -527,16 +527,17 @@ nlfem_status enqueue_rows(nlfem_ctx* c, nlfem_plan* pl, const double* g_nodal, d
 // Autotuner cache: shape class -> (block, workgroups per CU), shared by all
 // batches of the process.
 struct TuneKey {
-    int log2_pairs, log2_items, mc, fp32;
+    int log2_pairs, log2_items, mc, fp32, per_cu;
     bool operator<(const TuneKey& o) const {
         if (log2_pairs != o.log2_pairs) return log2_pairs < o.log2_pairs;
         if (log2_items != o.log2_items) return log2_items < o.log2_items;
         if (mc != o.mc) return mc < o.mc;
-        return fp32 < o.fp32;
+        if (fp32 != o.fp32) return fp32 < o.fp32;
+        return per_cu < o.per_cu;
     }
 };
 struct TuneVal {
-    int block, wg_per_cu;
+    int block;
     double ms;
 };
 std::map<TuneKey, TuneVal>& tune_cache() {
@@ -572,15 +573,21 @@ struct nlfem_batch {
     std::vector<void*> owned;
     std::vector<IntegrateArgs> descs;
     IntegrateArgs* d_descs = nullptr;
-    int2* d_items = nullptr;
-    int2* d_sample = nullptr;  // every sample_stride-th item: the autotuner times this list
-    int64_t n_items = 0, n_sample = 0, sample_stride = 1, total_pairs = 0;
-    unsigned long long* d_head = nullptr;
-    int umax_all = 1;
+    // Meshes whose local vertex sets allow the same number of resident
+    // workgroups per CU (LDS footprint) share one launch, so a mesh with a
+    // small horizon is not held to the occupancy of the largest.
+    struct Group {
+        int umax = 1, per_cu = 1;
+        int2* d_items = nullptr;   // (mesh, outer position), longest first
+        int2* d_sample = nullptr;  // every stride-th item: the autotuner times this list
+        int64_t n_items = 0, n_sample = 0, pairs = 0;
+        int block = 256;
+        double tune_ms = 0.0;
+    };
+    std::vector<Group> groups;
+    int64_t total_pairs = 0;
     bool fp32 = false;
     bool vr = false;
-    int block = 256, grid = 0, n_cu = 256;
-    double tune_ms = 0.0;
     bool tuned = false;
     hipStream_t gs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -614,11 +621,11 @@ void batch_free(nlfem_batch* b) {
 }
 
 // numeric phase of every mesh of the batch on stream s
-nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStream_t s, int block, int grid) {
+nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStream_t s) {
     nlfem_ctx* c = b->ctx;
     for (nlfem_plan* pl : b->plans) HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
-    HIPCHK(launch_integrate_batch(b->d_descs, b->d_items, b->n_items, b->d_head, b->umax_all, b->fp32, b->vr, block,
-                                  grid, s));
+    for (const nlfem_batch::Group& g : b->groups)
+        HIPCHK(launch_integrate_items(b->d_descs, g.d_items, g.n_items, g.umax, b->fp32, b->vr, g.block, s));
     for (size_t i = 0; i < b->plans.size(); ++i) {
         const nlfem_batch::Out& o = b->outs[i];
         nlfem_status st = enqueue_rows(c, b->plans[i], g_nodal ? g_nodal[i] : nullptr, o.ff_val, o.fc_val, o.rhs, s);
@@ -627,10 +634,10 @@ nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStre
     return NLFEM_OK;
 }
 
-double time_integrate(nlfem_batch* b, int block, int grid) {
+double time_integrate(nlfem_batch* b, const nlfem_batch::Group& g, int block) {
     Timer t(b->gs);
-    if (launch_integrate_batch(b->d_descs, b->d_sample, b->n_sample, b->d_head, b->umax_all, b->fp32, b->vr, block, grid,
-                               b->gs) != hipSuccess)
+    if (launch_integrate_items(b->d_descs, g.d_sample, g.n_sample, g.umax, b->fp32, b->vr, block, b->gs) !=
+        hipSuccess)
         return 1e30;
     return t.stop();
 }
@@ -857,7 +864,9 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     b->fp32 = n > 0 && params[0].precision == NLFEM_FP32_LOCAL;
     b->vr = n > 0 && params[0].cap_sampling == NLFEM_CAPS_OUTSIDE_UI;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) b->n_cu = prop.multiProcessorCount;
+    size_t lds_cu = 160 * 1024;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.maxSharedMemoryPerMultiProcessor > 0)
+        lds_cu = prop.maxSharedMemoryPerMultiProcessor;
     for (int32_t i = 0; i < n; ++i) {
         nlfem_plan* pl = nullptr;
         nlfem_status st = nlfem_plan_create(c, &meshes[i], &params[i], &pl);
@@ -868,8 +877,21 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         b->plans.push_back(pl);
     }
     hipStream_t s = c->stream;
-    std::vector<int2> items;
-    std::vector<int64_t> cost;
+    // resident 256-thread workgroups per CU that the LDS footprint allows,
+    // capped at the 3 the register budget allows
+    auto per_cu = [&](int umax) {
+        const size_t bytes = integrate_lds_bytes(std::max(umax, 1));
+        return (int)std::max<size_t>(1, std::min<size_t>(3, lds_cu / bytes));
+    };
+    std::map<int, int> gid;  // per_cu -> group
+    for (int32_t i = 0; i < n; ++i) gid[per_cu(b->plans[i]->umax)] = 0;
+    for (auto& kv : gid) {
+        kv.second = (int)b->groups.size();
+        b->groups.emplace_back();
+        b->groups.back().per_cu = kv.first;
+    }
+    std::vector<std::vector<int2>> items(b->groups.size());
+    std::vector<std::vector<int64_t>> cost(b->groups.size());
     b->outs.resize(n);
     for (int32_t i = 0; i < n; ++i) {
         nlfem_plan* pl = b->plans[i];
@@ -893,46 +915,63 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         HIPCHK(launch_copy_i32(pl->fc_col, o.fc_col, pl->nnz_fc, s));
         HIPCHK(launch_copy_i32(pl->free_to_vertex, o.f2v, nf, s));
         b->descs.push_back(make_args(pl, nullptr));
-        b->umax_all = std::max(b->umax_all, std::max(pl->umax, 1));
+        const int g = gid[per_cu(pl->umax)];
+        b->groups[g].umax = std::max(b->groups[g].umax, std::max(pl->umax, 1));
+        b->groups[g].pairs += pl->P;
         std::vector<int64_t> off(pl->n_outer + 1);
         HIPCHK(hipMemcpyAsync(off.data(), pl->pair_off, off.size() * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int64_t oi = 0; oi < pl->n_outer; ++oi) {
-            items.push_back(make_int2(i, (int)oi));
-            cost.push_back(off[oi + 1] - off[oi]);
+            items[g].push_back(make_int2(i, (int)oi));
+            cost[g].push_back(off[oi + 1] - off[oi]);
         }
         b->total_pairs += pl->P;
     }
-    for (auto& d : b->descs) d.umax = b->umax_all;
-    if (integrate_lds_bytes(b->umax_all) > c->lds_max) {
-        batch_free(b);
-        return fail(c, NLFEM_E_UNSUPPORTED, "batch ball vertex set too large for LDS");
+    // the kernel lays out LDS from the descriptor's umax: every mesh of a
+    // group uses the group's
+    for (int32_t i = 0; i < n; ++i) b->descs[i].umax = b->groups[gid[per_cu(b->plans[i]->umax)]].umax;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        nlfem_batch::Group& G = b->groups[g];
+        if (integrate_lds_bytes(G.umax) > c->lds_max) {
+            batch_free(b);
+            return fail(c, NLFEM_E_UNSUPPORTED, "batch ball vertex set too large for LDS");
+        }
+        // longest items first
+        std::vector<int64_t> order(items[g].size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t bb) { return cost[g][a] > cost[g][bb]; });
+        std::vector<int2> sorted(items[g].size());
+        for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[g][order[i]];
+        G.n_items = (int64_t)sorted.size();
+        if (G.n_items > 0x7fffffff) {
+            batch_free(b);
+            return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^31-1 outer tets in one batch group");
+        }
+        // tuning sample: a strided subset of the longest-first list with about
+        // 1.5e8 pairs, so each candidate shape is timed on the same mix of
+        // item costs in a fraction of the full launch
+        const int64_t stride = std::min<int64_t>(64, std::max<int64_t>(1, G.pairs / 150000000));
+        std::vector<int2> sample;
+        for (size_t i = 0; i < sorted.size(); i += (size_t)stride) sample.push_back(sorted[i]);
+        G.n_sample = (int64_t)sample.size();
+        G.d_sample = (int2*)b->alloc(sample.size() * sizeof(int2) + 16);
+        G.d_items = (int2*)b->alloc(sorted.size() * sizeof(int2) + 16);
+        if (!G.d_items || !G.d_sample) {
+            batch_free(b);
+            return fail(c, NLFEM_E_OOM, c->err);
+        }
+        if (!sorted.empty()) {
+            HIPCHK(hipMemcpyAsync(G.d_items, sorted.data(), sorted.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(G.d_sample, sample.data(), sample.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        }
+        // the host vectors are freed at the end of this scope: finish the copies first
+        HIPCHK(hipStreamSynchronize(s));
     }
-    // longest items first
-    std::vector<int64_t> order(items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t bb) { return cost[a] > cost[bb]; });
-    std::vector<int2> sorted(items.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
-    b->n_items = (int64_t)sorted.size();
-    // tuning sample: a strided subset of the longest-first list with about
-    // 1.5e8 pairs, so each candidate shape is timed on the same mix of item
-    // costs in a fraction of the full launch
-    b->sample_stride = std::min<int64_t>(64, std::max<int64_t>(1, b->total_pairs / 150000000));
-    std::vector<int2> sample;
-    for (size_t i = 0; i < sorted.size(); i += (size_t)b->sample_stride) sample.push_back(sorted[i]);
-    b->n_sample = (int64_t)sample.size();
-    b->d_sample = (int2*)b->alloc(sample.size() * sizeof(int2) + 16);
-    b->d_items = (int2*)b->alloc(sorted.size() * sizeof(int2) + 16);
     b->d_descs = (IntegrateArgs*)b->alloc(b->descs.size() * sizeof(IntegrateArgs) + 16);
-    b->d_head = (unsigned long long*)b->alloc(64);
-    if (!b->d_items || !b->d_sample || !b->d_descs || !b->d_head) {
+    if (!b->d_descs) {
         batch_free(b);
         return fail(c, NLFEM_E_OOM, c->err);
-    }
-    if (!sorted.empty()) {
-        HIPCHK(hipMemcpyAsync(b->d_items, sorted.data(), sorted.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(b->d_sample, sample.data(), sample.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     }
     if (!b->descs.empty())
         HIPCHK(hipMemcpyAsync(b->d_descs, b->descs.data(), b->descs.size() * sizeof(IntegrateArgs),
@@ -973,32 +1012,21 @@ nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, con
     if (fchanged && n)
         HIPCHK(hipMemcpyAsync(b->d_descs, b->descs.data(), n * sizeof(IntegrateArgs), hipMemcpyHostToDevice, b->gs));
     if (!b->tuned) {
-        TuneKey key{ilog2(std::max<int64_t>(b->total_pairs, 1)), ilog2(std::max<int64_t>(b->n_items, 1)),
-                    n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0};
-        auto it = tune_cache().find(key);
-        if (it != tune_cache().end()) {
-            b->block = it->second.block;
-            b->grid = b->n_cu * it->second.wg_per_cu;
-            b->tune_ms = it->second.ms;
-        } else {
-            const int blocks[2] = {128, 256};
-            const int wpc[4] = {2, 3, 4, 6};
-            double best = 1e30;
-            TuneVal bv{256, 3, 0.0};
-            for (int bi = 0; bi < 2; ++bi)
-                for (int wi = 0; wi < 4; ++wi) {
-                    // 3 waves per SIMD at most: 12 waves per CU
-                    if ((blocks[bi] / 64) * wpc[wi] > 12) continue;
-                    double ms = time_integrate(b, blocks[bi], b->n_cu * wpc[wi]);
-                    if (ms < best) {
-                        best = ms;
-                        bv = TuneVal{blocks[bi], wpc[wi], ms};
-                    }
+        for (nlfem_batch::Group& G : b->groups) {
+            TuneKey key{ilog2(std::max<int64_t>(G.pairs, 1)), ilog2(std::max<int64_t>(G.n_items, 1)),
+                        n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0, G.per_cu};
+            auto it = tune_cache().find(key);
+            if (it == tune_cache().end()) {
+                const int blocks[2] = {128, 256};
+                TuneVal bv{256, 1e30};
+                for (int bi = 0; bi < 2; ++bi) {
+                    const double ms = time_integrate(b, G, blocks[bi]);
+                    if (ms < bv.ms) bv = TuneVal{blocks[bi], ms};
                 }
-            tune_cache()[key] = bv;
-            b->block = bv.block;
-            b->grid = b->n_cu * bv.wg_per_cu;
-            b->tune_ms = bv.ms;
+                it = tune_cache().emplace(key, bv).first;
+            }
+            G.block = it->second.block;
+            G.tune_ms = it->second.ms;
         }
         b->tuned = true;
     }
@@ -1014,7 +1042,7 @@ nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, con
             b->graph = nullptr;
         }
         HIPCHK(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
-        nlfem_status st = batch_enqueue(b, gcur.data(), b->gs, b->block, b->grid);
+        nlfem_status st = batch_enqueue(b, gcur.data(), b->gs);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(b->gs, &g);
         if (st != NLFEM_OK) return st;
@@ -1050,9 +1078,17 @@ nlfem_status nlfem_batch_system(const nlfem_batch* b, int32_t i, const int64_t**
 nlfem_status nlfem_batch_tuning(const nlfem_batch* b, int32_t* block, int32_t* grid, double* tuned_integrate_ms,
                                 double* last_graph_ms) {
     if (!b) return NLFEM_E_INVALID_ARG;
-    if (block) *block = b->block;
-    if (grid) *grid = b->grid;
-    if (tuned_integrate_ms) *tuned_integrate_ms = b->tune_ms;
+    // workgroup size of the group with the most pairs and its number of
+    // workgroups (one per work item); time summed over the groups
+    const nlfem_batch::Group* top = nullptr;
+    double ms = 0.0;
+    for (const nlfem_batch::Group& G : b->groups) {
+        ms += G.tune_ms;
+        if (!top || G.pairs > top->pairs) top = &G;
+    }
+    if (block) *block = top ? top->block : 0;
+    if (grid) *grid = top ? (int32_t)std::min<int64_t>(top->n_items, 0x7fffffff) : 0;
+    if (tuned_integrate_ms) *tuned_integrate_ms = ms;
     if (last_graph_ms) *last_graph_ms = b->last_ms;
     return NLFEM_OK;
 }

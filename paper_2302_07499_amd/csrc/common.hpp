@@ -118,10 +118,9 @@ struct IntegrateArgs {
     int64_t gstride;           // = K
 };
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
-// persistent integration over work items (mesh index, outer position); block 128 or 256
-hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
-                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
-                                  hipStream_t s);
+// one workgroup per work item (mesh, outer position), in list order; block 128 or 256
+hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
+                                  bool vr, int block, hipStream_t s);
 size_t integrate_lds_bytes(int umax);
 // per-pair moments of outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k,
 // out_S [slots][15], out_qm [slots][3] = (q, m, class)

@@ -79,9 +79,10 @@ __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned 
 // each thread's own T0 words [4][2][BLOCK] (every fold of a wave targets the
 // same T0[k], so the threads sum privately and the block adds the slots up at
 // the end: the same integers, without same-address atomics), Ve [umax], and
-// the 4 outer points.
-template <typename T, int BLOCK, bool VR>
-__device__ __forceinline__ void integrate_outer(const IntegrateArgs& a, int64_t oi, unsigned long long* smem64,
+// the 4 outer points.  A is IntegrateArgs, or the same type in the constant
+// address space for descriptors read from a device table.
+template <typename T, int BLOCK, bool VR, typename A>
+__device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
     const int umax = a.umax;
     unsigned long long* R = smem64;             // coarse [4][umax]
@@ -210,28 +211,26 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(Integr
     integrate_outer<T, 256, VR>(a, (int64_t)blockIdx.x, smem64, P);
 }
 
-// Persistent batched integration: every workgroup takes work items (mesh,
-// outer tet) from a device queue until it is empty.  Items are ordered by
-// decreasing estimated cost; each item's results depend on the item only.
+// descriptors of a batch are read-only for the whole launch: read through the
+// constant address space so that they load into scalar registers, and can be
+// loaded again instead of being held, as kernel arguments are
+typedef const __attribute__((address_space(4))) IntegrateArgs ConstArgs;
+
+// One workgroup per work item (mesh, outer position), in list order: the
+// dispatcher starts workgroups in increasing index as slots free up, so a
+// longest-first list is taken longest first without a software queue.
 template <typename T, int BLOCK, bool VR>
-__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batch(const IntegrateArgs* descs, const int2* items,
-                                                           int64_t n_items, unsigned long long* head) {
+__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_items(const IntegrateArgs* descs,
+                                                                                 const int2* items) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
-    __shared__ long long cur;
-    while (true) {
-        if (threadIdx.x == 0) cur = (long long)atomicAdd(head, 1ull);
-        __syncthreads();
-        const long long it = cur;
-        __syncthreads();
-        if (it >= n_items) break;
-        const int2 item = items[it];
-        integrate_outer<T, BLOCK, VR>(descs[item.x], (int64_t)item.y, smem64, P);
-        __syncthreads();
-    }
+    const int2 item = items[blockIdx.x];
+    const int mesh = __builtin_amdgcn_readfirstlane(item.x);
+    const int pos = __builtin_amdgcn_readfirstlane(item.y);
+    ConstArgs* d = (ConstArgs*)(descs + mesh);
+    integrate_outer<T, BLOCK, VR>(*d, (int64_t)pos, smem64, P);
 }
 
-__global__ void k_reset_u64(unsigned long long* p) { *p = 0ull; }
 
 // per-pair moments for outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k
 template <typename T, bool VR>
@@ -322,27 +321,27 @@ hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
-                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
-                                  hipStream_t s) {
-    size_t sh = integrate_lds_bytes(umax);
-    k_reset_u64<<<1, 1, 0, s>>>(head);
-    if (n_items <= 0) return hipGetLastError();
+hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
+                                  bool vr, int block, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (n_items > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t sh = integrate_lds_bytes(umax);
+    const unsigned g = (unsigned)n_items;
     if (block == 128) {
         if (vr) {
-            if (fp32) k_integrate_batch<float, 128, true><<<grid, 128, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 128, true><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+            if (fp32) k_integrate_items<float, 128, true><<<g, 128, sh, s>>>(descs, items);
+            else k_integrate_items<double, 128, true><<<g, 128, sh, s>>>(descs, items);
         } else {
-            if (fp32) k_integrate_batch<float, 128, false><<<grid, 128, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 128, false><<<grid, 128, sh, s>>>(descs, items, n_items, head);
+            if (fp32) k_integrate_items<float, 128, false><<<g, 128, sh, s>>>(descs, items);
+            else k_integrate_items<double, 128, false><<<g, 128, sh, s>>>(descs, items);
         }
     } else {
         if (vr) {
-            if (fp32) k_integrate_batch<float, 256, true><<<grid, 256, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 256, true><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+            if (fp32) k_integrate_items<float, 256, true><<<g, 256, sh, s>>>(descs, items);
+            else k_integrate_items<double, 256, true><<<g, 256, sh, s>>>(descs, items);
         } else {
-            if (fp32) k_integrate_batch<float, 256, false><<<grid, 256, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 256, false><<<grid, 256, sh, s>>>(descs, items, n_items, head);
+            if (fp32) k_integrate_items<float, 256, false><<<g, 256, sh, s>>>(descs, items);
+            else k_integrate_items<double, 256, false><<<g, 256, sh, s>>>(descs, items);
         }
     }
     return hipGetLastError();

@@ -1,4 +1,4 @@
-"""Batched assembly (one persistent fused launch replayed from a HIP graph):
+"""Batched assembly (integration launches grouped by LDS footprint, replayed from a HIP graph):
 each mesh's result equals its single-mesh assembly bitwise, on every graph
 replay, and matches the oracle."""
 import sys

@@ -344,7 +344,7 @@ def main():
     traffic, tinfo = recorded_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_integrate<double>", "kernel_ms": round(t_int * 1e3, 3)}
+                "kernel": "k_integrate<double, false>", "kernel_ms": round(t_int * 1e3, 3)}
     if traffic is None:
         roofline["traffic_note"] = tinfo
     else:

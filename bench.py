@@ -21,6 +21,12 @@ Strategies: the same workload assembled with the other ball approximations
 fullcaps value, and fullcaps with the n_in = 3 caps sampled on the corner tet
 E - U_I, with the seed-to-seed spread of the matrix entries in both modes.
 
+Convergence: the paper's 3D accuracy experiment (Sec. 5) on synthetic meshes:
+Omega = (0,1)^3, delta = 0.1, u = prod x_d (1 - x_d), Kuhn meshes h = 1/m
+(m = 16..40) with a collar of whole cubes, N = 64, FP64; per strategy and level
+the assembly time, CG iterations, L2 error, observed order and the paper's
+efficiency ratio lambda.
+
 Serving: requests (n ~ U{8..40}, delta/h ~ U[2,5], N in {32,64}, FP64 /
 FP32-local 50/50) through the request server: saturation throughput with all
 requests queued at once, then a Poisson stream at 0.9x that rate for the
@@ -32,6 +38,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -193,6 +200,61 @@ def run_precision(P, mg, dev, args):
                                                      "ms": round(cg_ms, 2)}, "strategies": strategies}
 
 
+def run_convergence(P, mg, dev, args):
+    """The paper's 3D accuracy experiment (Sec. 5) on synthetic meshes: for
+    each strategy and mesh level, the assembly time (plan + numeric, HIP
+    synchronised wall clock), a CG solve, the L2(Omega) error against the
+    manufactured u, the observed order and the efficiency ratio
+    lambda_n = -log(e_{n-1}/e_n) / log(t_{n-1}/t_n)."""
+    import torch
+    from meshgen import convergence as cv
+    levels = [int(v) for v in args.convergence_levels.split(",") if v]
+    strategies = ["fullcaps", "nocaps", "barycenter", "overlap", "inside"]
+    out = {st: {"m": [], "h": [], "h_avg": [], "l2_error": [], "order": [None], "assembly_ms": [],
+                "lambda": [None], "cg_iters": [], "pairs": []} for st in strategies}
+    for m in levels:
+        pb = mg.convergence_problem(m, mc_samples=args.convergence_samples)
+        mesh = pb.mesh
+        reg = pb.tet_region.astype(bool)
+        X = mesh.coords[mesh.tets[reg]]
+        edges = [np.linalg.norm(X[:, a] - X[:, b], axis=1) for a in range(4) for b in range(a + 1, 4)]
+        h_avg = float(np.mean(edges))
+        mm, keep = dev.mesh(mesh.coords, mesh.tets, pb.vertex_free, pb.tet_region)
+        d_f = dev.to_dev(pb.f_qp, torch.float64)
+        d_g = dev.to_dev(pb.g_nodal, torch.float64)
+        for st in strategies:
+            prm = P.nlfem_params(pb.delta, pb.psi, pb.mc_samples, pb.seed, P.NLFEM_FP64, None, P.strategy_id(st),
+                                 P.cap_sampling_id("whole"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = P.Plan(dev, P.nlfem_plan_create(dev.ctx, mm, prm))
+            sysm = plan.alloc_system()
+            P.nlfem_assemble(plan.handle, d_f, d_g, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.fc_row_ptr,
+                             sysm.fc_col, sysm.fc_val, sysm.rhs, sysm.free_to_vertex, ctx=dev.ctx)
+            torch.cuda.synchronize()
+            t_asm = time.perf_counter() - t0
+            x, it, rr, ok = plan.solve(sysm, rtol=1e-12)
+            U = pb.g_nodal.copy()
+            U[sysm.free_to_vertex[:sysm.n_free].cpu().numpy()] = x.cpu().numpy()
+            err = cv.l2_error(mesh.coords, mesh.tets, pb.tet_region, U)
+            r = out[st]
+            if r["l2_error"]:
+                e0, t_0, h0 = r["l2_error"][-1], r["assembly_ms"][-1] * 1e-3, r["h"][-1]
+                r["order"].append(round(math.log(e0 / err) / math.log(h0 / (1.0 / m)), 3))
+                r["lambda"].append(round(-math.log(e0 / err) / math.log(t_0 / t_asm), 3))
+            r["m"].append(m); r["h"].append(1.0 / m); r["h_avg"].append(round(h_avg, 5))
+            r["l2_error"].append(err); r["assembly_ms"].append(round(1e3 * t_asm, 3))
+            r["cg_iters"].append(int(it)); r["pairs"].append(int(sum(plan.info["pair_counts"])))
+            log(f"convergence m={m} {st}: L2 error {err:.4e}, assembly {1e3 * t_asm:.1f} ms, CG {it} it")
+            plan.destroy()
+            del sysm, x
+        del keep, d_f, d_g
+    return {"workload": "Omega=(0,1)^3, delta=0.1, u=prod x_d(1-x_d), f=-Lu exact at the outer rule points, "
+                        f"g=u nodal; Kuhn meshes h=1/m with a collar of whole cubes, jitter 0.1h; "
+                        f"N={args.convergence_samples}; FP64; CG rtol 1e-12",
+            "strategies": out}
+
+
 def run_batched(P, mg, dev, args):
     import torch
     pbs = mg.batched_problems(args.batched_count)
@@ -299,6 +361,10 @@ def main():
     ap.add_argument("--serving-full", action="store_true", help="500 requests at 0.5x and 0.9x saturation")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-strategies", action="store_true", help="skip the nocaps/overlap/inside/barycenter lines")
+    ap.add_argument("--no-convergence", action="store_true", help="skip the L2-error convergence study")
+    ap.add_argument("--convergence-levels", default="16,20,24,28,32,36,40",
+                    help="cubes per unit length m (h = 1/m) of the convergence meshes")
+    ap.add_argument("--convergence-samples", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--pool-gb", type=int, default=160)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -349,6 +415,12 @@ def main():
         roofline["traffic_note"] = tinfo
     else:
         roofline.update(tinfo)
+
+    convergence = None
+    if not args.no_convergence:
+        log("convergence workload")
+        convergence = run_convergence(P, mg, dev, args)
+        P.nlfem_trim(dev.ctx)
 
     batched = None
     if not args.no_batched:
@@ -412,6 +484,7 @@ def main():
                            "assemble": round(float(np.mean(tk64[:, 5])), 3)},
         "cg": pr["cg"],
         "strategies_fp64": pr["strategies"],
+        "convergence": convergence,
         "batched": batched,
         "serving": serving,
         "roofline": roofline,

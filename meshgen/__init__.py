@@ -141,6 +141,7 @@ class Problem:
     info: dict = field(default_factory=dict)
     strategy: str = "fullcaps"  # ball approximation: fullcaps, nocaps, overlap, inside, barycenter
     cap_sampling: str = "whole"  # cap samples on the whole element, or on E_m minus U_I ("outside_ui")
+    tet_region: np.ndarray | None = None  # explicit T_Omega mask; None: tets with a free vertex
 
 
 def make_problem(name: str, n: int, delta_over_h: float | None = None, delta: float | None = None,
@@ -219,3 +220,6 @@ def outer_subset_mask(n_tets: int, fraction: float, seed: int = 7) -> np.ndarray
     """Deterministic subset of outer tets (1 = assemble this outer tet)."""
     rng = np.random.default_rng(seed)
     return (rng.random(n_tets) < fraction).astype(np.uint8)
+
+
+from .convergence import convergence_problem  # noqa: E402  (the convergence workload)

@@ -219,5 +219,6 @@ def problem_assemble(pb, outer_mask=None):
     m = pb.mesh
     return assemble(m.coords, m.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
                     f_qp=pb.f_qp, g_nodal=pb.g_nodal, outer_mask=outer_mask,
+                    tet_region=getattr(pb, "tet_region", None),
                     strategy=getattr(pb, "strategy", "fullcaps"),
                     cap_sampling=getattr(pb, "cap_sampling", "whole"))

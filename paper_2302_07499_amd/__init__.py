@@ -331,7 +331,7 @@ class Device:
     def plan_problem(self, pb, outer_mask=None):
         mm = pb.mesh
         return self.plan(mm.coords, mm.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
-                         precision=pb.precision, outer_mask=outer_mask,
+                         precision=pb.precision, outer_mask=outer_mask, tet_region=getattr(pb, "tet_region", None),
                          strategy=getattr(pb, "strategy", "fullcaps"),
                          cap_sampling=getattr(pb, "cap_sampling", "whole"))
 
@@ -400,7 +400,7 @@ class Batch:
         meshes = (nlfem_mesh * max(self.n, 1))()
         params = (nlfem_params * max(self.n, 1))()
         for i, pb in enumerate(problems):
-            m, keep = dev.mesh(pb.mesh.coords, pb.mesh.tets, pb.vertex_free)
+            m, keep = dev.mesh(pb.mesh.coords, pb.mesh.tets, pb.vertex_free, getattr(pb, "tet_region", None))
             om = None
             if outer_masks is not None and outer_masks[i] is not None:
                 om = dev.to_dev(outer_masks[i], t.uint8)
@@ -496,8 +496,10 @@ class Server:
         f = None if pb.f_qp is None else np.ascontiguousarray(pb.f_qp, dtype=np.float64)
         g = None if pb.g_nodal is None else np.ascontiguousarray(pb.g_nodal, dtype=np.float64)
         om = None if outer_mask is None else np.ascontiguousarray(outer_mask, dtype=np.uint8)
+        tr = getattr(pb, "tet_region", None)
+        tr = None if tr is None else np.ascontiguousarray(tr, dtype=np.uint8)
         m = nlfem_mesh(mesh.n_vertices, mesh.n_tets, coords.ctypes.data, tets.ctypes.data, vfree.ctypes.data,
-                       None, 0)
+                       None if tr is None else tr.ctypes.data, 0)
         prm = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
                            NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
                            None if om is None else om.ctypes.data, strategy_id(getattr(pb, "strategy", "fullcaps")),

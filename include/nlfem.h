@@ -36,6 +36,9 @@ typedef struct nlfem_plan nlfem_plan;
  * sum L_i L_j in 64 bits), which needs N * 2^21 < 2^32.                       */
 #define NLFEM_MAX_MC_SAMPLES 2047
 
+/* Largest per-axis degree of the polynomial g of nlfem_assemble_exact_g.   */
+#define NLFEM_MAX_G_DEGREE 4
+
 typedef enum {
     NLFEM_OK = 0,
     NLFEM_E_INVALID_ARG = 1,   /* null pointer, delta <= 0, N outside [1, 2047], unknown strategy or
@@ -153,6 +156,25 @@ nlfem_status nlfem_assemble(nlfem_plan *plan, const double *f_qp, const double *
                             int64_t *ff_row_ptr, int32_t *ff_col, double *ff_val,
                             int64_t *fc_row_ptr, int32_t *fc_col, double *fc_val, double *rhs,
                             int32_t *free_to_vertex);
+
+/* As nlfem_assemble, with the paper-exact right-hand side: the inner integral
+ * of g over Omega_I n B_{delta,h}(x) in F_h (eq. Fh) uses g itself at the
+ * inner integration points (the 4-point rule of Sec. 4.2.1 on each IN
+ * element and T_I subtet, and the accepted Monte Carlo samples of the caps)
+ * instead of its nodal interpolant, and b = F_h - sum over the constraint
+ * nodes on the boundary of Omega of A_h(phi_j, phi_i) g_j (eq. F1.5).  The
+ * matrix blocks are those of nlfem_assemble (A_fc keeps its nodal form); b
+ * differs from nlfem_assemble's by 2 psi sum w phi_i(p) int (g - g_h).
+ * g is the tensor polynomial, a HOST array read during the call:
+ *   g(y) = sum_{a,b,c = 0..g_degree} g_coef[a + n1 (b + n1 c)] y1^a y2^b y3^c,
+ *   n1 = g_degree + 1, 0 <= g_degree <= NLFEM_MAX_G_DEGREE;
+ * g_nodal must hold g at the constrained vertices.  Plans with cap sampling
+ * NLFEM_CAPS_OUTSIDE_UI are rejected (NLFEM_E_UNSUPPORTED).                  */
+nlfem_status nlfem_assemble_exact_g(nlfem_plan *plan, const double *f_qp, const double *g_nodal,
+                                    int32_t g_degree, const double *g_coef,
+                                    int64_t *ff_row_ptr, int32_t *ff_col, double *ff_val,
+                                    int64_t *fc_row_ptr, int32_t *fc_col, double *fc_val, double *rhs,
+                                    int32_t *free_to_vertex);
 
 /* Unpreconditioned FP64 conjugate gradients on a CSR matrix (DEVICE arrays),
  * x holds x0 on entry and the solution on exit.  Stops when

@@ -87,6 +87,13 @@ def u_exact(x: np.ndarray) -> np.ndarray:
     return q[..., 0] * q[..., 1] * q[..., 2]
 
 
+def u_tensor_coef() -> np.ndarray:
+    """u as tensor coefficients G[a, b, c] of y1^a y2^b y3^c: the product of
+    x (1 - x) = x - x^2 in each coordinate."""
+    q = np.array([0.0, 1.0, -1.0])
+    return np.einsum("a,b,c->abc", q, q, q)
+
+
 def ball_even_moments(delta: float) -> tuple[float, float, float, float]:
     """|B|, int_B z1^2, int_B z1^2 z2^2, int_B z1^2 z2^2 z3^2 over the ball of
     radius delta (radial integral times the sphere averages 1/3, 1/15, 1/105)."""
@@ -145,6 +152,7 @@ def convergence_problem(m: int, delta: float = 0.1, mc_samples: int = 64, seed: 
                  info={"m": m, "h": 1.0 / m, "collar": collar, "delta_over_h": delta * m, "jitter": jitter},
                  strategy=strategy)
     pb.tet_region = mesh.info["tet_in_omega"].copy()
+    pb.g_poly = u_tensor_coef()
     return pb
 
 

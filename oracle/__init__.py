@@ -35,7 +35,7 @@ class OrProblem(C.Structure):
                 ("tet_region", C.c_void_p), ("delta", C.c_double), ("psi", C.c_double),
                 ("mc_samples", C.c_int32), ("seed", C.c_uint64), ("outer_mask", C.c_void_p),
                 ("f_qp", C.c_void_p), ("g_nodal", C.c_void_p), ("strategy", C.c_int32),
-                ("cap_sampling", C.c_int32)]
+                ("cap_sampling", C.c_int32), ("g_degree", C.c_int32), ("g_coef", C.c_void_p)]
 
 
 # ball approximation strategies (Sec. 4.1), as numbered in the oracle
@@ -165,14 +165,27 @@ def pair_geometry(coords, tets, n, k, m, delta):
             "split": split.value}
 
 
+def gpoly_coef(g_poly):
+    """[a, b, c] array of the coefficients of y1^a y2^b y3^c -> (degree, flat
+    array with index a + n1 (b + n1 c))."""
+    G = np.asarray(g_poly, dtype=np.float64)
+    n1 = G.shape[0]
+    assert G.shape == (n1, n1, n1)
+    return n1 - 1, np.ascontiguousarray(G.transpose(2, 1, 0)).reshape(-1)
+
+
 def assemble(coords, tets, vertex_free, delta, psi, mc_samples, seed, f_qp=None, g_nodal=None,
-             tet_region=None, outer_mask=None, strategy="fullcaps", cap_sampling="whole"):
-    """Full oracle assembly.  Returns a dict of numpy arrays (CSR blocks + rhs)."""
+             tet_region=None, outer_mask=None, strategy="fullcaps", cap_sampling="whole", g_poly=None):
+    """Full oracle assembly.  Returns a dict of numpy arrays (CSR blocks + rhs).
+    With g_poly (tensor coefficients [a, b, c]) the right-hand side uses g
+    itself inside the inner integrals over Omega_I (eqs. Fh, F1.5)."""
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
     vf = _c(vertex_free, np.uint8); tr = _c(tet_region, np.uint8); om = _c(outer_mask, np.uint8)
     fq = _c(f_qp, np.float64); gn = _c(g_nodal, np.float64)
+    gdeg, gc = (0, None) if g_poly is None else gpoly_coef(g_poly)
     P = OrProblem(coords.shape[0], tets.shape[0], _p(coords), _p(tets), _p(vf), _p(tr), delta, psi,
-                  mc_samples, seed, _p(om), _p(fq), _p(gn), _strategy(strategy), _caps(cap_sampling))
+                  mc_samples, seed, _p(om), _p(fq), _p(gn), _strategy(strategy), _caps(cap_sampling),
+                  gdeg, _p(gc))
     S = OrSystem()
     rc = lib().or_assemble(C.byref(P), C.byref(S))
     if rc != 0:
@@ -215,10 +228,11 @@ def cg(row_ptr, col, val, b, rtol=1e-10, max_iter=None, x0=None):
     return x, it.value, rr.value, rc
 
 
-def problem_assemble(pb, outer_mask=None):
+def problem_assemble(pb, outer_mask=None, exact_g=False):
     m = pb.mesh
     return assemble(m.coords, m.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
                     f_qp=pb.f_qp, g_nodal=pb.g_nodal, outer_mask=outer_mask,
+                    g_poly=pb.g_poly if exact_g else None,
                     tet_region=getattr(pb, "tet_region", None),
                     strategy=getattr(pb, "strategy", "fullcaps"),
                     cap_sampling=getattr(pb, "cap_sampling", "whole"))

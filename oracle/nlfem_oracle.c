@@ -696,6 +696,9 @@ typedef struct {
     const double *g_nodal;     /* optional [n_vertices] */
     int32_t strategy;          /* OR_FULLCAPS .. OR_BARYCENTER */
     int32_t cap_sampling;      /* 1: n_in = 3 caps sampled on the corner tet E - U_I */
+    int32_t g_degree;          /* per-axis degree of g_coef */
+    const double *g_coef;      /* optional: g as a tensor polynomial -> the right-hand side of
+                                  eq. F1.5 with g itself inside the inner integrals of eq. Fh */
 } or_problem;
 
 typedef struct {
@@ -787,11 +790,48 @@ static void local_node(void *user, const double lam[4], double w, int is_mc) {
         for (int v = 0; v < M->nu; ++v) M->L[u][v] += (w * a[u]) * a[v];
 }
 
+/* g(y) = sum over a, b, c in 0..deg of coef[a + n1 (b + n1 c)] y1^a y2^b y3^c,
+ * n1 = deg + 1, summed monomial by monomial */
+static double gpoly_value(const double *coef, int deg, const double y[3]) {
+    int n1 = deg + 1;
+    double s = 0.0;
+    for (int c = 0; c <= deg; ++c)
+        for (int b = 0; b <= deg; ++b)
+            for (int a = 0; a <= deg; ++a) {
+                double mono = 1.0;
+                for (int e = 0; e < a; ++e) mono *= y[0];
+                for (int e = 0; e < b; ++e) mono *= y[1];
+                for (int e = 0; e < c; ++e) mono *= y[2];
+                s += coef[a + n1 * (b + n1 * c)] * mono;
+            }
+    return s;
+}
+
+/* inner integral over the pair's nodes of 1 (s0) and of g (gint); a node's
+ * point is y = sum_l lambda_l X_l */
+typedef struct {
+    const double (*X)[3];
+    const double *coef;
+    int deg;
+    double s0, gint;
+} ginner;
+
+static void g_node(void *user, const double lam[4], double w, int is_mc) {
+    (void)is_mc;
+    ginner *a = (ginner *)user;
+    double y[3];
+    for (int i = 0; i < 3; ++i)
+        y[i] = ((lam[0] * a->X[0][i] + lam[1] * a->X[1][i]) + lam[2] * a->X[2][i]) + lam[3] * a->X[3][i];
+    a->s0 += w;
+    a->gint += w * gpoly_value(a->coef, a->deg, y);
+}
+
 static int validate(const or_problem *P) {
     if (!P || P->n_vertices < 0 || P->n_tets < 0) return 1;
     if (!(P->delta > 0.0) || P->mc_samples < 1) return 1;
     if (P->strategy < OR_FULLCAPS || P->strategy > OR_BARYCENTER) return 1;
     if (P->cap_sampling != 0 && P->cap_sampling != 1) return 1;
+    if (P->g_coef && (P->g_degree < 0 || P->g_degree > 4 || P->cap_sampling != 0)) return 1;
     if (P->n_tets > 0 && (!P->coords || !P->tets || !P->vertex_free)) return 1;
     for (int64_t i = 0; i < 4 * P->n_tets; ++i)
         if (P->tets[i] < 0 || P->tets[i] >= P->n_vertices) return 2;
@@ -904,6 +944,35 @@ int or_assemble(const or_problem *P, or_system *S) {
                  * right-hand side through the nodal constraint values).     */
                 double fm = region[m] ? 1.0 : 2.0;
                 double scale = (P->psi * fm) * wk;
+                if (P->g_coef) {
+                    /* eq. F1.5 with F_h of eq. Fh, term by term:
+                     * T_Omega inner element: - A_h(phi_j, phi_i) g_j for the
+                     *   boundary nodes j, from the W term of eq. notreplaced;
+                     * T_Omega_I inner element: + 2 psi w phi_i(p) int g (the
+                     *   F_h term), and - the N term 2 psi w phi_j(p) phi_i(p)
+                     *   int 1 times g_j for the boundary nodes j of E_n.       */
+                    if (region[m]) {
+                        for (int u = 0; u < M.nu; ++u) {
+                            int32_t fu = free_id[M.U[u]];
+                            if (fu < 0) continue;
+                            for (int v = 0; v < M.nu; ++v)
+                                if (free_id[M.U[v]] < 0 && P->g_nodal)
+                                    S->rhs[fu] -= (scale * M.L[u][v]) * P->g_nodal[M.U[v]];
+                        }
+                    } else {
+                        ginner gi = {c.X, P->g_coef, P->g_degree, 0.0, 0.0};
+                        visit_nodes(&c, g_node, &gi);
+                        for (int u = 0; u < 4; ++u) {
+                            int32_t fu = free_id[M.U[u]];
+                            if (fu < 0) continue;
+                            double pu = (2.0 * P->psi) * (wk * M.c[u]);
+                            S->rhs[fu] += pu * gi.gint;
+                            for (int v = 0; v < 4; ++v)
+                                if (free_id[M.U[v]] < 0 && P->g_nodal)
+                                    S->rhs[fu] -= ((pu * M.c[v]) * gi.s0) * P->g_nodal[M.U[v]];
+                        }
+                    }
+                }
                 for (int u = 0; u < M.nu; ++u) {
                     int32_t fu = free_id[M.U[u]];
                     if (fu < 0) continue;
@@ -943,8 +1012,8 @@ int or_assemble(const or_problem *P, or_system *S) {
         if (free_id[c] >= 0) { S->ff_col[iff] = free_id[c]; S->ff_val[iff++] = T.a[i].val; }
         else { S->fc_col[ifc] = c; S->fc_val[ifc++] = T.a[i].val; }
     }
-    /* b = F_h - A_fc g  (nodal constraint values) */
-    if (P->g_nodal) {
+    /* b = F_h - A_fc g  (nodal constraint values; the exact-g form was summed above) */
+    if (P->g_nodal && !P->g_coef) {
         for (int64_t r = 0; r < nf; ++r) {
             double acc = 0.0;
             for (int64_t e = S->fc_row_ptr[r]; e < S->fc_row_ptr[r + 1]; ++e)

@@ -93,7 +93,8 @@ class nlfem_server_counters(C.Structure):
 
 
 EXPORTS = ["nlfem_create", "nlfem_destroy", "nlfem_last_error", "nlfem_memory_in_use", "nlfem_trim",
-           "nlfem_rule_constants", "nlfem_plan_create", "nlfem_plan_info", "nlfem_assemble", "nlfem_cg",
+           "nlfem_rule_constants", "nlfem_plan_create", "nlfem_plan_info", "nlfem_assemble",
+           "nlfem_assemble_exact_g", "nlfem_cg",
            "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings",
            "nlfem_batch_create", "nlfem_batch_info", "nlfem_batch_assemble", "nlfem_batch_system",
            "nlfem_batch_tuning", "nlfem_batch_destroy",
@@ -125,6 +126,7 @@ def load():
     L.nlfem_plan_info.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                   C.POINTER(C.c_size_t)]
     L.nlfem_assemble.argtypes = [P] * 11
+    L.nlfem_assemble_exact_g.argtypes = [P, P, P, C.c_int32, P] + [P] * 8
     L.nlfem_cg.argtypes = [P, i64, P, P, P, P, P, C.c_double, C.c_int32, C.POINTER(C.c_int32),
                            C.POINTER(C.c_double)]
     L.nlfem_plan_destroy.argtypes = [P]
@@ -225,6 +227,25 @@ def nlfem_assemble(plan, f_qp, g_nodal, ff_row_ptr, ff_col, ff_val, fc_row_ptr, 
                    free_to_vertex, ctx=None):
     st = load().nlfem_assemble(plan, _ptr(f_qp), _ptr(g_nodal), _ptr(ff_row_ptr), _ptr(ff_col), _ptr(ff_val),
                                _ptr(fc_row_ptr), _ptr(fc_col), _ptr(fc_val), _ptr(rhs), _ptr(free_to_vertex))
+    _check(st, ctx)
+
+
+def gpoly_coef(g_poly):
+    """[a, b, c] array of the coefficients of y1^a y2^b y3^c -> (degree, flat
+    float64 array with index a + n1 (b + n1 c), n1 = degree + 1)."""
+    G = np.asarray(g_poly, dtype=np.float64)
+    n1 = G.shape[0]
+    if G.shape != (n1, n1, n1):
+        raise ValueError("g_poly must be a cube array [a, b, c]")
+    return n1 - 1, np.ascontiguousarray(G.transpose(2, 1, 0)).reshape(-1)
+
+
+def nlfem_assemble_exact_g(plan, f_qp, g_nodal, g_poly, ff_row_ptr, ff_col, ff_val, fc_row_ptr, fc_col, fc_val,
+                           rhs, free_to_vertex, ctx=None):
+    deg, coef = gpoly_coef(g_poly)
+    st = load().nlfem_assemble_exact_g(plan, _ptr(f_qp), _ptr(g_nodal), deg, coef.ctypes.data, _ptr(ff_row_ptr),
+                                       _ptr(ff_col), _ptr(ff_val), _ptr(fc_row_ptr), _ptr(fc_col), _ptr(fc_val),
+                                       _ptr(rhs), _ptr(free_to_vertex))
     _check(st, ctx)
 
 
@@ -364,14 +385,21 @@ class Plan:
                       t.empty(max(nf, 1), dtype=t.float64, device=d), t.empty(max(nf, 1), dtype=t.int32, device=d),
                       dict(self.info))
 
-    def assemble(self, f_qp=None, g_nodal=None, out: System | None = None) -> System:
+    def assemble(self, f_qp=None, g_nodal=None, out: System | None = None, g_poly=None) -> System:
+        """g_poly (tensor coefficients [a, b, c] of g): the paper-exact
+        right-hand side (nlfem_assemble_exact_g); else nodal g only."""
         t = self.dev.torch
         sysm = out if out is not None else self.alloc_system()
         fq = None if f_qp is None else (f_qp if isinstance(f_qp, t.Tensor) else self.dev.to_dev(f_qp, t.float64))
         gn = None if g_nodal is None else (g_nodal if isinstance(g_nodal, t.Tensor)
                                            else self.dev.to_dev(g_nodal, t.float64))
-        nlfem_assemble(self.handle, fq, gn, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.fc_row_ptr,
-                       sysm.fc_col, sysm.fc_val, sysm.rhs, sysm.free_to_vertex, ctx=self.dev.ctx)
+        if g_poly is None:
+            nlfem_assemble(self.handle, fq, gn, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.fc_row_ptr,
+                           sysm.fc_col, sysm.fc_val, sysm.rhs, sysm.free_to_vertex, ctx=self.dev.ctx)
+        else:
+            nlfem_assemble_exact_g(self.handle, fq, gn, g_poly, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val,
+                                   sysm.fc_row_ptr, sysm.fc_col, sysm.fc_val, sysm.rhs, sysm.free_to_vertex,
+                                   ctx=self.dev.ctx)
         sysm._keep = (fq, gn)
         return sysm
 

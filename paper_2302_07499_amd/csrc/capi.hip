@@ -769,9 +769,13 @@ nlfem_status nlfem_plan_info(const nlfem_plan* pl, int64_t* n_free, int64_t* nnz
     return NLFEM_OK;
 }
 
-nlfem_status nlfem_assemble(nlfem_plan* pl, const double* f_qp, const double* g_nodal, int64_t* ff_row_ptr,
-                            int32_t* ff_col, double* ff_val, int64_t* fc_row_ptr, int32_t* fc_col, double* fc_val,
-                            double* rhs, int32_t* free_to_vertex) {
+namespace {
+
+// numeric phase; g_deg < 0: nodal constraint values only
+nlfem_status assemble_impl(nlfem_plan* pl, const double* f_qp, const double* g_nodal, int32_t g_deg,
+                           const double* g_coef, int64_t* ff_row_ptr, int32_t* ff_col, double* ff_val,
+                           int64_t* fc_row_ptr, int32_t* fc_col, double* fc_val, double* rhs,
+                           int32_t* free_to_vertex) {
     if (!pl) return NLFEM_E_INVALID_ARG;
     nlfem_ctx* c = pl->ctx;
     if (pl->nnz_ff > 0 && !ff_val) return fail(c, NLFEM_E_INVALID_ARG, "ff_val is required");
@@ -789,6 +793,13 @@ nlfem_status nlfem_assemble(nlfem_plan* pl, const double* f_qp, const double* g_
     Timer tint(s);
     HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
     HIPCHK(launch_integrate(a, pl->precision == NLFEM_FP32_LOCAL, s));
+    if (g_deg >= 0) {
+        const size_t nc = (size_t)(g_deg + 1) * (g_deg + 1) * (g_deg + 1);
+        TMP(t_coef, nc * sizeof(double));
+        // pageable source: the call returns once the host data is staged
+        HIPCHK(hipMemcpyAsync(t_coef.p, g_coef, nc * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(launch_exact_g(a, g_nodal, t_coef.as<double>(), g_deg, s));
+    }
     pl->times[3] = tint.stop();
     Timer tred(s);
     nlfem_status st = enqueue_rows(c, pl, g_nodal, ff_val, fc_val, rhs, s);
@@ -796,6 +807,30 @@ nlfem_status nlfem_assemble(nlfem_plan* pl, const double* f_qp, const double* g_
     pl->times[4] = tred.stop();
     pl->times[5] = total.stop();
     return NLFEM_OK;
+}
+
+}  // namespace
+
+nlfem_status nlfem_assemble(nlfem_plan* pl, const double* f_qp, const double* g_nodal, int64_t* ff_row_ptr,
+                            int32_t* ff_col, double* ff_val, int64_t* fc_row_ptr, int32_t* fc_col, double* fc_val,
+                            double* rhs, int32_t* free_to_vertex) {
+    return assemble_impl(pl, f_qp, g_nodal, -1, nullptr, ff_row_ptr, ff_col, ff_val, fc_row_ptr, fc_col, fc_val, rhs,
+                         free_to_vertex);
+}
+
+nlfem_status nlfem_assemble_exact_g(nlfem_plan* pl, const double* f_qp, const double* g_nodal, int32_t g_degree,
+                                    const double* g_coef, int64_t* ff_row_ptr, int32_t* ff_col, double* ff_val,
+                                    int64_t* fc_row_ptr, int32_t* fc_col, double* fc_val, double* rhs,
+                                    int32_t* free_to_vertex) {
+    if (!pl) return NLFEM_E_INVALID_ARG;
+    nlfem_ctx* c = pl->ctx;
+    static_assert(NLFEM_MAX_G_DEGREE == kMaxGDegree, "g degree limit");
+    if (g_degree < 0 || g_degree > NLFEM_MAX_G_DEGREE || !g_coef)
+        return fail(c, NLFEM_E_INVALID_ARG, "g_degree outside [0, NLFEM_MAX_G_DEGREE] or g_coef null");
+    if (pl->cap_sampling != NLFEM_CAPS_WHOLE_ELEMENT)
+        return fail(c, NLFEM_E_UNSUPPORTED, "exact g needs whole-element cap sampling");
+    return assemble_impl(pl, f_qp, g_nodal, g_degree, g_coef, ff_row_ptr, ff_col, ff_val, fc_row_ptr, fc_col, fc_val,
+                         rhs, free_to_vertex);
 }
 
 nlfem_status nlfem_plan_timings(const nlfem_plan* pl, double times[6]) {

@@ -20,6 +20,10 @@ enum : int { S_FULLCAPS = 0, S_NOCAPS = 1, S_OVERLAP = 2, S_INSIDE = 3, S_BARYCE
 constexpr double kAlpha = 0x1.2bbae2a27f932p-1;
 constexpr double kBeta = 0x1.1b06d1d200913p-3;
 
+// exact-g right-hand side: tensor polynomial degree per axis, coefficients
+constexpr int kMaxGDegree = 4;
+constexpr int kMaxGCoef = (kMaxGDegree + 1) * (kMaxGDegree + 1) * (kMaxGDegree + 1);
+
 // Uniform grid over tet bounding-box minimum corners (see k_plan.hip).
 struct Grid {
     double ox, oy, oz;  // origin
@@ -122,6 +126,10 @@ hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
                                   bool vr, int block, hipStream_t s);
 size_t integrate_lds_bytes(int umax);
+// adds the exact-g defect of the T_Omega_I inner integrals to the load terms
+// in oblk (tensor polynomial g of degree deg per axis, coefficients on the
+// device; whole-element cap sampling only)
+hipError_t launch_exact_g(const IntegrateArgs& a, const double* g_nodal, const double* coef, int deg, hipStream_t s);
 // per-pair moments of outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k,
 // out_S [slots][15], out_qm [slots][3] = (q, m, class)
 hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, int64_t o_hi, double* out_S,

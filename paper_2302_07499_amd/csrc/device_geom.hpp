@@ -362,10 +362,11 @@ __device__ __forceinline__ int nth_bit(unsigned m, int n) {
 //             T_I = {0,1,2,4}, {0,2,4,5}, {0,3,4,5}, planes (1,2,4), (2,4,5).
 // Every lane runs the same instruction stream: the three subtets are always
 // evaluated (zero-volume ones for n_in = 1 and n_in = 0), the hull points and
-// planes are picked by selects.
-template <typename T>
-__device__ inline void cut_setup(const double* Xg, const double* p, double d2, const double* r2, double vol,
-                                 CutGeom& g, double* D, double* G, CornerGeom* cr = nullptr) {
+// planes are picked by selects.  sub(v0, v1, v2, v3, V) receives each subtet
+// of T_I as barycentric vertex rows and its volume.
+template <typename Sub>
+__device__ __forceinline__ void cut_build(const double* Xg, const double* p, double d2, const double* r2, double vol,
+                                          CutGeom& g, CornerGeom* cr, Sub&& sub) {
     unsigned in = 0;
 #pragma unroll
     for (int l = 0; l < 4; ++l)
@@ -420,9 +421,9 @@ __device__ inline void cut_setup(const double* Xg, const double* p, double d2, c
         XA[l] = alt ? H4[l] : H5[l];
         YB[l] = alt ? H2[l] : H1[l];
     }
-    subtet_moments<T>(H0, H1, H2, XA, vol * (alt ? d124 : d125), D, G);
-    subtet_moments<T>(H0, YB, H4, H5, vol * (alt ? d245 : d145), D, G);
-    subtet_moments<T>(H0, H3, H4, H5, vol * d345, D, G);
+    sub(H0, H1, H2, XA, vol * (alt ? d124 : d125));
+    sub(H0, YB, H4, H5, vol * (alt ? d245 : d145));
+    sub(H0, H3, H4, H5, vol * d345);
     g.nin = ni;
     g.nplanes = any ? (c2 ? 2 : 1) : 0;
     // planes: c0 through (h3, h4, h5) for n_in = 3, else (h1, h2, alt ? h4 : h5);
@@ -467,6 +468,16 @@ __device__ inline void in_moments(double vol, double* S) {
 #pragma unroll
             for (int j = i; j < 4; ++j) S[k++] += (w * rule_w(r, i)) * rule_w(r, j);
     }
+}
+
+// cut_build with the moments of every subtet added to D and G
+template <typename T>
+__device__ inline void cut_setup(const double* Xg, const double* p, double d2, const double* r2, double vol,
+                                 CutGeom& g, double* D, double* G, CornerGeom* cr = nullptr) {
+    cut_build(Xg, p, d2, r2, vol, g, cr,
+              [&](const double* v0, const double* v1, const double* v2, const double* v3, double V) {
+                  subtet_moments<T>(v0, v1, v2, v3, V, D, G);
+              });
 }
 
 template <typename T>
@@ -670,6 +681,117 @@ __device__ inline void pair_moments(const double* X, double vol, const double* p
     for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
 #pragma unroll
     for (int i = 0; i < 10; ++i) S[5 + i] = G[i] + S[5 + i];
+}
+
+// ---------------------------------------------------------------------------
+// Paper-exact right-hand side (eq. Fh: g itself at the inner integration
+// points).  g is a tensor polynomial
+//   g(y) = sum_{a,b,c = 0..deg} coef[a + n1 (b + n1 c)] y1^a y2^b y3^c,  n1 = deg + 1,
+// evaluated by Horner's rule along y3, then y2, then y1.
+template <int DEG, typename CP>
+__device__ __forceinline__ double gpoly_eval(CP coef, double y1, double y2, double y3) {
+    constexpr int n1 = DEG + 1;
+    double acc = 0.0;
+#pragma unroll
+    for (int a = DEG; a >= 0; --a) {
+        double ay = 0.0;
+#pragma unroll
+        for (int b = DEG; b >= 0; --b) {
+            double bz = 0.0;
+#pragma unroll
+            for (int c = DEG; c >= 0; --c) bz = bz * y3 + coef[a + n1 * (b + n1 * c)];
+            ay = ay * y2 + bz;
+        }
+        acc = acc * y1 + ay;
+    }
+    return acc;
+}
+
+// e = g - g_h at the point with barycentrics lam in the inner tet X ([4][3]),
+// g_h the affine interpolant of the nodal values gv of X's vertices
+template <int DEG, typename CP>
+__device__ __forceinline__ double g_defect_at(const double* X, const double* lam, const double* gv, CP coef) {
+    double y[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[i] = ((lam[0] * X[i] + lam[1] * X[3 + i]) + lam[2] * X[6 + i]) + lam[3] * X[9 + i];
+    const double gh = ((lam[0] * gv[0] + lam[1] * gv[1]) + lam[2] * gv[2]) + lam[3] * gv[3];
+    return gpoly_eval<DEG>(coef, y[0], y[1], y[2]) - gh;
+}
+
+// Integral of e = g - g_h over E_m n B_delta,h(p) with the inner rules of the
+// pair: the 4-point rule of Sec. 4.2.1 on E_m (class IN) or on every subtet
+// of T_I, and, when the caps are part of the pair, the accepted Monte Carlo
+// samples of cut_mc (the same counters, the same acceptance test) with weight
+// |E_m|/N each.  The matrix already carries the g_h part through the nodal
+// constraint values, so this defect is what the right-hand side lacks.
+template <int DEG, typename CP>
+__device__ inline double pair_g_defect(const double* X, double vol, const double* p, double d2, int code, int N,
+                                       bool caps, uint32_t key0, uint32_t key1, uint32_t q, uint32_t m,
+                                       const double* gv, CP coef) {
+    double acc = 0.0;
+    if (code == C_IN) {
+        const double w = vol * 0.25;
+        for (int r = 0; r < 4; ++r) {
+            double lam[4];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) lam[l] = rule_w(r, l);
+            acc += w * g_defect_at<DEG>(X, lam, gv, coef);
+        }
+        return acc;
+    }
+    double r2[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        double dx = X[3 * l] - p[0], dy = X[3 * l + 1] - p[1], dz = X[3 * l + 2] - p[2];
+        r2[l] = (dx * dx + dy * dy) + dz * dz;
+    }
+    CutGeom g;
+    cut_build(X, p, d2, r2, vol, g, nullptr,
+              [&](const double* v0, const double* v1, const double* v2, const double* v3, double V) {
+                  const double w = V * 0.25;
+                  for (int r = 0; r < 4; ++r) {
+                      double lam[4];
+#pragma unroll
+                      for (int l = 0; l < 4; ++l)
+                          lam[l] = ((rule_w(r, 0) * v0[l] + rule_w(r, 1) * v1[l]) + rule_w(r, 2) * v2[l]) +
+                                   rule_w(r, 3) * v3[l];
+                      acc += w * g_defect_at<DEG>(X, lam, gv, coef);
+                  }
+              });
+    if (!caps) return acc;
+    // the sample frame and acceptance test of cut_mc, term for term
+    const double u = 1.0 / 2097152.0;
+    const double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
+    const double f1x = ((X[3] - p[0]) - e0x) * u, f1y = ((X[4] - p[1]) - e0y) * u, f1z = ((X[5] - p[2]) - e0z) * u;
+    const double f2x = ((X[6] - p[0]) - e0x) * u, f2y = ((X[7] - p[1]) - e0y) * u, f2z = ((X[8] - p[2]) - e0z) * u;
+    const double f3x = ((X[9] - p[0]) - e0x) * u, f3y = ((X[10] - p[1]) - e0y) * u, f3z = ((X[11] - p[2]) - e0z) * u;
+    const double p00 = g.c0[0], p01 = (g.c0[1] - g.c0[0]) * u, p02 = (g.c0[2] - g.c0[0]) * u,
+                 p03 = (g.c0[3] - g.c0[0]) * u;
+    const double p10 = g.c1[0], p11 = (g.c1[1] - g.c1[0]) * u, p12 = (g.c1[2] - g.c1[0]) * u,
+                 p13 = (g.c1[3] - g.c1[0]) * u;
+    double sum = 0.0;
+    for (int s = 0; s < N; s += 2) {
+        uint32_t w[4];
+        philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
+        for (int h = 0; h < 2; ++h) {
+            if (s + h >= N) break;
+            uint32_t L[4];
+            lambda_u(w, h, L);
+            const double l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
+            const double dx = fma(l3, f3x, fma(l2, f2x, fma(l1, f1x, e0x)));
+            const double dy = fma(l3, f3y, fma(l2, f2y, fma(l1, f1y, e0y)));
+            const double dz = fma(l3, f3z, fma(l2, f2z, fma(l1, f1z, e0z)));
+            const double rr = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double h0 = fma(l3, p03, fma(l2, p02, fma(l1, p01, p00)));
+            const double h1 = fma(l3, p13, fma(l2, p12, fma(l1, p11, p10)));
+            const bool inU = (h0 >= 0.0) && (h1 >= 0.0);
+            if ((rr < d2) && !inU) {
+                const double lam[4] = {(double)L[0] * u, l1 * u, l2 * u, l3 * u};
+                sum += g_defect_at<DEG>(X, lam, gv, coef);
+            }
+        }
+    }
+    return acc + (vol / (double)N) * sum;
 }
 
 }  // namespace nlfem

@@ -232,6 +232,63 @@ __global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_item
 }
 
 
+// Paper-exact right-hand side (eq. Fh with g at the inner points, eq. F1.5):
+// the load terms of each outer tet gain
+//   sum_k w c_kj 2 psi sum_{E_m in T_Omega_I} int_{E_m n B_delta,h(p_k)} (g - g_h),
+// g_h the nodal interpolant that the constraint columns already carry.  One
+// workgroup per outer tet, after the integration (which writes the load
+// terms) and before the row assembly; the per-point sums are reduced in a
+// fixed order, so the result is reproducible.
+constexpr int kExactGBlock = 256;
+template <int DEG>
+__global__ __launch_bounds__(kExactGBlock, 2) void k_exact_g(IntegrateArgs a, const double* g_nodal, const double* coef) {
+    // coefficients through the constant address space: scalar loads that the
+    // compiler may repeat instead of holding them in vector registers
+    typedef const __attribute__((address_space(4))) double ConstCoef;
+    ConstCoef* cf = (ConstCoef*)coef;
+    __shared__ double P[4][3];
+    __shared__ double red[4][kExactGBlock];
+    const int64_t oi = blockIdx.x;
+    const int n = a.outer_ids[oi];
+    const int t = threadIdx.x;
+    if (t < 4) {
+        double Xn[12];
+        for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
+        outer_point(Xn, t, P[t]);
+    }
+    __syncthreads();
+    const double d2 = a.delta * a.delta;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t p = a.pair_off[oi] + t; p < a.pair_off[oi + 1]; p += kExactGBlock) {
+        const int m = a.pair_m[p];
+        if (a.region[m]) continue;  // T_Omega inner elements carry no g
+        const uint32_t code = a.pair_cls[p];
+        const double* X = a.tetX + 12 * (int64_t)m;
+        double gv[4];
+        for (int l = 0; l < 4; ++l) gv[l] = g_nodal ? g_nodal[a.tets[4 * (int64_t)m + l]] : 0.0;
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            const int c = (int)((code >> (3 * k)) & 7u);
+            if (c == C_OUT) continue;
+            acc[k] += pair_g_defect<DEG>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1,
+                                         (uint32_t)(4 * n + k), (uint32_t)m, gv, cf);
+        }
+    }
+    for (int k = 0; k < 4; ++k) red[k][t] = acc[k];
+    __syncthreads();
+    for (int h = kExactGBlock / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + h];
+        __syncthreads();
+    }
+    if (t < 4) {
+        const double w = a.vol[n] * 0.25;
+        double add = 0.0;
+        for (int k = 0; k < 4; ++k) add += (w * rule_w(k, t)) * ((2.0 * a.psi) * red[k][0]);
+        a.oblk[20 * oi + 16 + t] += add;
+    }
+}
+
 // per-pair moments for outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k
 template <typename T, bool VR>
 __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_lo, double* out_S, int32_t* out_qm) {
@@ -363,6 +420,20 @@ hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, i
 
 
 
+
+hipError_t launch_exact_g(const IntegrateArgs& a, const double* g_nodal, const double* coef, int deg, hipStream_t s) {
+    if (a.n_outer <= 0) return hipSuccess;
+    if (deg < 0 || deg > kMaxGDegree || a.vr) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)a.n_outer;
+    switch (deg) {
+        case 0: k_exact_g<0><<<g, kExactGBlock, 0, s>>>(a, g_nodal, coef); break;
+        case 1: k_exact_g<1><<<g, kExactGBlock, 0, s>>>(a, g_nodal, coef); break;
+        case 2: k_exact_g<2><<<g, kExactGBlock, 0, s>>>(a, g_nodal, coef); break;
+        case 3: k_exact_g<3><<<g, kExactGBlock, 0, s>>>(a, g_nodal, coef); break;
+        default: k_exact_g<4><<<g, kExactGBlock, 0, s>>>(a, g_nodal, coef); break;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_zero_f64(double* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -59,6 +59,8 @@ FLOP_PER_IN_PAIR = 100
 # WRITE_SIZE counter runs summarised in this file; it is reported only while
 # the kernel's sources and build flags hash to the digest recorded there.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_integrate_traffic_precision.txt")
+# VALU instruction counters of the same kernel (rocprofv3 --pmc SQ_INSTS_VALU ...), same rule
+VALU_RECORD = os.path.join(ROOT, "profiles", "k_integrate_valu_precision.txt")
 INTEGRATE_SOURCES = ["paper_2302_07499_amd/csrc/k_numeric.hip", "paper_2302_07499_amd/csrc/device_geom.hpp",
                      "paper_2302_07499_amd/csrc/common.hpp", "paper_2302_07499_amd/build.py"]
 
@@ -70,6 +72,29 @@ def integrate_sources_digest():
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(rel.encode() + b"\0" + f.read())
     return h.hexdigest()
+
+
+def _read_record(path):
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    return rec
+
+
+def recorded_valu():
+    """VALU issue figures of the integration kernel from the counter summary,
+    or None when the kernel sources changed since."""
+    try:
+        rec = _read_record(VALU_RECORD)
+        if rec.get("sources_sha256") != integrate_sources_digest():
+            return None
+        return {"issue_frac": float(rec["valu_issue_frac"]), "insts_per_launch": float(rec["valu_insts_per_launch"]),
+                "hw_f64_flop_per_launch": float(rec["valu_f64_flop_per_launch"])}
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def recorded_traffic():
@@ -434,6 +459,12 @@ def main():
         roofline["traffic_note"] = tinfo
     else:
         roofline.update(tinfo)
+    valu = recorded_valu()
+    if valu is not None:
+        # hardware view from the counters: VALU wave instructions per SIMD-cycle
+        # against the issue limit, and the FP64 FLOPs the hardware executed
+        roofline["valu_issue_frac"] = round(valu["issue_frac"], 4)
+        roofline["hw_f64_tflops"] = round(valu["hw_f64_flop_per_launch"] / t_int / 1e12, 3)
 
     convergence = None
     if not args.no_convergence:

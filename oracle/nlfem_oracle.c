@@ -470,6 +470,11 @@ typedef struct {
 
 typedef void (*node_fn)(void *user, const double lam[4], double w, int is_mc);
 
+/* a . b as the FMA chain fma(a_z, b_z, fma(a_y, b_y, a_x b_x)) */
+static double dotf(const double a[3], const double b[3]) {
+    return fma(a[2], b[2], fma(a[1], b[1], a[0] * b[0]));
+}
+
 static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
     if (c->cls == OR_OUT) return;
     if (c->cls == OR_IN) {
@@ -492,8 +497,10 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
             fn(user, lam, w, 0);
         }
     }
-    /* sample point relative to p: y - p = (X_0 - p) + sum_{l=1..3} lambda_l (X_l - X_0),
-     * with X_l - X_0 taken as (X_l - p) - (X_0 - p), as an FMA chain over l = 1, 2, 3 */
+    /* Sample test.  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3 the sample
+     * point relative to p is y - p = e_0 + sum_{l=1..3} lambda_l F_l, e_0 = X_0 - p,
+     * F_l = (X_l - p) - (X_0 - p); |y - p|^2 is evaluated as its quadratic form in
+     * lambda_1..3 (coefficients below), the U_I planes as FMA chains over l.   */
     if (!c->caps) return;
     /* Sampling region: the whole E (samples in U_I rejected), or, for n_in = 3
      * with cap sampling on, E - U_I itself: the corner tet with vertices
@@ -525,14 +532,25 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
     double f[4][3];
     for (int l = 1; l < 4; ++l)
         for (int i = 0; i < 3; ++i) f[l][i] = e[l][i] - e[0][i];
+    /* |y - p|^2 = |e_0 + sum_l mu_l F_l|^2 written out as the quadratic form
+     * q0 + sum_l mu_l (qb_l + qa_ll mu_l + sum_{j>l} qa_lj mu_j) with
+     * q0 = e_0.e_0, qb_l = 2 e_0.F_l, qa_ll = F_l.F_l, qa_lj = 2 F_l.F_j
+     * (dot products as FMA chains over x, y, z), evaluated as three inner FMA
+     * chains and one outer one */
+    double q0 = dotf(e[0], e[0]);
+    double qb[4], qa[4][4];
+    for (int l = 1; l < 4; ++l) {
+        qb[l] = 2.0 * dotf(e[0], f[l]);
+        for (int j = l; j < 4; ++j) qa[l][j] = (j == l ? 1.0 : 2.0) * dotf(f[l], f[j]);
+    }
     double wmc = vol_r / (double)c->N;
     for (int s = 0; s < c->N; ++s) {
         double mu[4];
         or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, mu);
-        double d[3];
-        for (int i = 0; i < 3; ++i)
-            d[i] = fma(mu[3], f[3][i], fma(mu[2], f[2][i], fma(mu[1], f[1][i], e[0][i])));
-        double rr = fma(d[2], d[2], fma(d[1], d[1], d[0] * d[0]));
+        double t1 = fma(qa[1][3], mu[3], fma(qa[1][2], mu[2], fma(qa[1][1], mu[1], qb[1])));
+        double t2 = fma(qa[2][3], mu[3], fma(qa[2][2], mu[2], qb[2]));
+        double t3 = fma(qa[3][3], mu[3], qb[3]);
+        double rr = fma(mu[3], t3, fma(mu[2], t2, fma(mu[1], t1, q0)));
         if (!(rr < c->d2)) continue;
         if (corner) {
             double lam[4];

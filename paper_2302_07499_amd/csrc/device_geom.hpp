@@ -206,7 +206,9 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        // three-input XORs as one v_bitop3_b32 each (truth table 0x96 = a ^ b ^ c)
+        uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -228,13 +230,14 @@ __device__ __forceinline__ void lambda_u(const uint32_t* w, int h, uint32_t* L) 
         u1 = ((w[0] & 0x7FFu) << 10) | (w[1] & 0x3FFu);
         u2 = ((w[2] & 0x7FFu) << 10) | (w[3] & 0x3FFu);
     }
-    uint32_t a = min(u0, u1), b = max(u0, u1);
-    uint32_t b2 = min(b, u2), c = max(b, u2);
-    uint32_t a2 = min(a, b2), b3 = max(a, b2);
-    L[0] = a2;
-    L[1] = b3 - a2;
-    L[2] = c - b3;
-    L[3] = 2097152u - c;
+    // sorted as lo <= mid <= hi (the median as one v_med3_u32)
+    const uint32_t lo = min(min(u0, u1), u2);
+    const uint32_t hi = max(max(u0, u1), u2);
+    const uint32_t mid = max(min(u0, u1), min(max(u0, u1), u2));
+    L[0] = lo;
+    L[1] = mid - lo;
+    L[2] = hi - mid;
+    L[3] = 2097152u - hi;
 }
 
 // ---------------------------------------------------------------------------
@@ -496,19 +499,51 @@ __device__ inline void cut_det(const double* X, double vol, const double* p, dou
     cut_setup<T>(X, p, d2, r2, vol, g, D, G, cr);
 }
 
+// |y - p|^2 of a sample as a quadratic form in its barycentrics (l_1..l_3,
+// with l_0 eliminated): with e = X_0 - p and F_l = (X_l - p) - (X_0 - p),
+//   |y - p|^2 = c + sum_l l_l (b_l + A_ll l_l + sum_{j>l} A_lj l_j),
+// c = e.e, b_l = 2 e.F_l, A_ll = F_l.F_l, A_lj = 2 F_l.F_j (each dot product
+// an FMA chain over x, y, z), evaluated as three inner FMA chains and one
+// outer chain: 9 FMAs per sample.
+__device__ __forceinline__ double dot3f(double ax, double ay, double az, double bx, double by, double bz) {
+    return fma(az, bz, fma(ay, by, ax * bx));
+}
+struct BallForm {
+    double c, b1, b2, b3, a11, a12, a13, a22, a23, a33;
+    __device__ __forceinline__ BallForm(double ex, double ey, double ez, double f1x, double f1y, double f1z, double f2x,
+                                        double f2y, double f2z, double f3x, double f3y, double f3z) {
+        c = dot3f(ex, ey, ez, ex, ey, ez);
+        b1 = 2.0 * dot3f(ex, ey, ez, f1x, f1y, f1z);
+        b2 = 2.0 * dot3f(ex, ey, ez, f2x, f2y, f2z);
+        b3 = 2.0 * dot3f(ex, ey, ez, f3x, f3y, f3z);
+        a11 = dot3f(f1x, f1y, f1z, f1x, f1y, f1z);
+        a12 = 2.0 * dot3f(f1x, f1y, f1z, f2x, f2y, f2z);
+        a13 = 2.0 * dot3f(f1x, f1y, f1z, f3x, f3y, f3z);
+        a22 = dot3f(f2x, f2y, f2z, f2x, f2y, f2z);
+        a23 = 2.0 * dot3f(f2x, f2y, f2z, f3x, f3y, f3z);
+        a33 = dot3f(f3x, f3y, f3z, f3x, f3y, f3z);
+    }
+    __device__ __forceinline__ double eval(double l1, double l2, double l3) const {
+        const double t1 = fma(a13, l3, fma(a12, l2, fma(a11, l1, b1)));
+        const double t2 = fma(a23, l3, fma(a22, l2, b2));
+        const double t3 = fma(a33, l3, b3);
+        return fma(l3, t3, fma(l2, t2, fma(l1, t1, c)));
+    }
+};
+
 template <typename T, bool VR = false>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
                               const CornerGeom* cr = nullptr) {
     // The sample barycentrics are lambda = L * 2^-21 with integer L (spacings
     // of 21-bit uniforms).  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3
-    // substituted, the sample point relative to p is
-    //   y - p = (X_0 - p) + sum_{l=1..3} lambda_l ((X_l - p) - (X_0 - p))
-    // and a plane value c . lambda = c_0 + sum_{l=1..3} lambda_l (c_l - c_0),
-    // both as FMA chains over l = 1, 2, 3.  The loop works with L itself: the
-    // differences are prescaled by 2^-21 (exact), so every product L * f'
-    // equals lambda * f exactly and all roundings are those of the lambda
-    // form.  The sums are scaled back at the end (exact powers of two).
+    // substituted, |y - p|^2 is the quadratic form of BallForm in lambda_1..3
+    // and a plane value c . lambda = c_0 + sum_{l=1..3} lambda_l (c_l - c_0)
+    // an FMA chain over l = 1, 2, 3.  The loop works with L itself: the
+    // differences are prescaled by 2^-21 (exact), so every product with L
+    // equals the lambda form's product exactly and all roundings are those of
+    // the lambda form.  The sums are scaled back at the end (exact powers of
+    // two).
     //
     // Sums over the accepted samples are integers: the count and sum L_j
     // (j = 1..3) in 32 bits, sum L_i L_j (1 <= i <= j <= 3) in 64 bits (one
@@ -548,6 +583,7 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
             p10 = 1.0; p11 = 0.0; p12 = 0.0; p13 = 0.0;
         }
     }
+    const BallForm bf(e0x, e0y, e0z, f1x, f1y, f1z, f2x, f2y, f2z, f3x, f3y, f3z);
     constexpr bool kF32 = sizeof(T) == 4;
     uint32_t icnt = 0, ia1 = 0, ia2 = 0, ia3 = 0;
     uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
@@ -560,10 +596,7 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
                 uint32_t L[4];
                 lambda_u(w, h, L);
                 double l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
-                double dx = fma(l3, f3x, fma(l2, f2x, fma(l1, f1x, e0x)));
-                double dy = fma(l3, f3y, fma(l2, f2y, fma(l1, f1y, e0y)));
-                double dz = fma(l3, f3z, fma(l2, f2z, fma(l1, f1z, e0z)));
-                double rr = fma(dz, dz, fma(dy, dy, dx * dx));
+                double rr = bf.eval(l1, l2, l3);
                 double h0 = fma(l3, p03, fma(l2, p02, fma(l1, p01, p00)));
                 double h1 = fma(l3, p13, fma(l2, p12, fma(l1, p11, p10)));
                 bool inU = (h0 >= 0.0) && (h1 >= 0.0);
@@ -769,6 +802,7 @@ __device__ inline double pair_g_defect(const double* X, double vol, const double
                  p03 = (g.c0[3] - g.c0[0]) * u;
     const double p10 = g.c1[0], p11 = (g.c1[1] - g.c1[0]) * u, p12 = (g.c1[2] - g.c1[0]) * u,
                  p13 = (g.c1[3] - g.c1[0]) * u;
+    const BallForm bf(e0x, e0y, e0z, f1x, f1y, f1z, f2x, f2y, f2z, f3x, f3y, f3z);
     double sum = 0.0;
     for (int s = 0; s < N; s += 2) {
         uint32_t w[4];
@@ -778,10 +812,7 @@ __device__ inline double pair_g_defect(const double* X, double vol, const double
             uint32_t L[4];
             lambda_u(w, h, L);
             const double l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
-            const double dx = fma(l3, f3x, fma(l2, f2x, fma(l1, f1x, e0x)));
-            const double dy = fma(l3, f3y, fma(l2, f2y, fma(l1, f1y, e0y)));
-            const double dz = fma(l3, f3z, fma(l2, f2z, fma(l1, f1z, e0z)));
-            const double rr = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double rr = bf.eval(l1, l2, l3);
             const double h0 = fma(l3, p03, fma(l2, p02, fma(l1, p01, p00)));
             const double h1 = fma(l3, p13, fma(l2, p12, fma(l1, p11, p10)));
             const bool inU = (h0 >= 0.0) && (h1 >= 0.0);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -540,6 +541,11 @@ struct TuneVal {
     int block;
     double ms;
 };
+// guarded by tune_mutex(): batches of different threads share the cache
+std::mutex& tune_mutex() {
+    static std::mutex m;
+    return m;
+}
 std::map<TuneKey, TuneVal>& tune_cache() {
     static std::map<TuneKey, TuneVal> m;
     return m;
@@ -1050,18 +1056,26 @@ nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, con
         for (nlfem_batch::Group& G : b->groups) {
             TuneKey key{ilog2(std::max<int64_t>(G.pairs, 1)), ilog2(std::max<int64_t>(G.n_items, 1)),
                         n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0, G.per_cu};
-            auto it = tune_cache().find(key);
-            if (it == tune_cache().end()) {
+            TuneVal tv{0, 0.0};
+            {
+                std::lock_guard<std::mutex> lk(tune_mutex());
+                auto it = tune_cache().find(key);
+                if (it != tune_cache().end()) tv = it->second;
+            }
+            if (tv.block == 0) {
+                // timed outside the lock; a concurrent batch of the same class
+                // may time it too, and either result is a valid choice
+                tv = TuneVal{256, 1e30};
                 const int blocks[2] = {128, 256};
-                TuneVal bv{256, 1e30};
                 for (int bi = 0; bi < 2; ++bi) {
                     const double ms = time_integrate(b, G, blocks[bi]);
-                    if (ms < bv.ms) bv = TuneVal{blocks[bi], ms};
+                    if (ms < tv.ms) tv = TuneVal{blocks[bi], ms};
                 }
-                it = tune_cache().emplace(key, bv).first;
+                std::lock_guard<std::mutex> lk(tune_mutex());
+                tune_cache().emplace(key, tv);
             }
-            G.block = it->second.block;
-            G.tune_ms = it->second.ms;
+            G.block = tv.block;
+            G.tune_ms = tv.ms;
         }
         b->tuned = true;
     }

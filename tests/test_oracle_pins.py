@@ -391,6 +391,26 @@ def test_plain_symmetry_rowsums_spd(orc, plain_sys):
         assert np.all(np.diff(c) > 0)
 
 
+def test_translation_invariance(orc, plain_sys):
+    """Moving the mesh by a dyadic vector changes no class and no sample
+    (counters do not depend on coordinates); the matrix agrees to rounding.
+    The free mask is carried over (it is data, not recomputed)."""
+    pb, S = plain_sys
+    shift = np.array([0.5, -0.25, 0.125])
+    m = pb.mesh
+    T = orc.assemble(m.coords + shift, m.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
+                     g_nodal=pb.g_nodal)
+    R = orc.assemble(m.coords, m.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
+                     g_nodal=pb.g_nodal)
+    assert np.array_equal(T["pair_counts"], R["pair_counts"])
+    for k in ["ff_row_ptr", "ff_col", "fc_row_ptr", "fc_col"]:
+        assert np.array_equal(T[k], R[k]), k
+    scale = np.abs(R["ff_val"]).max()
+    assert np.max(np.abs(T["ff_val"] - R["ff_val"])) <= 1e-12 * scale
+    assert np.max(np.abs(T["fc_val"] - R["fc_val"])) <= 1e-12 * scale
+    assert np.max(np.abs(T["rhs"] - R["rhs"])) <= 1e-12 * np.abs(R["rhs"]).max()
+
+
 def test_plain_cg_matches_dense_solve(orc, plain_sys):
     pb, S = plain_sys
     A = _dense(S, pb.mesh.n_vertices)[:, S["free_to_vertex"]]

@@ -209,10 +209,12 @@ nlfem_status nlfem_debug_pairs(nlfem_plan *plan, int64_t q_begin, int64_t q_end,
  * symbolic phase runs per mesh as in nlfem_plan_create.  The numeric phase
  * groups the meshes by how many integration workgroups fit on a CU next to
  * their local vertex set in LDS (1, 2 or 3); each group is ONE integration
- * launch with one workgroup per (mesh, outer tet) work item, longest first.
- * The launches and the per-mesh reductions are captured once in a HIP graph
- * and replayed.  Each group's workgroup size (128 or 256) is picked on the
- * first call by timing both on a strided sample of its work items (about
+ * launch over its (mesh, outer tet) work items, longest first: either a
+ * persistent grid of 2, 3, 4 or 6 workgroups per CU that pull items from a
+ * device queue, or one workgroup per item.  The launches and the per-mesh
+ * reductions are captured once in a HIP graph and replayed.  Each group's
+ * launch form and workgroup size (128 or 256) are picked on the first call
+ * by timing the candidates on a strided sample of its work items (about
  * 1.5e8 pairs; cached per shape class for the process).  Results are
  * bitwise those of nlfem_assemble on each mesh alone.                        */
 typedef struct nlfem_batch nlfem_batch;
@@ -236,9 +238,10 @@ nlfem_status nlfem_batch_system(const nlfem_batch *batch, int32_t i, const int64
                                 const double **fc_val, const double **rhs,
                                 const int32_t **free_to_vertex);
 /* Chosen workgroup size of the group with the most pairs and its number of
- * workgroups (its work items), the integration time of the chosen sizes on
- * the tuning samples summed over the groups, and the time of the last graph
- * replay (milliseconds, HIP events).                                         */
+ * workgroups (the persistent grid, or its number of work items), the
+ * integration time of the chosen shapes on the tuning samples summed over
+ * the groups, and the time of the last graph replay (milliseconds, HIP
+ * events).                                                                   */
 nlfem_status nlfem_batch_tuning(const nlfem_batch *batch, int32_t *block, int32_t *grid,
                                 double *tuned_integrate_ms, double *last_graph_ms);
 nlfem_status nlfem_batch_destroy(nlfem_batch *batch);

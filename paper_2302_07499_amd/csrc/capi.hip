@@ -538,7 +538,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int block;
+    int block, wg_per_cu;  // wg_per_cu 0: one workgroup per item, else a persistent grid of n_cu * wg_per_cu
     double ms;
 };
 // guarded by tune_mutex(): batches of different threads share the cache
@@ -587,11 +587,13 @@ struct nlfem_batch {
         int2* d_items = nullptr;   // (mesh, outer position), longest first
         int2* d_sample = nullptr;  // every stride-th item: the autotuner times this list
         int64_t n_items = 0, n_sample = 0, pairs = 0;
-        int block = 256;
+        unsigned long long* d_head = nullptr;  // queue head of the persistent launch
+        int block = 256, grid = 0;             // grid 0: one workgroup per item
         double tune_ms = 0.0;
     };
     std::vector<Group> groups;
     int64_t total_pairs = 0;
+    int n_cu = 256;
     bool fp32 = false;
     bool vr = false;
     bool tuned = false;
@@ -630,8 +632,13 @@ void batch_free(nlfem_batch* b) {
 nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStream_t s) {
     nlfem_ctx* c = b->ctx;
     for (nlfem_plan* pl : b->plans) HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
-    for (const nlfem_batch::Group& g : b->groups)
-        HIPCHK(launch_integrate_items(b->d_descs, g.d_items, g.n_items, g.umax, b->fp32, b->vr, g.block, s));
+    for (const nlfem_batch::Group& g : b->groups) {
+        if (g.grid > 0)
+            HIPCHK(launch_integrate_batch(b->d_descs, g.d_items, g.n_items, g.d_head, g.umax, b->fp32, b->vr, g.block,
+                                          g.grid, s));
+        else
+            HIPCHK(launch_integrate_items(b->d_descs, g.d_items, g.n_items, g.umax, b->fp32, b->vr, g.block, s));
+    }
     for (size_t i = 0; i < b->plans.size(); ++i) {
         const nlfem_batch::Out& o = b->outs[i];
         nlfem_status st = enqueue_rows(c, b->plans[i], g_nodal ? g_nodal[i] : nullptr, o.ff_val, o.fc_val, o.rhs, s);
@@ -640,11 +647,15 @@ nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStre
     return NLFEM_OK;
 }
 
-double time_integrate(nlfem_batch* b, const nlfem_batch::Group& g, int block) {
+// integration time of the group's tuning sample with one launch shape
+// (grid 0: one workgroup per item)
+double time_integrate(nlfem_batch* b, const nlfem_batch::Group& g, int block, int grid) {
     Timer t(b->gs);
-    if (launch_integrate_items(b->d_descs, g.d_sample, g.n_sample, g.umax, b->fp32, b->vr, block, b->gs) !=
-        hipSuccess)
-        return 1e30;
+    const hipError_t e =
+        grid > 0 ? launch_integrate_batch(b->d_descs, g.d_sample, g.n_sample, g.d_head, g.umax, b->fp32, b->vr, block,
+                                          grid, b->gs)
+                 : launch_integrate_items(b->d_descs, g.d_sample, g.n_sample, g.umax, b->fp32, b->vr, block, b->gs);
+    if (e != hipSuccess) return 1e30;
     return t.stop();
 }
 
@@ -906,8 +917,10 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     b->vr = n > 0 && params[0].cap_sampling == NLFEM_CAPS_OUTSIDE_UI;
     hipDeviceProp_t prop;
     size_t lds_cu = 160 * 1024;
-    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.maxSharedMemoryPerMultiProcessor > 0)
-        lds_cu = prop.maxSharedMemoryPerMultiProcessor;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        b->n_cu = prop.multiProcessorCount;
+        if (prop.maxSharedMemoryPerMultiProcessor > 0) lds_cu = prop.maxSharedMemoryPerMultiProcessor;
+    }
     for (int32_t i = 0; i < n; ++i) {
         nlfem_plan* pl = nullptr;
         nlfem_status st = nlfem_plan_create(c, &meshes[i], &params[i], &pl);
@@ -998,7 +1011,8 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         G.n_sample = (int64_t)sample.size();
         G.d_sample = (int2*)b->alloc(sample.size() * sizeof(int2) + 16);
         G.d_items = (int2*)b->alloc(sorted.size() * sizeof(int2) + 16);
-        if (!G.d_items || !G.d_sample) {
+        G.d_head = (unsigned long long*)b->alloc(64);
+        if (!G.d_items || !G.d_sample || !G.d_head) {
             batch_free(b);
             return fail(c, NLFEM_E_OOM, c->err);
         }
@@ -1056,7 +1070,7 @@ nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, con
         for (nlfem_batch::Group& G : b->groups) {
             TuneKey key{ilog2(std::max<int64_t>(G.pairs, 1)), ilog2(std::max<int64_t>(G.n_items, 1)),
                         n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0, G.per_cu};
-            TuneVal tv{0, 0.0};
+            TuneVal tv{0, 0, 0.0};
             {
                 std::lock_guard<std::mutex> lk(tune_mutex());
                 auto it = tune_cache().find(key);
@@ -1064,17 +1078,23 @@ nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, con
             }
             if (tv.block == 0) {
                 // timed outside the lock; a concurrent batch of the same class
-                // may time it too, and either result is a valid choice
-                tv = TuneVal{256, 1e30};
+                // may time it too, and either result is a valid choice.
+                // Candidates: a persistent grid of 2, 3, 4 or 6 workgroups per
+                // CU (at most 12 waves per CU), or one workgroup per item.
+                tv = TuneVal{256, 0, 1e30};
                 const int blocks[2] = {128, 256};
-                for (int bi = 0; bi < 2; ++bi) {
-                    const double ms = time_integrate(b, G, blocks[bi]);
-                    if (ms < tv.ms) tv = TuneVal{blocks[bi], ms};
-                }
+                const int wpc[5] = {2, 3, 4, 6, 0};
+                for (int bi = 0; bi < 2; ++bi)
+                    for (int wi = 0; wi < 5; ++wi) {
+                        if ((blocks[bi] / 64) * wpc[wi] > 12) continue;
+                        const double ms = time_integrate(b, G, blocks[bi], b->n_cu * wpc[wi]);
+                        if (ms < tv.ms) tv = TuneVal{blocks[bi], wpc[wi], ms};
+                    }
                 std::lock_guard<std::mutex> lk(tune_mutex());
                 tune_cache().emplace(key, tv);
             }
             G.block = tv.block;
+            G.grid = b->n_cu * tv.wg_per_cu;
             G.tune_ms = tv.ms;
         }
         b->tuned = true;
@@ -1128,7 +1148,8 @@ nlfem_status nlfem_batch_tuning(const nlfem_batch* b, int32_t* block, int32_t* g
                                 double* last_graph_ms) {
     if (!b) return NLFEM_E_INVALID_ARG;
     // workgroup size of the group with the most pairs and its number of
-    // workgroups (one per work item); time summed over the groups
+    // workgroups (the persistent grid, or one per work item); time summed
+    // over the groups
     const nlfem_batch::Group* top = nullptr;
     double ms = 0.0;
     for (const nlfem_batch::Group& G : b->groups) {
@@ -1136,7 +1157,7 @@ nlfem_status nlfem_batch_tuning(const nlfem_batch* b, int32_t* block, int32_t* g
         if (!top || G.pairs > top->pairs) top = &G;
     }
     if (block) *block = top ? top->block : 0;
-    if (grid) *grid = top ? (int32_t)std::min<int64_t>(top->n_items, 0x7fffffff) : 0;
+    if (grid) *grid = top ? (top->grid > 0 ? top->grid : (int32_t)std::min<int64_t>(top->n_items, 0x7fffffff)) : 0;
     if (tuned_integrate_ms) *tuned_integrate_ms = ms;
     if (last_graph_ms) *last_graph_ms = b->last_ms;
     return NLFEM_OK;

@@ -122,6 +122,11 @@ struct IntegrateArgs {
     int64_t gstride;           // = K
 };
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
+// persistent: grid workgroups pull (mesh, outer position) items from a device
+// queue (head reset by the launch); block 128 or 256
+hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
+                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
+                                  hipStream_t s);
 // one workgroup per work item (mesh, outer position), in list order; block 128 or 256
 hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
                                   bool vr, int block, hipStream_t s);

@@ -80,8 +80,11 @@ __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned 
 // same T0[k], so the threads sum privately and the block adds the slots up at
 // the end: the same integers, without same-address atomics), Ve [umax], and
 // the 4 outer points.  A is IntegrateArgs, or the same type in the constant
-// address space for descriptors read from a device table.
-template <typename T, int BLOCK, bool VR, typename A>
+// address space for descriptors read from a device table.  OPAQUE_TID hides
+// the thread index behind an empty asm so that a caller's loop cannot hoist
+// the per-thread addresses out of it (they would stay live across the whole
+// item loop of a persistent kernel and spill).
+template <typename T, int BLOCK, bool VR, typename A, bool OPAQUE_TID = false>
 __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
     const int umax = a.umax;
@@ -94,7 +97,8 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
     const int U = (int)(a.ve_off[oi + 1] - vb);
-    const int t = threadIdx.x;
+    int t = threadIdx.x;
+    if constexpr (OPAQUE_TID) asm volatile("" : "+v"(t));
     for (int i = t; i < U; i += BLOCK) ve[i] = a.ve_ids[vb + i];
     for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
     for (int i = 0; i < 8; ++i) T0p[i * BLOCK + t] = 0ull;
@@ -215,6 +219,34 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(Integr
 // constant address space so that they load into scalar registers, and can be
 // loaded again instead of being held, as kernel arguments are
 typedef const __attribute__((address_space(4))) IntegrateArgs ConstArgs;
+
+// Persistent batched integration: a grid sized to the machine pulls work
+// items (mesh, outer position) from a device queue, longest first, until it
+// is empty; each item's results depend on the item only.
+template <typename T, int BLOCK, bool VR>
+__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batch(const IntegrateArgs* descs,
+                                                                                 const int2* items, int64_t n_items,
+                                                                                 unsigned long long* head) {
+    extern __shared__ unsigned long long smem64[];
+    __shared__ double P[4][3];
+    __shared__ long long cur;
+    while (true) {
+        if (threadIdx.x == 0) cur = (long long)atomicAdd(head, 1ull);
+        __syncthreads();
+        const long long it = cur;
+        __syncthreads();
+        if (it >= n_items) break;
+        // the item and its descriptor are the same for the whole workgroup
+        const int2 item = items[__builtin_amdgcn_readfirstlane((int)it)];
+        const int mesh = __builtin_amdgcn_readfirstlane(item.x);
+        const int pos = __builtin_amdgcn_readfirstlane(item.y);
+        ConstArgs* d = (ConstArgs*)(descs + mesh);
+        integrate_outer<T, BLOCK, VR, ConstArgs, true>(*d, (int64_t)pos, smem64, P);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_u64(unsigned long long* p) { *p = 0ull; }
 
 // One workgroup per work item (mesh, outer position), in list order: the
 // dispatcher starts workgroups in increasing index as slots free up, so a
@@ -374,6 +406,35 @@ hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     } else {
         if (fp32) k_integrate<float, false><<<g, 256, sh, s>>>(a);
         else k_integrate<double, false><<<g, 256, sh, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
+                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
+                                  hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (n_items > 0x7fffffff || grid <= 0) return hipErrorInvalidValue;
+    const size_t sh = integrate_lds_bytes(umax);
+    // a fill kernel, not a memset: the launch is captured in a graph
+    k_reset_u64<<<1, 1, 0, s>>>(head);
+    const unsigned g = (unsigned)grid;
+    if (block == 128) {
+        if (vr) {
+            if (fp32) k_integrate_batch<float, 128, true><<<g, 128, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 128, true><<<g, 128, sh, s>>>(descs, items, n_items, head);
+        } else {
+            if (fp32) k_integrate_batch<float, 128, false><<<g, 128, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 128, false><<<g, 128, sh, s>>>(descs, items, n_items, head);
+        }
+    } else {
+        if (vr) {
+            if (fp32) k_integrate_batch<float, 256, true><<<g, 256, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 256, true><<<g, 256, sh, s>>>(descs, items, n_items, head);
+        } else {
+            if (fp32) k_integrate_batch<float, 256, false><<<g, 256, sh, s>>>(descs, items, n_items, head);
+            else k_integrate_batch<double, 256, false><<<g, 256, sh, s>>>(descs, items, n_items, head);
+        }
     }
     return hipGetLastError();
 }

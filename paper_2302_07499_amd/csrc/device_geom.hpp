@@ -318,31 +318,11 @@ __device__ __forceinline__ double edge_t(const double* Xg, const double* p, doub
     return t > 1.0 ? 1.0 : t;
 }
 
-// Moments of the subtet with barycentric vertex rows v0..v3 and volume V:
+// Moments of a subtet with barycentric vertex rows v0..v3 and volume V:
 //   S0 = V, S1 = V/4 sum_a v_a, S2 = V/20 (sum_a v_a v_a^T + s s^T), s = sum_a v_a.
 // These are the integrals of the affine barycentric coordinates over the
 // subtet; the 4-point rule of Sec. 4.2.1 is exact for them (degree <= 2), so
-// it gives the same values.  Evaluated in T; S0, S1 are added to D[0..4],
-// S2 (upper triangle) to G.
-template <typename T>
-__device__ __forceinline__ void subtet_moments(const double* v0, const double* v1, const double* v2, const double* v3,
-                                               double V, double* D, double* G) {
-    T sv[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) sv[l] = (T)(((v0[l] + v1[l]) + v2[l]) + v3[l]);
-    const T w4 = (T)(V * 0.25), w20 = (T)(V * 0.05);
-    D[0] += V;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) D[1 + j] += (double)(w4 * sv[j]);
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = i; j < 4; ++j) {
-            const T q = (((T)v0[i] * (T)v0[j] + (T)v1[i] * (T)v1[j]) + (T)v2[i] * (T)v2[j]) + (T)v3[i] * (T)v3[j];
-            G[k++] += (double)(w20 * (q + sv[i] * sv[j]));
-        }
-}
+// it gives the same values.  ti_moments (below) sums them over T_I in T.
 
 // position of the n-th set bit of m (n = 0: lowest), -1 if there is none
 __device__ __forceinline__ int nth_bit(unsigned m, int n) {
@@ -365,8 +345,21 @@ __device__ __forceinline__ int nth_bit(unsigned m, int n) {
 //             T_I = {0,1,2,4}, {0,2,4,5}, {0,3,4,5}, planes (1,2,4), (2,4,5).
 // Every lane runs the same instruction stream: the three subtets are always
 // evaluated (zero-volume ones for n_in = 1 and n_in = 0), the hull points and
-// planes are picked by selects.  sub(v0, v1, v2, v3, V) receives each subtet
-// of T_I as barycentric vertex rows and its volume.
+// planes are picked by selects.  sub(ti) receives T_I once (TISet).
+struct TISet {
+    const double *H0, *H1, *H2, *H3, *H4, *H5;  // dense barycentric rows of the hull points
+    const double *XA, *YB;                      // alt ? H4 : H5 and alt ? H2 : H1
+    bool alt;
+    double Va, Vb, Vc;  // volumes of (H0, H1, H2, XA), (H0, YB, H4, H5), (H0, H3, H4, H5)
+    // subtet s = 0, 1, 2 as four rows and its volume
+    template <typename F>
+    __device__ __forceinline__ void each(F&& f) const {
+        f(H0, H1, H2, XA, Va);
+        f(H0, YB, H4, H5, Vb);
+        f(H0, H3, H4, H5, Vc);
+    }
+};
+
 template <typename Sub>
 __device__ __forceinline__ void cut_build(const double* Xg, const double* p, double d2, const double* r2, double vol,
                                           CutGeom& g, CornerGeom* cr, Sub&& sub) {
@@ -424,9 +417,7 @@ __device__ __forceinline__ void cut_build(const double* Xg, const double* p, dou
         XA[l] = alt ? H4[l] : H5[l];
         YB[l] = alt ? H2[l] : H1[l];
     }
-    sub(H0, H1, H2, XA, vol * (alt ? d124 : d125));
-    sub(H0, YB, H4, H5, vol * (alt ? d245 : d145));
-    sub(H0, H3, H4, H5, vol * d345);
+    sub(TISet{H0, H1, H2, H3, H4, H5, XA, YB, alt, vol * (alt ? d124 : d125), vol * (alt ? d245 : d145), vol * d345});
     g.nin = ni;
     g.nplanes = any ? (c2 ? 2 : 1) : 0;
     // planes: c0 through (h3, h4, h5) for n_in = 3, else (h1, h2, alt ? h4 : h5);
@@ -473,14 +464,59 @@ __device__ inline void in_moments(double vol, double* S) {
     }
 }
 
-// cut_build with the moments of every subtet added to D and G
+// Moments of T_I added to D (S0, S1 per subtet) and G.
+// S2 = sum_s V_s/20 (sum_{a in s} v_a v_a^T + s_s s_s^T) is regrouped by
+// hull point: sum_h W_h h h^T + sum_s V_s/20 s_s s_s^T, W_h = the sum of
+// V_s/20 over the subtets holding h (14 + 14 multiply-adds per hull point and
+// per subtet instead of 100 per subtet).
+template <typename T>
+__device__ __forceinline__ void ti_moments(const TISet& ti, double* D, double* G) {
+    T g2[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) g2[k] = (T)0;
+    auto outer = [&](const double* h, double W) {  // g2 += (W/20) h h^T
+        const T w = (T)(W * 0.05);
+        T hw[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) hw[l] = w * (T)h[l];
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = i; j < 4; ++j) {
+                g2[k] = fma(hw[i], (T)h[j], g2[k]);
+                ++k;
+            }
+    };
+    ti.each([&](const double* v0, const double* v1, const double* v2, const double* v3, double V) {
+        T sv[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) sv[l] = (T)(((v0[l] + v1[l]) + v2[l]) + v3[l]);
+        const T w4 = (T)(V * 0.25);
+        D[0] += V;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) D[1 + j] += (double)(w4 * sv[j]);
+        double s[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) s[l] = (double)sv[l];
+        outer(s, V);
+    });
+    const double a = ti.alt ? ti.Va : 0.0, b = ti.alt ? 0.0 : ti.Va;
+    outer(ti.H0, (ti.Va + ti.Vb) + ti.Vc);
+    outer(ti.H1, ti.Va + (ti.alt ? 0.0 : ti.Vb));
+    outer(ti.H2, ti.Va + (ti.alt ? ti.Vb : 0.0));
+    outer(ti.H3, ti.Vc);
+    outer(ti.H4, (a + ti.Vb) + ti.Vc);
+    outer(ti.H5, (b + ti.Vb) + ti.Vc);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) G[k] += (double)g2[k];
+}
+
+// cut_build with the moments of T_I added to D and G
 template <typename T>
 __device__ inline void cut_setup(const double* Xg, const double* p, double d2, const double* r2, double vol,
                                  CutGeom& g, double* D, double* G, CornerGeom* cr = nullptr) {
-    cut_build(Xg, p, d2, r2, vol, g, cr,
-              [&](const double* v0, const double* v1, const double* v2, const double* v3, double V) {
-                  subtet_moments<T>(v0, v1, v2, v3, V, D, G);
-              });
+    cut_build(Xg, p, d2, r2, vol, g, cr, [&](const TISet& ti) { ti_moments<T>(ti, D, G); });
 }
 
 template <typename T>
@@ -779,18 +815,19 @@ __device__ inline double pair_g_defect(const double* X, double vol, const double
         r2[l] = (dx * dx + dy * dy) + dz * dz;
     }
     CutGeom g;
-    cut_build(X, p, d2, r2, vol, g, nullptr,
-              [&](const double* v0, const double* v1, const double* v2, const double* v3, double V) {
-                  const double w = V * 0.25;
-                  for (int r = 0; r < 4; ++r) {
-                      double lam[4];
+    cut_build(X, p, d2, r2, vol, g, nullptr, [&](const TISet& ti) {
+        ti.each([&](const double* v0, const double* v1, const double* v2, const double* v3, double V) {
+            const double w = V * 0.25;
+            for (int r = 0; r < 4; ++r) {
+                double lam[4];
 #pragma unroll
-                      for (int l = 0; l < 4; ++l)
-                          lam[l] = ((rule_w(r, 0) * v0[l] + rule_w(r, 1) * v1[l]) + rule_w(r, 2) * v2[l]) +
-                                   rule_w(r, 3) * v3[l];
-                      acc += w * g_defect_at<DEG>(X, lam, gv, coef);
-                  }
-              });
+                for (int l = 0; l < 4; ++l)
+                    lam[l] = ((rule_w(r, 0) * v0[l] + rule_w(r, 1) * v1[l]) + rule_w(r, 2) * v2[l]) +
+                             rule_w(r, 3) * v3[l];
+                acc += w * g_defect_at<DEG>(X, lam, gv, coef);
+            }
+        });
+    });
     if (!caps) return acc;
     // the sample frame and acceptance test of cut_mc, term for term
     const double u = 1.0 / 2097152.0;

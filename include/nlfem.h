@@ -244,6 +244,13 @@ nlfem_status nlfem_batch_system(const nlfem_batch *batch, int32_t i, const int64
  * events).                                                                   */
 nlfem_status nlfem_batch_tuning(const nlfem_batch *batch, int32_t *block, int32_t *grid,
                                 double *tuned_integrate_ms, double *last_graph_ms);
+/* Pins the launch shape of every group instead of the autotuner's choice:
+ * workgroup size block (128 or 256) and a persistent grid of wg_per_cu
+ * workgroups per CU, or wg_per_cu = 0 for one workgroup per work item
+ * ((block / 64) * wg_per_cu <= 12).  Takes effect on the next
+ * nlfem_batch_assemble, which captures its graph again; results do not
+ * depend on the shape.                                                       */
+nlfem_status nlfem_batch_set_launch(nlfem_batch *batch, int32_t block, int32_t wg_per_cu);
 nlfem_status nlfem_batch_destroy(nlfem_batch *batch);
 
 /* Device kernel timing of the last nlfem_assemble / nlfem_plan_create on the

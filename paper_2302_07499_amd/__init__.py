@@ -97,7 +97,7 @@ EXPORTS = ["nlfem_create", "nlfem_destroy", "nlfem_last_error", "nlfem_memory_in
            "nlfem_assemble_exact_g", "nlfem_cg",
            "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings",
            "nlfem_batch_create", "nlfem_batch_info", "nlfem_batch_assemble", "nlfem_batch_system",
-           "nlfem_batch_tuning", "nlfem_batch_destroy",
+           "nlfem_batch_tuning", "nlfem_batch_set_launch", "nlfem_batch_destroy",
            "nlfem_server_create", "nlfem_server_submit", "nlfem_server_poll", "nlfem_server_wait",
            "nlfem_server_take", "nlfem_server_stats", "nlfem_server_last_error", "nlfem_server_destroy"]
 
@@ -138,6 +138,7 @@ def load():
     L.nlfem_batch_system.argtypes = [P, C.c_int32] + [C.POINTER(P)] * 8
     L.nlfem_batch_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
+    L.nlfem_batch_set_launch.argtypes = [P, C.c_int32, C.c_int32]
     L.nlfem_batch_destroy.argtypes = [P]
     L.nlfem_server_create.argtypes = [C.c_int, C.c_int32, C.c_size_t, C.POINTER(P)]
     L.nlfem_server_submit.argtypes = [P, C.POINTER(nlfem_mesh), C.POINTER(nlfem_params), P, P,
@@ -487,6 +488,10 @@ class Batch:
         b, g, tm, lm = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
         _check(load().nlfem_batch_tuning(self.handle, C.byref(b), C.byref(g), C.byref(tm), C.byref(lm)))
         return {"block": b.value, "grid": g.value, "tuned_integrate_ms": tm.value, "last_graph_ms": lm.value}
+
+    def set_launch(self, block: int, wg_per_cu: int):
+        """Pins every group's launch shape (wg_per_cu 0: one workgroup per item)."""
+        _check(load().nlfem_batch_set_launch(self.handle, int(block), int(wg_per_cu)), self.dev.ctx)
 
     def destroy(self):
         if self.handle is not None and self.dev.ctx is not None:

@@ -1163,6 +1163,32 @@ nlfem_status nlfem_batch_tuning(const nlfem_batch* b, int32_t* block, int32_t* g
     return NLFEM_OK;
 }
 
+nlfem_status nlfem_batch_set_launch(nlfem_batch* b, int32_t block, int32_t wg_per_cu) {
+    if (!b) return NLFEM_E_INVALID_ARG;
+    nlfem_ctx* c = b->ctx;
+    if (block != 128 && block != 256) return fail(c, NLFEM_E_INVALID_ARG, "block must be 128 or 256");
+    if (wg_per_cu < 0 || (block / 64) * wg_per_cu > 12)
+        return fail(c, NLFEM_E_INVALID_ARG, "wg_per_cu outside [0, 12 / waves per workgroup]");
+    // the next nlfem_batch_assemble uses this shape for every group and
+    // captures its graph again
+    if (b->gs) HIPCHK(hipStreamSynchronize(b->gs));
+    for (nlfem_batch::Group& G : b->groups) {
+        G.block = block;
+        G.grid = b->n_cu * wg_per_cu;
+        G.tune_ms = 0.0;
+    }
+    b->tuned = true;
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return NLFEM_OK;
+}
+
 nlfem_status nlfem_batch_destroy(nlfem_batch* b) {
     if (!b) return NLFEM_E_INVALID_ARG;
     batch_free(b);

@@ -94,6 +94,27 @@ def test_batch_lds_groups(dev):
     batch.destroy()
 
 
+@pytest.mark.parametrize("shape", [(256, 3), (128, 6), (256, 0), (128, 0)])
+def test_batch_launch_shapes(dev, shape):
+    """Both launch forms (persistent grid, one workgroup per item) and both
+    workgroup sizes give each mesh's single-mesh result bitwise."""
+    import paper_2302_07499_amd as P
+    pbs = _mix("fp64", count=5, seed=9)
+    batch = P.Batch(dev, pbs)
+    batch.set_inputs([pb.f_qp for pb in pbs], [pb.g_nodal for pb in pbs])
+    batch.set_launch(*shape)
+    batch.assemble()
+    for i, pb in enumerate(pbs):
+        g = batch.system_numpy(i)
+        e = _eager(dev, pb)
+        for k in ["ff_val", "fc_val", "rhs"]:
+            assert np.array_equal(g[k], e[k]), (shape, i, k)
+    _say(f"shape {shape}: tuning {batch.tuning()}")
+    with pytest.raises(P.NlfemError):
+        batch.set_launch(256, 4)  # 16 waves per CU
+    batch.destroy()
+
+
 def test_batch_matches_oracle(dev, orc):
     import paper_2302_07499_amd as P
     pbs = _mix("fp64", count=4, seed=5)

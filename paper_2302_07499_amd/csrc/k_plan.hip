@@ -253,7 +253,8 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
                                                        const float4* box, Grid g, double delta, int strategy,
                                                        const int64_t* cand_off, int64_t* cand_n, int32_t* cand_m,
                                                        uint32_t* cand_code) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: in a scalar register, the outer tet and its points are too
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
     double P[4][3];
@@ -333,7 +334,8 @@ __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, cons
                                                         const int32_t* cand_m, uint32_t* cand_code) {
     __shared__ int64_t qp[4][kQueue];
     __shared__ uint8_t qk[4][kQueue];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: in a scalar register, the outer tet and its points are too
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
     double P[4][3];
@@ -415,7 +417,8 @@ __device__ __forceinline__ uint32_t strategy_code(uint32_t code, int strategy) {
 // Per outer tet: hits per "number of cut points" bucket (cnt[oi*5 + b]).
 __global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
                                                     int strategy, const uint32_t* cand_code, int64_t* cnt) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: in a scalar register, the outer tet and its points are too
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
     const int64_t src = cand_off[oi], n = cand_n[oi];
@@ -463,7 +466,8 @@ __device__ __forceinline__ int cut_mask(uint32_t c12) {
 __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
                                                       const int64_t* pair_off, int strategy, const int32_t* cand_m,
                                                       const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: in a scalar register, the outer tet and its points are too
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
     if (oi >= n_outer) return;
     const int64_t src = cand_off[oi], n = cand_n[oi];

@@ -913,6 +913,13 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     }
     nlfem_batch* b = new nlfem_batch();
     b->ctx = c;
+    // frees the partial batch on every early return (including HIPCHK's)
+    struct Guard {
+        nlfem_batch* b;
+        ~Guard() {
+            if (b) batch_free(b);
+        }
+    } guard{b};
     b->fp32 = n > 0 && params[0].precision == NLFEM_FP32_LOCAL;
     b->vr = n > 0 && params[0].cap_sampling == NLFEM_CAPS_OUTSIDE_UI;
     hipDeviceProp_t prop;
@@ -925,7 +932,6 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         nlfem_plan* pl = nullptr;
         nlfem_status st = nlfem_plan_create(c, &meshes[i], &params[i], &pl);
         if (st != NLFEM_OK) {
-            batch_free(b);
             return st;
         }
         b->plans.push_back(pl);
@@ -960,7 +966,6 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         o.rhs = (double*)b->alloc((size_t)(nf + 1) * 8);
         o.f2v = (int32_t*)b->alloc((size_t)(nf + 1) * 4);
         if (!o.ff_row_ptr || !o.ff_col || !o.ff_val || !o.fc_row_ptr || !o.fc_col || !o.fc_val || !o.rhs || !o.f2v) {
-            batch_free(b);
             return fail(c, NLFEM_E_OOM, c->err);
         }
         HIPCHK(launch_copy_i64(pl->ff_row_ptr, o.ff_row_ptr, nf + 1, s));
@@ -987,7 +992,6 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     for (size_t g = 0; g < b->groups.size(); ++g) {
         nlfem_batch::Group& G = b->groups[g];
         if (integrate_lds_bytes(G.umax) > c->lds_max) {
-            batch_free(b);
             return fail(c, NLFEM_E_UNSUPPORTED, "batch ball vertex set too large for LDS");
         }
         // longest items first
@@ -999,7 +1003,6 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[g][order[i]];
         G.n_items = (int64_t)sorted.size();
         if (G.n_items > 0x7fffffff) {
-            batch_free(b);
             return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^31-1 outer tets in one batch group");
         }
         // tuning sample: a strided subset of the longest-first list with about
@@ -1013,7 +1016,6 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         G.d_items = (int2*)b->alloc(sorted.size() * sizeof(int2) + 16);
         G.d_head = (unsigned long long*)b->alloc(64);
         if (!G.d_items || !G.d_sample || !G.d_head) {
-            batch_free(b);
             return fail(c, NLFEM_E_OOM, c->err);
         }
         if (!sorted.empty()) {
@@ -1025,7 +1027,6 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     }
     b->d_descs = (IntegrateArgs*)b->alloc(b->descs.size() * sizeof(IntegrateArgs) + 16);
     if (!b->d_descs) {
-        batch_free(b);
         return fail(c, NLFEM_E_OOM, c->err);
     }
     if (!b->descs.empty())
@@ -1035,9 +1036,9 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     if (hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
-        batch_free(b);
         return fail(c, NLFEM_E_DEVICE, "stream/event creation failed");
     }
+    guard.b = nullptr;
     *out = b;
     return NLFEM_OK;
 }

@@ -83,6 +83,8 @@ def lib():
         L.or_pair_geometry.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, P, P, P, P,
                                        P, P, P]
         L.or_pair_geometry.restype = C.c_int
+        L.or_cap_region.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, P, P]
+        L.or_cap_region.restype = C.c_int
         L.or_assemble.argtypes = [C.POINTER(OrProblem), C.POINTER(OrSystem)]
         L.or_assemble.restype = C.c_int
         L.or_system_free.argtypes = [C.POINTER(OrSystem)]
@@ -163,6 +165,18 @@ def pair_geometry(coords, tets, n, k, m, delta):
     return {"n_in": nin, "t": t.reshape(4, 4), "sub": sub.reshape(3, 4, 4)[:max(ns.value, 0)],
             "subvol": subvol[:max(ns.value, 0)], "planes": plane.reshape(2, 4)[:max(npl.value, 0)],
             "split": split.value}
+
+
+def cap_region(coords, tets, n, k, m, delta):
+    """Sub-tets of the cap region E - U_I of pair (4 n + k, m) as sampled with
+    cap sampling on: (rows [j, 4, 4] barycentric in E, point 0 the apex, and
+    volumes [j]); None when the pair is not cut, no sub-tets for CUT(0)."""
+    coords = _c(coords, np.float64); tets = _c(tets, np.int32)
+    rows = np.zeros(48); vol = np.zeros(3)
+    n_sub = lib().or_cap_region(_p(coords), _p(tets), n, k, m, delta, _p(rows), _p(vol))
+    if n_sub < 0:
+        return None
+    return rows.reshape(3, 4, 4)[:n_sub], vol[:n_sub]
 
 
 def gpoly_coef(g_poly):

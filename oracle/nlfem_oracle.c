@@ -463,12 +463,102 @@ typedef struct {
     cutgeom g;
     int N;
     int caps; /* 1: the fullcaps Monte Carlo term is part of the pair */
-    int cap_sampling; /* 1: for n_in = 3 the caps are sampled on E - U_I (a corner tet) */
+    int cap_sampling; /* 1: for n_in >= 1 the caps are sampled on E - U_I (cap_region) */
     uint64_t seed;
     uint32_t q, m;
 } pairctx;
 
 typedef void (*node_fn)(void *user, const double lam[4], double w, int is_mc);
+
+/* ------------------------------------------------------------------------ */
+/* The cap region E - U_I (closure of E minus the inner polytope), sampled
+ * instead of the whole E when cap sampling is on (Sec. 4.2.2 leaves the
+ * sampling of the caps open).  U_I = E n {planes >= 0}; the first outside
+ * vertex o = O[0] lies strictly outside every plane (each plane separates the
+ * inside from the outside vertices along the edges it cuts), and a point of E
+ * outside U_I lies outside at least one plane, so the segment from o to it
+ * stays outside U_I: E - U_I is star-shaped from o.  The cones from o over its
+ * boundary faces that do not contain o therefore tile it:
+ *  - n_in = 3 (inside a0 < a1 < a2): one face, the cut triangle; the corner
+ *    tet (o; P_a0o, P_a1o, P_a2o);
+ *  - n_in = 1 (inside a, outside o < c < d): the cut triangle (P_ao, P_ac,
+ *    P_ad) and the quad (c, d, P_ad, P_ac) left of face a c d, halved on its
+ *    diagonal c-P_ad: (o; P_ao, P_ac, P_ad), (o; c, d, P_ad), (o; c, P_ad, P_ac);
+ *  - n_in = 2 (inside a < b, outside o < d): the triangle (d, P_ad, P_bd) left
+ *    of face a b d and the two triangles of U_I's inner quad on the diagonal
+ *    U_I uses; P_ao-P_bd: (o; d, P_ad, P_bd), (o; P_ao, P_ad, P_bd),
+ *    (o; P_ao, P_bo, P_bd); P_ad-P_bo: (o; d, P_ad, P_bd), (o; P_ao, P_ad, P_bo),
+ *    (o; P_ad, P_bo, P_bd).
+ * P_xy is the sphere crossing on the edge from inside x to outside y.  A
+ * point's offset from p is X_a - p for a vertex and (X_x - p) + t (X_y - X_x)
+ * (one FMA) for a crossing.  The corner tet's volume is
+ * |E| (1 - t_0)(1 - t_1)(1 - t_2), a cone tet's |E| |det of its rows|.       */
+typedef struct {
+    int a, b; /* vertex a (b < 0) or the crossing on edge a -> b */
+} rpoint;
+
+typedef struct {
+    int n;               /* sub-tets: 1 (n_in = 3) or 3 (n_in = 1, 2) */
+    double row[3][4][4]; /* sub-tet j, point r (r = 0: o), barycentric component */
+    double e[3][4][3];   /* point minus p */
+    double vol[3];
+} capregion;
+
+static void region_point(const pairctx *c, rpoint q, double row[4], double e[3]) {
+    if (q.b < 0) {
+        unit(q.a, row);
+        for (int i = 0; i < 3; ++i) e[i] = c->X[q.a][i] - c->p[i];
+    } else {
+        const double t = c->g.t[q.a][q.b];
+        edge_point(&c->g, q.a, q.b, row);
+        for (int i = 0; i < 3; ++i) e[i] = fma(t, c->X[q.b][i] - c->X[q.a][i], c->X[q.a][i] - c->p[i]);
+    }
+}
+
+static int cap_region(const pairctx *c, capregion *r) {
+    const cutgeom *g = &c->g;
+    const int o = g->O[0];
+    rpoint V[3][4];
+    for (int j = 0; j < 3; ++j) V[j][0] = (rpoint){o, -1};
+    if (g->n_in == 3) {
+        r->n = 1;
+        for (int l = 0; l < 3; ++l) V[0][1 + l] = (rpoint){g->I[l], o};
+    } else if (g->n_in == 1) {
+        const int a = g->I[0], cc = g->O[1], d = g->O[2];
+        r->n = 3;
+        V[0][1] = (rpoint){a, o};   V[0][2] = (rpoint){a, cc};  V[0][3] = (rpoint){a, d};
+        V[1][1] = (rpoint){cc, -1}; V[1][2] = (rpoint){d, -1};  V[1][3] = (rpoint){a, d};
+        V[2][1] = (rpoint){cc, -1}; V[2][2] = (rpoint){a, d};   V[2][3] = (rpoint){a, cc};
+    } else if (g->n_in == 2) {
+        const int a = g->I[0], b = g->I[1], d = g->O[1];
+        r->n = 3;
+        V[0][1] = (rpoint){d, -1}; V[0][2] = (rpoint){a, d}; V[0][3] = (rpoint){b, d};
+        if (g->split == 1) {
+            V[1][1] = (rpoint){a, o}; V[1][2] = (rpoint){a, d}; V[1][3] = (rpoint){b, d};
+            V[2][1] = (rpoint){a, o}; V[2][2] = (rpoint){b, o}; V[2][3] = (rpoint){b, d};
+        } else {
+            V[1][1] = (rpoint){a, o}; V[1][2] = (rpoint){a, d}; V[1][3] = (rpoint){b, o};
+            V[2][1] = (rpoint){a, d}; V[2][2] = (rpoint){b, o}; V[2][3] = (rpoint){b, d};
+        }
+    } else {
+        return 0;
+    }
+    for (int j = 0; j < r->n; ++j)
+        for (int q = 0; q < 4; ++q) region_point(c, V[j][q], r->row[j][q], r->e[j][q]);
+    if (r->n == 1) {
+        double rho = 1.0;
+        for (int l = 0; l < 3; ++l) {
+            const double t = g->t[g->I[l]][o];
+            rho = (l == 0) ? 1.0 - t : rho * (1.0 - t);
+        }
+        r->vol[0] = c->vol * rho;
+    } else {
+        for (int j = 0; j < 3; ++j)
+            r->vol[j] = c->vol * fabs(det3_bary(r->row[j][0], r->row[j][1], r->row[j][2], r->row[j][3]));
+    }
+    return 1;
+}
+
 
 /* a . b as the FMA chain fma(a_z, b_z, fma(a_y, b_y, a_x b_x)) */
 static double dotf(const double a[3], const double b[3]) {
@@ -502,80 +592,77 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
      * F_l = (X_l - p) - (X_0 - p); |y - p|^2 is evaluated as its quadratic form in
      * lambda_1..3 (coefficients below), the U_I planes as FMA chains over l.   */
     if (!c->caps) return;
-    /* Sampling region: the whole E (samples in U_I rejected), or, for n_in = 3
-     * with cap sampling on, E - U_I itself: the corner tet with vertices
-     * Y_0 = X_o and Y_l = X_{a_l} + t (X_o - X_{a_l}) (o the outside vertex,
-     * a_l the inside ones ascending, t the sphere crossing on a_l -> o), of
-     * volume |E| (1 - t_0)(1 - t_1)(1 - t_2).  A sample's region coordinates
-     * mu give its barycentrics in E as lambda = sum_j mu_j row(Y_j).        */
-    int corner = c->cap_sampling && g->n_in == 3;
-    double e[4][3], row[4][4], vol_r = c->vol;
-    if (corner) {
-        int o = g->O[0];
-        for (int i = 0; i < 3; ++i) e[0][i] = c->X[o][i] - c->p[i];
-        unit(o, row[0]);
-        double rho = 1.0;
-        for (int l = 0; l < 3; ++l) {
-            int a = g->I[l];
-            double t = g->t[a][o];
-            for (int i = 0; i < 3; ++i) e[1 + l][i] = fma(t, c->X[o][i] - c->X[a][i], c->X[a][i] - c->p[i]);
-            for (int v = 0; v < 4; ++v) row[1 + l][v] = v == a ? 1.0 - t : (v == o ? t : 0.0);
-            rho = (l == 0) ? 1.0 - t : rho * (1.0 - t);
+    /* Sampling region: the whole E (samples in U_I rejected), or, with cap
+     * sampling on and n_in >= 1, E - U_I itself (cap_region), no U_I test.
+     * Sub-tet j of n takes the samples s with floor(j N / n) <= s <
+     * floor((j + 1) N / n), N_j of them (N >= 3), each of weight |T_j| / N_j;
+     * a sample's coordinates mu in T_j give its barycentrics in E as
+     * lambda = sum_r mu_r row(T_j, r).                                        */
+    capregion R;
+    const int region = c->cap_sampling && cap_region(c, &R);
+    const int nb = region ? R.n : 1;
+    for (int j = 0; j < nb; ++j) {
+        double e[4][3];
+        for (int l = 0; l < 4; ++l)
+            for (int i = 0; i < 3; ++i) e[l][i] = region ? R.e[j][l][i] : c->X[l][i] - c->p[i];
+        double f[4][3];
+        for (int l = 1; l < 4; ++l)
+            for (int i = 0; i < 3; ++i) f[l][i] = e[l][i] - e[0][i];
+        /* |y - p|^2 = |e_0 + sum_l mu_l F_l|^2 written out as the quadratic form
+         * q0 + sum_l mu_l (qb_l + qa_ll mu_l + sum_{j>l} qa_lj mu_j) with
+         * q0 = e_0.e_0, qb_l = 2 e_0.F_l, qa_ll = F_l.F_l, qa_lj = 2 F_l.F_j
+         * (dot products as FMA chains over x, y, z), evaluated as three inner FMA
+         * chains and one outer one */
+        double q0 = dotf(e[0], e[0]);
+        double qb[4], qa[4][4];
+        for (int l = 1; l < 4; ++l) {
+            qb[l] = 2.0 * dotf(e[0], f[l]);
+            for (int i = l; i < 4; ++i) qa[l][i] = (i == l ? 1.0 : 2.0) * dotf(f[l], f[i]);
         }
-        vol_r = c->vol * rho;
-    } else {
-        for (int l = 0; l < 4; ++l) {
-            for (int i = 0; i < 3; ++i) e[l][i] = c->X[l][i] - c->p[i];
-            unit(l, row[l]);
-        }
-    }
-    double f[4][3];
-    for (int l = 1; l < 4; ++l)
-        for (int i = 0; i < 3; ++i) f[l][i] = e[l][i] - e[0][i];
-    /* |y - p|^2 = |e_0 + sum_l mu_l F_l|^2 written out as the quadratic form
-     * q0 + sum_l mu_l (qb_l + qa_ll mu_l + sum_{j>l} qa_lj mu_j) with
-     * q0 = e_0.e_0, qb_l = 2 e_0.F_l, qa_ll = F_l.F_l, qa_lj = 2 F_l.F_j
-     * (dot products as FMA chains over x, y, z), evaluated as three inner FMA
-     * chains and one outer one */
-    double q0 = dotf(e[0], e[0]);
-    double qb[4], qa[4][4];
-    for (int l = 1; l < 4; ++l) {
-        qb[l] = 2.0 * dotf(e[0], f[l]);
-        for (int j = l; j < 4; ++j) qa[l][j] = (j == l ? 1.0 : 2.0) * dotf(f[l], f[j]);
-    }
-    double wmc = vol_r / (double)c->N;
-    for (int s = 0; s < c->N; ++s) {
-        double mu[4];
-        or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, mu);
-        double t1 = fma(qa[1][3], mu[3], fma(qa[1][2], mu[2], fma(qa[1][1], mu[1], qb[1])));
-        double t2 = fma(qa[2][3], mu[3], fma(qa[2][2], mu[2], qb[2]));
-        double t3 = fma(qa[3][3], mu[3], qb[3]);
-        double rr = fma(mu[3], t3, fma(mu[2], t2, fma(mu[1], t1, q0)));
-        if (!(rr < c->d2)) continue;
-        if (corner) {
-            double lam[4];
-            for (int v = 0; v < 4; ++v)
-                lam[v] = ((mu[0] * row[0][v] + mu[1] * row[1][v]) + mu[2] * row[2][v]) + mu[3] * row[3][v];
-            fn(user, lam, wmc, 1);
-        } else if (!in_UI(g, mu)) {
-            fn(user, mu, wmc, 1);
+        const int s0 = (int)(((int64_t)j * c->N) / nb), s1 = (int)(((int64_t)(j + 1) * c->N) / nb);
+        const double wmc = (region ? R.vol[j] : c->vol) / (double)(s1 - s0);
+        for (int s = s0; s < s1; ++s) {
+            double mu[4];
+            or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, mu);
+            double t1 = fma(qa[1][3], mu[3], fma(qa[1][2], mu[2], fma(qa[1][1], mu[1], qb[1])));
+            double t2 = fma(qa[2][3], mu[3], fma(qa[2][2], mu[2], qb[2]));
+            double t3 = fma(qa[3][3], mu[3], qb[3]);
+            double rr = fma(mu[3], t3, fma(mu[2], t2, fma(mu[1], t1, q0)));
+            if (!(rr < c->d2)) continue;
+            if (region) {
+                double lam[4];
+                for (int v = 0; v < 4; ++v)
+                    lam[v] = ((mu[0] * R.row[j][0][v] + mu[1] * R.row[j][1][v]) + mu[2] * R.row[j][2][v]) +
+                             mu[3] * R.row[j][3][v];
+                fn(user, lam, wmc, 1);
+            } else if (!in_UI(g, mu)) {
+                fn(user, mu, wmc, 1);
+            }
         }
     }
 }
 
 /* Moments of the pair: S0 = sum w, S1_j = sum w lam_j, S2_ij = sum w lam_i
  * lam_j (upper triangle 00,01,02,03,11,12,13,22,23,33).  The deterministic
- * nodes are summed one by one; the Monte Carlo part is summed as exact dyadic
- * counts and scaled by |E_m|/N once.                                         */
+ * nodes are summed one by one; the Monte Carlo part is summed per block of
+ * equal weight (exact dyadic counts for the whole element) and each block
+ * scaled by its weight once.                                         */
 typedef struct {
     double det[15];
-    double mc[15];
-    double wmc; /* weight of the Monte Carlo nodes (the same for all of a pair) */
+    double mc[15];   /* the current block of Monte Carlo nodes (one weight) */
+    double wmc;      /* that weight */
+    double done[15]; /* earlier blocks, scaled */
+    int nmc;
 } momacc;
 
 static void mom_node(void *user, const double lam[4], double w, int is_mc) {
     momacc *a = (momacc *)user;
     if (is_mc) {
+        if (a->nmc > 0 && w != a->wmc) {
+            for (int k = 0; k < 15; ++k) a->done[k] += a->wmc * a->mc[k];
+            memset(a->mc, 0, sizeof a->mc);
+        }
+        a->nmc++;
         a->wmc = w;
         a->mc[0] += 1.0;
         for (int j = 0; j < 4; ++j) a->mc[1 + j] += lam[j];
@@ -611,7 +698,7 @@ static void pair_moments(const pairctx *c, double S[15]) {
     momacc a;
     memset(&a, 0, sizeof a);
     visit_nodes(c, mom_node, &a);
-    for (int k = 0; k < 15; ++k) S[k] = a.det[k] + a.wmc * a.mc[k];
+    for (int k = 0; k < 15; ++k) S[k] = a.det[k] + (a.done[k] + a.wmc * a.mc[k]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -698,6 +785,29 @@ int or_pair_geometry(const double *coords, const int32_t *tets, int64_t n, int k
     return c.g.n_in;
 }
 
+/* the cap region E - U_I of pair (q = 4 n + k, m): its sub-tets' barycentric
+ * rows [3][4][4] and volumes; returns the number of sub-tets (0 for CUT(0)),
+ * -1 when the pair is not cut */
+int or_cap_region(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m, double delta,
+                  double row_out[48], double vol_out[3]) {
+    double Xn[4][3], Xm[4][3], p[3];
+    rule_init();
+    load_tet(coords, tets, n, Xn);
+    outer_point(Xn, k, p);
+    load_tet(coords, tets, m, Xm);
+    pairctx c;
+    pair_setup(&c, Xm, p, delta, 3, 0, 0, 0, OR_FULLCAPS, 1);
+    if (c.cls < OR_CUT0) return -1;
+    capregion R;
+    if (!cap_region(&c, &R)) return 0;
+    for (int j = 0; j < R.n; ++j) {
+        vol_out[j] = R.vol[j];
+        for (int r = 0; r < 4; ++r)
+            for (int l = 0; l < 4; ++l) row_out[16 * j + 4 * r + l] = R.row[j][r][l];
+    }
+    return R.n;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Assembly (Sec. 4.3, main algorithm).                                      */
 typedef struct {
@@ -713,7 +823,7 @@ typedef struct {
     const double *f_qp;        /* optional [n_tets][4] */
     const double *g_nodal;     /* optional [n_vertices] */
     int32_t strategy;          /* OR_FULLCAPS .. OR_BARYCENTER */
-    int32_t cap_sampling;      /* 1: n_in = 3 caps sampled on the corner tet E - U_I */
+    int32_t cap_sampling;      /* 1: caps of n_in >= 1 sampled on E - U_I (N >= 3) */
     int32_t g_degree;          /* per-axis degree of g_coef */
     const double *g_coef;      /* optional: g as a tensor polynomial -> the right-hand side of
                                   eq. F1.5 with g itself inside the inner integrals of eq. Fh */
@@ -849,6 +959,7 @@ static int validate(const or_problem *P) {
     if (!(P->delta > 0.0) || P->mc_samples < 1) return 1;
     if (P->strategy < OR_FULLCAPS || P->strategy > OR_BARYCENTER) return 1;
     if (P->cap_sampling != 0 && P->cap_sampling != 1) return 1;
+    if (P->cap_sampling == 1 && P->mc_samples < 3) return 1;
     if (P->g_coef && (P->g_degree < 0 || P->g_degree > 4 || P->cap_sampling != 0)) return 1;
     if (P->n_tets > 0 && (!P->coords || !P->tets || !P->vertex_free)) return 1;
     for (int64_t i = 0; i < 4 * P->n_tets; ++i)

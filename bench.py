@@ -198,7 +198,7 @@ def run_precision(P, mg, dev, args):
             ms = 1e3 * float(np.mean(ts))
             strategies[st] = {"value": round(npairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
                               "pairs_per_step": npairs, "integrate_ms": round(float(np.mean(tks[:, 3])), 3)}
-        # fullcaps with the n_in = 3 caps sampled on the corner tet E - U_I, and the
+        # fullcaps with the caps sampled on E - U_I (corner tet or three cone tets), and the
         # seed-to-seed spread of the matrix entries in both sampling modes
         ts, tks, inf, pl, sm = run("fp64", 2, 1, "fullcaps", "outside_ui")
         pl.destroy()

@@ -70,9 +70,13 @@ typedef enum {
 /* Where the fullcaps Monte Carlo samples are drawn (strategy fullcaps only).  */
 typedef enum {
     NLFEM_CAPS_WHOLE_ELEMENT = 0, /* uniform on E_m, rejecting U_I (default)                        */
-    NLFEM_CAPS_OUTSIDE_UI = 1     /* uniform on E_m minus U_I where that is one tet (n_in = 3: the
-                                     corner at the outside vertex); same expectation, every sample
-                                     in the cap region; other cases as the default                */
+    NLFEM_CAPS_OUTSIDE_UI = 1     /* uniform on E_m minus U_I, no U_I test: for n_in = 3 the corner
+                                     tet at the outside vertex; for n_in = 1, 2 the three cone tets
+                                     from the first outside vertex over the region's far faces,
+                                     tet j taking the samples floor(j N/3) <= s < floor((j+1) N/3)
+                                     at weight |T_j| / N_j; CUT(0) as the default.  Same
+                                     expectation, lower variance (Sec. 4.2.2 leaves the sampling
+                                     open); needs mc_samples >= 3 (else NLFEM_E_INVALID_ARG)      */
 } nlfem_cap_sampling;
 
 /* Tetrahedral mesh of Omega u Omega_I (Sec. 3.1: coinciding triangulations of

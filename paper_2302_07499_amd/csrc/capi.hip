@@ -744,6 +744,8 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
         return fail(c, NLFEM_E_INVALID_ARG, "unknown ball approximation strategy");
     if (prm->cap_sampling != NLFEM_CAPS_WHOLE_ELEMENT && prm->cap_sampling != NLFEM_CAPS_OUTSIDE_UI)
         return fail(c, NLFEM_E_INVALID_ARG, "unknown cap sampling mode");
+    if (prm->cap_sampling == NLFEM_CAPS_OUTSIDE_UI && prm->mc_samples < 3)
+        return fail(c, NLFEM_E_INVALID_ARG, "cap sampling on E_m minus U_I needs mc_samples >= 3");
     if (mesh->n_tets >= (int64_t)1 << 31 || mesh->n_vertices >= (int64_t)1 << 31)
         return fail(c, NLFEM_E_UNSUPPORTED, "mesh larger than 2^31 entities");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");

@@ -110,7 +110,7 @@ struct IntegrateArgs {
     double delta, psi;
     int mc_samples;
     int caps;  // 1: cut points add the fullcaps Monte Carlo term (strategy fullcaps)
-    int vr;    // 1: caps of n_in = 3 points sampled on E_m minus U_I (the corner tet)
+    int vr;    // 1: caps of cut pairs with n_in >= 1 sampled on E_m minus U_I (cone tets)
     uint32_t key0, key1;
     int fx_shift;  // scale 2^fx_shift of the LDS sums T0 and R
     int g_shift;   // scale of the cut part of G_m (global accumulators)

@@ -251,14 +251,24 @@ struct CutGeom {
     double c0[4], c1[4];  // U_I = E n {c0.l >= 0} [n {c1.l >= 0}]
 };
 
-// E_m minus U_I when it is a single tet (n_in = 3): the corner at the outside
-// vertex o, with vertices X_o and the sphere crossings X_a + t (X_o - X_a) on
-// the edges from the inside vertices a[0..2] (ascending).  Used when the caps
-// are sampled over E_m minus U_I instead of the whole E_m.
+// Hull point of U_I: the barycentric point (1 - t) e_a + t e_b, or the
+// vertex e_a when b < 0.
+struct HullPt {
+    int a, b;
+    double t;
+};
+
+// The cap region E_m minus U_I, sampled instead of the whole E_m when the
+// caps are sampled on it.  It is star-shaped from the first outside vertex o
+// (o lies outside every plane of U_I, and a point of E_m outside U_I lies
+// outside one of them), so the cones from o over its faces that do not
+// contain o tile it: one corner tet for n_in = 3, three tets for n_in = 1, 2
+// (built in cut_build); n = 0 for CUT(0), which samples the whole element.
+// Sub-tet j is (o, v[j][0], v[j][1], v[j][2]) with physical volume vol[j].
 struct CornerGeom {
-    bool on;
-    int o, a[3];
-    double t[3];
+    int n, o;
+    HullPt v[3][3];
+    double vol[3];
 };
 
 __device__ __forceinline__ double det3m(double a0, double a1, double a2, double b0, double b1, double b2, double c0,
@@ -273,12 +283,6 @@ __device__ __forceinline__ double det3_bary(const double* b0, const double* b1, 
     return ax * (by * cz - bz * cy) - ay * (bx * cz - bz * cx) + az * (bx * cy - by * cx);
 }
 
-// Hull point of U_I: the barycentric point (1 - t) e_a + t e_b, or the
-// vertex e_a when b < 0.
-struct HullPt {
-    int a, b;
-    double t;
-};
 
 __device__ __forceinline__ void hull_dense(const HullPt& h, double* e) {
 #pragma unroll
@@ -383,12 +387,6 @@ __device__ __forceinline__ void cut_build(const double* Xg, const double* p, dou
     const HullPt x2 = cross(any, c3 ? I1 : I0, c3 ? O0 : O1);      // P_I0O1 | P_I1O0 (n_in = 3)
     const HullPt x3 = cross(any, c1 ? I0 : (c2 ? I1 : I2), c1 ? O2 : (c2 ? O1 : O0));  // h5
     const HullPt x4 = cross(c2, I1, O0);                           // P_I1O0 (n_in = 2)
-    if (cr) {
-        cr->on = c3;
-        cr->o = x1.b;
-        cr->a[0] = x1.a; cr->a[1] = x2.a; cr->a[2] = x3.a;
-        cr->t[0] = x1.t; cr->t[1] = x2.t; cr->t[2] = x3.t;
-    }
     const int v0 = any ? I0 : 0;
     const HullPt h0{v0, -1, 0.0};
     // (n_in = 0 lanes take h0 everywhere: their dummy crossings may be NaN)
@@ -410,6 +408,36 @@ __device__ __forceinline__ void cut_build(const double* Xg, const double* p, dou
     const double d124 = fabs(det3_bary(H0, H1, H2, H4)), d245 = fabs(det3_bary(H0, H2, H4, H5));
     const double v1 = (d125 + d145) + d345, v2 = (d124 + d245) + d345;
     const bool alt = c2 && !(v1 >= v2);  // second diagonal
+    if (cr) {
+        // cones from o = O0 (P_xy: the crossing on edge x -> y):
+        //   n_in = 3: (o; P_I0o, P_I1o, P_I2o)
+        //   n_in = 1 (a = I0, c = O1, d = O2): (o; P_ao, P_ac, P_ad), (o; c, d, P_ad), (o; c, P_ad, P_ac)
+        //   n_in = 2 (a = I0, b = I1, d = O1): (o; d, P_ad, P_bd), then the two triangles of
+        //   U_I's inner quad on its diagonal: P_ao-P_bd: (o; P_ao, P_ad, P_bd), (o; P_ao, P_bo, P_bd);
+        //   P_ad-P_bo (alt): (o; P_ao, P_ad, P_bo), (o; P_ad, P_bo, P_bd)
+        const HullPt vc{O1, -1, 0.0}, vd{O2, -1, 0.0};
+        cr->o = O0;
+        cr->n = c3 ? 1 : ((c1 || c2) ? 3 : 0);
+        auto set = [&](int j, const HullPt& a, const HullPt& b, const HullPt& c) {
+            cr->v[j][0] = a; cr->v[j][1] = b; cr->v[j][2] = c;
+        };
+        set(0, c2 ? vc : x1, x2, x3);
+        set(1, c1 ? vc : x1, c1 ? vd : x2, c1 ? x3 : (alt ? x4 : x3));
+        set(2, c1 ? vc : (alt ? x2 : x1), c1 ? x3 : x4, c1 ? x2 : x3);
+        if (c3) {
+            cr->vol[0] = vol * (((1.0 - x1.t) * (1.0 - x2.t)) * (1.0 - x3.t));
+        } else if (c1 || c2) {
+            double R0[4], R1[4], R2[4], R3[4];
+            hull_dense(HullPt{O0, -1, 0.0}, R0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                hull_dense(cr->v[j][0], R1);
+                hull_dense(cr->v[j][1], R2);
+                hull_dense(cr->v[j][2], R3);
+                cr->vol[j] = vol * fabs(det3_bary(R0, R1, R2, R3));
+            }
+        }
+    }
     // subtets of T_I: (h0, h1, h2, alt ? h4 : h5), (h0, alt ? h2 : h1, h4, h5), (h0, h3, h4, h5)
     double XA[4], YB[4];
 #pragma unroll
@@ -567,161 +595,240 @@ struct BallForm {
     }
 };
 
+// Monte Carlo sums of one block of samples of a pair, and its moments.
+//
+// The sample barycentrics are lambda = L * 2^-21 with integer L (spacings of
+// 21-bit uniforms).  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3
+// substituted, |y - p|^2 is the quadratic form of BallForm in lambda_1..3 and
+// a plane value c . lambda = c_0 + sum_{l=1..3} lambda_l (c_l - c_0) an FMA
+// chain over l = 1, 2, 3.  The loop works with L itself: the differences are
+// prescaled by 2^-21 (exact), so every product with L equals the lambda
+// form's product exactly and all roundings are those of the lambda form.  The
+// sums are scaled back at the end (exact powers of two).
+//
+// Sums over the accepted samples are integers: the count and sum L_j
+// (j = 1..3) in 32 bits, sum L_i L_j (1 <= i <= j <= 3) in 64 bits (one
+// multiply-add each), exact for N <= 2047.  The L_0 terms follow exactly from
+// sum_l L_l = 2^21, in integers or, equally exactly, in double (every partial
+// sum is a multiple of 2^-42 below 2^11).  Both precisions of the local
+// integrals therefore get the same, exact Monte Carlo moments.
+struct McSums {
+    uint32_t icnt = 0, ia1 = 0, ia2 = 0, ia3 = 0;
+    uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
+    // sample L in the frame (bf, planes pl: p?0 + sum_l L_l p?l >= 0 both means
+    // in U_I, rejected); accepted iff inside the open ball and not in U_I
+    __device__ __forceinline__ void add(const BallForm& bf, const double* pl, double d2, const uint32_t* L) {
+        double l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
+        double rr = bf.eval(l1, l2, l3);
+        double h0 = fma(l3, pl[3], fma(l2, pl[2], fma(l1, pl[1], pl[0])));
+        double h1 = fma(l3, pl[7], fma(l2, pl[6], fma(l1, pl[5], pl[4])));
+        bool inU = (h0 >= 0.0) && (h1 >= 0.0);
+        bool acc = (rr < d2) && !inU;
+        const uint32_t x1 = acc ? L[1] : 0u, x2 = acc ? L[2] : 0u, x3 = acc ? L[3] : 0u;
+        icnt += acc ? 1u : 0u;
+        ia1 += x1; ia2 += x2; ia3 += x3;
+        B11 += (uint64_t)x1 * x1; B12 += (uint64_t)x1 * x2; B13 += (uint64_t)x1 * x3;
+        B22 += (uint64_t)x2 * x2; B23 += (uint64_t)x2 * x3; B33 += (uint64_t)x3 * x3;
+    }
+    // moments of the accepted samples' coordinates, times scale, to S[15]
+    template <typename T>
+    __device__ __forceinline__ void finish(double scale, double* S) const {
+        constexpr bool kF32 = sizeof(T) == 4;
+        const double u = 1.0 / 2097152.0;
+        // L_0 terms in integers (used by the float form below)
+        const uint64_t TT = 2097152ull;
+        const uint64_t A1 = ia1, A2 = ia2, A3 = ia3;
+        const uint64_t A0 = (uint64_t)icnt * TT - A1 - A2 - A3;
+        const uint64_t B01 = A1 * TT - B11 - B12 - B13, B02 = A2 * TT - B12 - B22 - B23,
+                       B03 = A3 * TT - B13 - B23 - B33;
+        const uint64_t B00 = A0 * TT - B01 - B02 - B03;
+        double cnt = (double)icnt, a0 = (double)A0, a1 = (double)A1, a2 = (double)A2, a3 = (double)A3;
+        double b00 = (double)B00, b01 = (double)B01, b02 = (double)B02, b03 = (double)B03, b11 = (double)B11,
+               b12 = (double)B12, b13 = (double)B13, b22 = (double)B22, b23 = (double)B23, b33 = (double)B33;
+        const double u2 = u * u;
+        double dc = (double)cnt, d1 = (double)a1 * u, d2s = (double)a2 * u, d3 = (double)a3 * u;
+        double c11 = (double)b11 * u2, c12 = (double)b12 * u2, c13 = (double)b13 * u2, c22 = (double)b22 * u2,
+               c23 = (double)b23 * u2, c33 = (double)b33 * u2;
+        double d0, c00, c01, c02, c03;
+        if (kF32) {
+            d0 = (double)a0 * u;
+            c00 = (double)b00 * u2;
+            c01 = (double)b01 * u2;
+            c02 = (double)b02 * u2;
+            c03 = (double)b03 * u2;
+        } else {
+            d0 = ((dc - d1) - d2s) - d3;
+            c01 = ((d1 - c11) - c12) - c13;
+            c02 = ((d2s - c12) - c22) - c23;
+            c03 = ((d3 - c13) - c23) - c33;
+            c00 = ((d0 - c01) - c02) - c03;
+        }
+        S[0] = scale * dc; S[1] = scale * d0; S[2] = scale * d1; S[3] = scale * d2s; S[4] = scale * d3;
+        S[5] = scale * c00; S[6] = scale * c01; S[7] = scale * c02; S[8] = scale * c03; S[9] = scale * c11;
+        S[10] = scale * c12; S[11] = scale * c13; S[12] = scale * c22; S[13] = scale * c23; S[14] = scale * c33;
+    }
+};
+
+// The whole element's sample frame: ball form and U_I's planes, prescaled
+__device__ __forceinline__ BallForm whole_frame(const double* X, const double* p, const CutGeom& g, double* pl) {
+    const double u = 1.0 / 2097152.0;
+    const double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
+    const double f1x = ((X[3] - p[0]) - e0x) * u, f1y = ((X[4] - p[1]) - e0y) * u, f1z = ((X[5] - p[2]) - e0z) * u;
+    const double f2x = ((X[6] - p[0]) - e0x) * u, f2y = ((X[7] - p[1]) - e0y) * u, f2z = ((X[8] - p[2]) - e0z) * u;
+    const double f3x = ((X[9] - p[0]) - e0x) * u, f3y = ((X[10] - p[1]) - e0y) * u,
+                 f3z = ((X[11] - p[2]) - e0z) * u;
+    pl[0] = g.c0[0]; pl[1] = (g.c0[1] - g.c0[0]) * u; pl[2] = (g.c0[2] - g.c0[0]) * u; pl[3] = (g.c0[3] - g.c0[0]) * u;
+    pl[4] = g.c1[0]; pl[5] = (g.c1[1] - g.c1[0]) * u; pl[6] = (g.c1[2] - g.c1[0]) * u; pl[7] = (g.c1[3] - g.c1[0]) * u;
+    return BallForm(e0x, e0y, e0z, f1x, f1y, f1z, f2x, f2y, f2z, f3x, f3y, f3z);
+}
+
+// Sub-tet j of the cap region: its ball form, and planes that never hold
+// (no U_I test)
+__device__ __forceinline__ BallForm region_frame(const double* X, const double* p, const CornerGeom* cr, int j,
+                                                 double* pl) {
+    const double u = 1.0 / 2097152.0;
+    const double* Xo = X + 3 * cr->o;
+    const double e0x = Xo[0] - p[0], e0y = Xo[1] - p[1], e0z = Xo[2] - p[2];
+    // point - p: X_a - p for a vertex, (X_a - p) + t (X_b - X_a) as one FMA for a crossing
+    double fy[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const HullPt h = cr->v[j][l];
+        const double* Xa = X + 3 * h.a;
+        const double* Xb = X + 3 * (h.b < 0 ? h.a : h.b);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double e0c = c == 0 ? e0x : (c == 1 ? e0y : e0z);
+            const double ev = h.b < 0 ? Xa[c] - p[c] : fma(h.t, Xb[c] - Xa[c], Xa[c] - p[c]);
+            fy[l][c] = (ev - e0c) * u;
+        }
+    }
+    pl[0] = -1.0; pl[1] = 0.0; pl[2] = 0.0; pl[3] = 0.0;
+    pl[4] = 1.0; pl[5] = 0.0; pl[6] = 0.0; pl[7] = 0.0;
+    return BallForm(e0x, e0y, e0z, fy[0][0], fy[0][1], fy[0][2], fy[1][0], fy[1][1], fy[1][2], fy[2][0], fy[2][1],
+                    fy[2][2]);
+}
+
+// S += the moments Sj of sub-tet j's coordinates mu mapped to E_m's:
+// lambda = A mu with A[v][r] = component v of point r of the sub-tet
+__device__ inline void region_map_add(const CornerGeom* cr, int j, const double* Sj, double* S) {
+    double A[4][4];
+    {
+        double R[4];
+        hull_dense(HullPt{cr->o, -1, 0.0}, R);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[v][0] = R[v];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            hull_dense(cr->v[j][l], R);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A[v][1 + l] = R[v];
+        }
+    }
+    double M2[4][4];
+    int k = 5;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = i; r < 4; ++r) {
+            M2[i][r] = Sj[k];
+            M2[r][i] = Sj[k];
+            ++k;
+        }
+    S[0] += Sj[0];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc = fma(A[v][r], Sj[1 + r], acc);
+        S[1 + v] += acc;
+    }
+    k = 5;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int w = v; w < 4; ++w) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc = fma(A[v][i] * A[w][r], M2[i][r], acc);
+            S[k++] += acc;
+        }
+}
+
+// The Monte Carlo part of a cut pair, over samples 0 <= s < N (Philox
+// counters (q, m, s >> 1, 0), two samples per call): uniform on E_m, those in
+// U_I rejected; or, with the cap region on (VR, cr->n > 0), sub-tet j of n
+// takes the samples floor(j N / n) <= s < floor((j + 1) N / n), N_j of them
+// (N >= 3), with weight |T_j| / N_j and no U_I test, and its moments in the
+// sub-tet's coordinates mu map to E_m's as lambda = sum_r mu_r row(T_j, r).
+// Every lane runs the same sample loop (lanes of other classes in the wave
+// do not serialise it).
 template <typename T, bool VR = false>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
                               const CornerGeom* cr = nullptr) {
-    // The sample barycentrics are lambda = L * 2^-21 with integer L (spacings
-    // of 21-bit uniforms).  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3
-    // substituted, |y - p|^2 is the quadratic form of BallForm in lambda_1..3
-    // and a plane value c . lambda = c_0 + sum_{l=1..3} lambda_l (c_l - c_0)
-    // an FMA chain over l = 1, 2, 3.  The loop works with L itself: the
-    // differences are prescaled by 2^-21 (exact), so every product with L
-    // equals the lambda form's product exactly and all roundings are those of
-    // the lambda form.  The sums are scaled back at the end (exact powers of
-    // two).
-    //
-    // Sums over the accepted samples are integers: the count and sum L_j
-    // (j = 1..3) in 32 bits, sum L_i L_j (1 <= i <= j <= 3) in 64 bits (one
-    // multiply-add each), exact for N <= 2047.  The L_0 terms follow exactly
-    // from sum_l L_l = 2^21, in integers or, equally exactly, in double (every
-    // partial sum is a multiple of 2^-42 below 2^11).  Both precisions of the
-    // local integrals therefore get the same, exact Monte Carlo moments.
-    const double u = 1.0 / 2097152.0;
-    double e0x = X[0] - p[0], e0y = X[1] - p[1], e0z = X[2] - p[2];
-    double f1x = ((X[3] - p[0]) - e0x) * u, f1y = ((X[4] - p[1]) - e0y) * u, f1z = ((X[5] - p[2]) - e0z) * u;
-    double f2x = ((X[6] - p[0]) - e0x) * u, f2y = ((X[7] - p[1]) - e0y) * u, f2z = ((X[8] - p[2]) - e0z) * u;
-    double f3x = ((X[9] - p[0]) - e0x) * u, f3y = ((X[10] - p[1]) - e0y) * u, f3z = ((X[11] - p[2]) - e0z) * u;
-    double p00 = g.c0[0], p01 = (g.c0[1] - g.c0[0]) * u, p02 = (g.c0[2] - g.c0[0]) * u,
-           p03 = (g.c0[3] - g.c0[0]) * u;
-    double p10 = g.c1[0], p11 = (g.c1[1] - g.c1[0]) * u, p12 = (g.c1[2] - g.c1[0]) * u,
-           p13 = (g.c1[3] - g.c1[0]) * u;
-    if constexpr (VR) {
-        if (cr->on) {
-            // samples uniform on the corner tet Y_0 = X_o, Y_l = X_a + t (X_o - X_a);
-            // Y_l - p = (X_a - p) + t (X_o - X_a) as one FMA; no U_I test
-            const double* Xo = X + 3 * cr->o;
-            e0x = Xo[0] - p[0]; e0y = Xo[1] - p[1]; e0z = Xo[2] - p[2];
-            double fy[3][3];
+    double pl[8];
+    if constexpr (!VR) {
+        const BallForm bf = whole_frame(X, p, g, pl);
+        McSums acc;
+        for (int s = 0; s < N; s += 2) {
+            uint32_t w[4];
+            philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
 #pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                const double* Xa = X + 3 * cr->a[l];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double e0c = c == 0 ? e0x : (c == 1 ? e0y : e0z);
-                    fy[l][c] = (fma(cr->t[l], Xo[c] - Xa[c], Xa[c] - p[c]) - e0c) * u;
+            for (int h = 0; h < 2; ++h) {
+                if (s + h < N) {
+                    uint32_t L[4];
+                    lambda_u(w, h, L);
+                    acc.add(bf, pl, d2, L);
                 }
             }
-            f1x = fy[0][0]; f1y = fy[0][1]; f1z = fy[0][2];
-            f2x = fy[1][0]; f2y = fy[1][1]; f2z = fy[1][2];
-            f3x = fy[2][0]; f3y = fy[2][1]; f3z = fy[2][2];
-            p00 = -1.0; p01 = 0.0; p02 = 0.0; p03 = 0.0;
-            p10 = 1.0; p11 = 0.0; p12 = 0.0; p13 = 0.0;
         }
-    }
-    const BallForm bf(e0x, e0y, e0z, f1x, f1y, f1z, f2x, f2y, f2z, f3x, f3y, f3z);
-    constexpr bool kF32 = sizeof(T) == 4;
-    uint32_t icnt = 0, ia1 = 0, ia2 = 0, ia3 = 0;
-    uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
-    for (int s = 0; s < N; s += 2) {
-        uint32_t w[4];
-        philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (s + h < N) {
-                uint32_t L[4];
-                lambda_u(w, h, L);
-                double l1 = (double)L[1], l2 = (double)L[2], l3 = (double)L[3];
-                double rr = bf.eval(l1, l2, l3);
-                double h0 = fma(l3, p03, fma(l2, p02, fma(l1, p01, p00)));
-                double h1 = fma(l3, p13, fma(l2, p12, fma(l1, p11, p10)));
-                bool inU = (h0 >= 0.0) && (h1 >= 0.0);
-                bool acc = (rr < d2) && !inU;
-                const uint32_t x1 = acc ? L[1] : 0u, x2 = acc ? L[2] : 0u, x3 = acc ? L[3] : 0u;
-                icnt += acc ? 1u : 0u;
-                ia1 += x1; ia2 += x2; ia3 += x3;
-                B11 += (uint64_t)x1 * x1; B12 += (uint64_t)x1 * x2; B13 += (uint64_t)x1 * x3;
-                B22 += (uint64_t)x2 * x2; B23 += (uint64_t)x2 * x3; B33 += (uint64_t)x3 * x3;
-            }
-        }
-    }
-    // L_0 terms in integers (used by the float form below)
-    const uint64_t TT = 2097152ull;
-    const uint64_t A1 = ia1, A2 = ia2, A3 = ia3;
-    const uint64_t A0 = (uint64_t)icnt * TT - A1 - A2 - A3;
-    const uint64_t B01 = A1 * TT - B11 - B12 - B13, B02 = A2 * TT - B12 - B22 - B23, B03 = A3 * TT - B13 - B23 - B33;
-    const uint64_t B00 = A0 * TT - B01 - B02 - B03;
-    double cnt = (double)icnt, a0 = (double)A0, a1 = (double)A1, a2 = (double)A2, a3 = (double)A3;
-    double b00 = (double)B00, b01 = (double)B01, b02 = (double)B02, b03 = (double)B03, b11 = (double)B11,
-           b12 = (double)B12, b13 = (double)B13, b22 = (double)B22, b23 = (double)B23, b33 = (double)B33;
-    const double u2 = u * u;
-    double dc = (double)cnt, d1 = (double)a1 * u, d2s = (double)a2 * u, d3 = (double)a3 * u;
-    double c11 = (double)b11 * u2, c12 = (double)b12 * u2, c13 = (double)b13 * u2, c22 = (double)b22 * u2,
-           c23 = (double)b23 * u2, c33 = (double)b33 * u2;
-    double d0, c00, c01, c02, c03;
-    if (kF32) {
-        d0 = (double)a0 * u;
-        c00 = (double)b00 * u2;
-        c01 = (double)b01 * u2;
-        c02 = (double)b02 * u2;
-        c03 = (double)b03 * u2;
+        acc.finish<T>(vol / (double)N, S);
     } else {
-        d0 = ((dc - d1) - d2s) - d3;
-        c01 = ((d1 - c11) - c12) - c13;
-        c02 = ((d2s - c12) - c22) - c23;
-        c03 = ((d3 - c13) - c23) - c33;
-        c00 = ((d0 - c01) - c02) - c03;
-    }
-    const double scale = vol / (double)N;
-    S[0] = scale * dc; S[1] = scale * d0; S[2] = scale * d1; S[3] = scale * d2s; S[4] = scale * d3;
-    S[5] = scale * c00; S[6] = scale * c01; S[7] = scale * c02; S[8] = scale * c03; S[9] = scale * c11;
-    S[10] = scale * c12; S[11] = scale * c13; S[12] = scale * c22; S[13] = scale * c23; S[14] = scale * c33;
-    if constexpr (VR) {
-        if (cr->on) {
-            // moments of the corner-tet coordinates mu -> moments of lambda = A mu,
-            // A[o][0] = 1, A[o][l] = t_l, A[a_l][l] = 1 - t_l; region volume
-            // |E| (1 - t_0)(1 - t_1)(1 - t_2)
-            const double rho = ((1.0 - cr->t[0]) * (1.0 - cr->t[1])) * (1.0 - cr->t[2]);
-            double A[4][4];
+        // nb = 0: the whole element (CUT(0)), 1: the corner tet, 3: three cone tets
+        const int nb = cr->n;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                A[v][0] = v == cr->o ? 1.0 : 0.0;
-#pragma unroll
-                for (int l = 0; l < 3; ++l)
-                    A[v][1 + l] = v == cr->a[l] ? 1.0 - cr->t[l] : (v == cr->o ? cr->t[l] : 0.0);
+        for (int i = 0; i < 15; ++i) S[i] = 0.0;
+        BallForm bf = nb > 0 ? region_frame(X, p, cr, 0, pl) : whole_frame(X, p, g, pl);
+        McSums acc;
+        // the samples in three segments, the same for every lane of the wave
+        // (N is): the cone tets' blocks; a lane with one frame runs through all
+        // three unchanged, a lane with three folds a block and loads the next
+        // frame between segments
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            const int s0 = (j * N) / 3, s1 = ((j + 1) * N) / 3;
+            if (j > 0 && nb == 3) {
+                double Sj[15];
+                acc.finish<T>(cr->vol[j - 1] / (double)(s0 - ((j - 1) * N) / 3), Sj);
+                region_map_add(cr, j - 1, Sj, S);
+                acc = McSums();
+                bf = region_frame(X, p, cr, j, pl);
             }
-            double M1[4], M2[4][4];
+            for (int s = s0 & ~1; s < s1; s += 2) {
+                uint32_t w[4];
+                philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) M1[j] = rho * S[1 + j];
-            int k = 5;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = i; j < 4; ++j) {
-                    M2[i][j] = rho * S[k];
-                    M2[j][i] = M2[i][j];
-                    ++k;
+                for (int h = 0; h < 2; ++h) {
+                    if (s + h >= s0 && s + h < s1) {
+                        uint32_t L[4];
+                        lambda_u(w, h, L);
+                        acc.add(bf, pl, d2, L);
+                    }
                 }
-            S[0] = rho * S[0];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc = fma(A[v][j], M1[j], acc);
-                S[1 + v] = acc;
             }
-            k = 5;
+        }
+        // the last block: samples (2N)/3 .. N of cone tet 2, or all N of the one frame
+        const int jl = nb == 3 ? 2 : 0, sb = nb == 3 ? (2 * N) / 3 : 0;
+        double Sj[15];
+        acc.finish<T>((nb > 0 ? cr->vol[jl] : vol) / (double)(N - sb), Sj);
+        if (nb > 0) {
+            region_map_add(cr, jl, Sj, S);
+        } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int w = v; w < 4; ++w) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) acc = fma(A[v][i] * A[w][j], M2[i][j], acc);
-                    S[k++] = acc;
-                }
+            for (int i = 0; i < 15; ++i) S[i] = Sj[i];
         }
     }
 }

@@ -93,29 +93,30 @@ def test_unknown_strategy_rejected(dev):
     assert ei.value.status == P.NLFEM_E_INVALID_ARG
 
 
-# ---- cap sampling on E_m minus U_I (the corner tet for n_in = 3) ----------
-def test_plain_corner_cap_sampling(dev, orc):
+# ---- cap sampling on E_m minus U_I (corner tet for n_in = 3, three cone tets for n_in = 1, 2)
+def test_plain_region_cap_sampling(dev, orc):
     pb = mg.plain_problem()
     pb.cap_sampling = "outside_ui"
     _check(dev, orc, pb)
 
 
-def test_precision_subset_corner_cap_sampling(dev, orc):
+def test_precision_subset_region_cap_sampling(dev, orc):
     pb = mg.precision_problem()
     pb.cap_sampling = "outside_ui"
     mask = mg.outer_subset_mask(pb.mesh.n_tets, 0.001, seed=23)
     _check(dev, orc, pb, mask)
 
 
-def test_corner_cap_sampling_pair_moments(dev, orc):
-    """per-pair moments of every pair of two outer tets against the oracle"""
+def test_region_cap_sampling_pair_moments(dev, orc):
+    """per-pair moments of every pair of two outer tets against the oracle,
+    cut pairs of every n_in among them"""
     import paper_2302_07499_amd as P
     pb = mg.make_problem("jit", 8, delta_over_h=3.0, jitter=0.2, jitter_seed=5, mc_samples=32, seed=3)
     pb.cap_sampling = "outside_ui"
     plan = dev.plan_problem(pb)
     region = np.array([pb.vertex_free[t].any() for t in pb.mesh.tets])
     outer = np.nonzero(region)[0]
-    n3 = 0
+    seen = {3: 0, 4: 0, 5: 0}
     for n in outer[[0, len(outer) // 2]]:
         rec = plan.debug_pairs(4 * int(n), 4 * int(n) + 4)
         for k in range(4):
@@ -128,9 +129,19 @@ def test_corner_cap_sampling_pair_moments(dev, orc):
             assert np.array_equal(mm, np.nonzero(cls)[0])
             sc = np.maximum(np.abs(S[mm]).max(axis=1, keepdims=True), 1e-300)
             assert np.max(np.abs(rec["S"][sel][order] - S[mm]) / sc) <= 1e-12
-            n3 += int((cls[mm] == 5).sum())
-    assert n3 > 0
+            for c in (3, 4, 5):
+                seen[c] += int((cls[mm] == c).sum())
+    assert min(seen.values()) > 0, seen
     plan.destroy()
+
+
+def test_region_cap_sampling_needs_three_samples(dev):
+    import paper_2302_07499_amd as P
+    m = mg.kuhn_cube_mesh(2)
+    vf = mg.free_mask_box(m.coords, 0.3)
+    with pytest.raises(P.NlfemError) as ei:
+        dev.plan(m.coords, m.tets, vf, 0.3, 1.0, 2, 0, cap_sampling="outside_ui")
+    assert ei.value.status == P.NLFEM_E_INVALID_ARG
 
 
 def test_unknown_cap_sampling_rejected(dev):

@@ -248,11 +248,53 @@ __global__ void k_cand_count(const double* tetX, const int32_t* outer_ids, int64
 //   k_pair_compact    (below) gathers the hits into the pair arrays.
 constexpr uint32_t kPending = 0xFFu;
 
+// orders this wave's LDS writes before its later reads (a wave runs in
+// lockstep; the fences keep the compiler from reordering across)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// classes of candidate j against the four points (one byte per point: IN,
+// CUT(n_in), kPending, or 0 = OUT); 0 if its box is beyond delta of all four
+__device__ __forceinline__ uint32_t classify_candidate(const double* tetX, const uint32_t* cell_tets,
+                                                       const float4* box, int64_t j, const double (*P)[3],
+                                                       double d2, double far2, int strategy, int& m) {
+    const float4 lo = box[2 * j], hi = box[2 * j + 1];
+    bool near = false;
+    for (int k = 0; k < 4; ++k) near = near || !(box_dist2(lo, hi, P[k]) > far2);
+    if (!near) return 0u;
+    m = (int)cell_tets[j];
+    double X[12];
+    for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
+    uint32_t code = 0;
+    for (int k = 0; k < 4; ++k) {
+        int cl;
+        if (strategy == S_BARYCENTER) {
+            cl = barycenter_inside(X, P[k], d2) ? C_IN : C_OUT;
+        } else {
+            cl = classify_fast(X, P[k], d2);
+            // inside: only whole-inside elements; nothing is left pending
+            if (strategy == S_INSIDE && cl != C_IN) cl = C_OUT;
+        }
+        code |= (cl < 0 ? kPending : (uint32_t)cl) << (8 * k);
+    }
+    return code;
+}
+
+// cell rows of one outer tet's candidate region kept in LDS (up to kMaxRows
+// at a time), so that the wave walks the region as one list in full 64-lane
+// chunks across rows
+constexpr int kMaxRows = 256;
+
 __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                                                        const int64_t* cell_start, const uint32_t* cell_tets,
                                                        const float4* box, Grid g, double delta, int strategy,
                                                        const int64_t* cand_off, int64_t* cand_n, int32_t* cand_m,
                                                        uint32_t* cand_code) {
+    __shared__ int64_t row_beg[4][kMaxRows];
+    __shared__ int64_t row_pre[4][kMaxRows + 1];  // candidates before each row
     // the wave index is uniform: in a scalar register, the outer tet and its points are too
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
@@ -272,55 +314,65 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
     // compacted, in candidate order, from the start of the region
     const int64_t base = cand_off[oi];
     int64_t n_hit = 0;
-    for (int cz = z0; cz <= z1; ++cz) {
-        for (int cy = y0; cy <= y1; ++cy) {
-            int x0, x1;
-            if (!row_range(b, g, cy, cz, x0, x1)) continue;
-            const int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
-            const int64_t beg = cell_start[row + x0], end = cell_start[row + x1 + 1];
-            for (int64_t j0 = beg; j0 < end; j0 += 64) {
-                const int64_t j = j0 + lane;
-                uint32_t code = 0;
-                int m = 0;
-                if (j < end) {
-                    const float4 lo = box[2 * j], hi = box[2 * j + 1];
-                    bool near = false;
-                    for (int k = 0; k < 4; ++k) near = near || !(box_dist2(lo, hi, P[k]) > far2);
-                    if (near) {
-                        m = (int)cell_tets[j];
-                        double X[12];
-                        for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
-                        for (int k = 0; k < 4; ++k) {
-                            int cl;
-                            if (strategy == S_BARYCENTER) {
-                                cl = barycenter_inside(X, P[k], d2) ? C_IN : C_OUT;
-                            } else {
-                                cl = classify_fast(X, P[k], d2);
-                                // inside: only whole-inside elements; nothing is left pending
-                                if (strategy == S_INSIDE && cl != C_IN) cl = C_OUT;
-                            }
-                            code |= (cl < 0 ? kPending : (uint32_t)cl) << (8 * k);
-                        }
-                    }
-                }
-                const bool hit = code != 0u;
-                const uint64_t bal = __ballot(hit);
-                if (hit) {
-                    const int64_t pos = base + n_hit + __popcll(bal & lt);
-                    cand_m[pos] = m;
-                    cand_code[pos] = code;
-                }
-                n_hit += __popcll(bal);
-            }
+    auto emit = [&](uint32_t code, int m) {
+        const bool hit = code != 0u;
+        const uint64_t bal = __ballot(hit);
+        if (hit) {
+            const int64_t pos = base + n_hit + __popcll(bal & lt);
+            cand_m[pos] = m;
+            cand_code[pos] = code;
         }
+        n_hit += __popcll(bal);
+    };
+    const int ny = y1 - y0 + 1;
+    const int n_rows = (z1 >= z0 && y1 >= y0) ? ny * (z1 - z0 + 1) : 0;
+    int64_t* RB = row_beg[wave];
+    int64_t* RP = row_pre[wave];
+    // rows in (cz, cy) order, kMaxRows at a time: their first candidate and a
+    // running count, then the candidates of those rows as one list
+    for (int rb = 0; rb < n_rows; rb += kMaxRows) {
+        const int nr = min(kMaxRows, n_rows - rb);
+        int64_t run = 0;
+        for (int r0 = 0; r0 < nr; r0 += 64) {
+            const int r = r0 + lane;
+            int64_t cnt = 0, beg = 0;
+            if (r < nr) {
+                const int cz = z0 + (rb + r) / ny, cy = y0 + (rb + r) % ny;
+                int x0, x1;
+                if (row_range(b, g, cy, cz, x0, x1)) {
+                    const int64_t row = (int64_t)g.nx * ((int64_t)cy + (int64_t)g.ny * cz);
+                    beg = cell_start[row + x0];
+                    cnt = cell_start[row + x1 + 1] - beg;
+                }
+            }
+            // inclusive scan of the counts across the wave
+            int64_t inc = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int64_t v = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += v;
+            }
+            if (r < nr) {
+                RB[r] = beg;
+                RP[r] = run + inc - cnt;
+            }
+            run += __shfl(inc, 63, 64);
+        }
+        if (lane == 0) RP[nr] = run;
+        wave_sync();
+        int r = 0;  // this lane's row cursor: its candidate index only grows
+        for (int64_t c0 = 0; c0 < run; c0 += 64) {
+            const int64_t c = c0 + lane;
+            uint32_t code = 0;
+            int m = 0;
+            if (c < run) {
+                while (RP[r + 1] <= c) ++r;
+                code = classify_candidate(tetX, cell_tets, box, RB[r] + (c - RP[r]), P, d2, far2, strategy, m);
+            }
+            emit(code, m);
+        }
+        wave_sync();  // the next batch of rows overwrites RB and RP
     }
     if (lane == 0) cand_n[oi] = n_hit;
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One wave per outer tet: the pending (candidate, point) cases are queued in

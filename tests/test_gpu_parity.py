@@ -157,6 +157,45 @@ def test_precision_subset_fp32(dev, precision_subset):
     assert e["ff_abs"] <= FP32_TOL and e["fc_abs"] <= FP32_TOL and e["rhs"] <= FP32_TOL
 
 
+def _slab_problem(n, delta_over_h):
+    """n x n Kuhn cubes one cube thick in x (the first layer of the n^3 cube
+    mesh, vertices renumbered), free where min(y, 1-y, z, 1-z) > delta."""
+    full = mg.kuhn_cube_mesh(n)
+    keep = (np.arange(full.n_tets) // 6) % n == 0
+    T = full.tets[keep]
+    used = np.unique(T)
+    remap = np.full(full.coords.shape[0], -1, dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    X = np.ascontiguousarray(full.coords[used])
+    mesh = mg.Mesh(coords=X, tets=np.ascontiguousarray(remap[T].astype(np.int32)), n=n, h=1.0 / n,
+                   info={"kind": "slab"})
+    delta = delta_over_h / n
+    yz = X[:, 1:]
+    free = (np.minimum(yz, 1.0 - yz).min(axis=1) > delta).astype(np.uint8)
+    return mg.Problem(name="slab", mesh=mesh, delta=delta, psi=mg.psi_unit_laplacian(delta), mc_samples=8,
+                      seed=4, vertex_free=free, f_qp=mg.const_f_qp(mesh.n_tets, -2.0),
+                      g_nodal=mg.g_x1_squared(X))
+
+
+def test_wide_horizon_candidate_rows(dev, orc):
+    """A 32 x 32 slab of cubes one cube thick with delta = 10h: the ball of an
+    outer tet spans 484 to 625 cell rows of the candidate grid, more than the
+    fast classification keeps in LDS at a time (256), so it walks them in
+    batches; the ball meets only the slab, so the vertex sets still fit."""
+    pb = _slab_problem(32, 10.0)
+    mask = mg.outer_subset_mask(pb.mesh.n_tets, 0.1, seed=12)
+    plan, s, g = _gpu_system(dev, pb, outer_mask=mask)
+    o = orc.problem_assemble(pb, outer_mask=mask)
+    plan.destroy()
+    assert np.array_equal(g["pair_counts"], o["pair_counts"])
+    H.pattern_equal(g, o)
+    e = H.value_errors(g, o)
+    _say(f"slab fp64 errors {e}")
+    assert e["ff_abs"] <= FP64_TOL and e["fc_abs"] <= FP64_TOL
+    assert e["ff_rel"] <= FP64_TOL and e["fc_rel"] <= FP64_TOL
+    assert e["rhs"] <= FP64_TOL
+
+
 def test_precision_full_sampled_points(dev, orc):
     """Full precision workload in the benchmark's configuration: pair lists and
     moments of sampled outer points against the oracle's brute force, plus

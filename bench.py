@@ -18,8 +18,9 @@ FP32-local), one integration launch per LDS-footprint group of meshes per graph 
 
 Strategies: the same workload assembled with the other ball approximations
 (nocaps, overlap, inside, barycenter; FP64), one line each beside the main
-fullcaps value, and fullcaps with the n_in = 3 caps sampled on the corner tet
-E - U_I, with the seed-to-seed spread of the matrix entries in both modes.
+fullcaps value, and fullcaps with the caps sampled on E - U_I (the corner tet
+for n_in = 3, three cone tets for n_in = 1, 2), with the seed-to-seed spread of
+the matrix entries in both modes.
 
 Convergence: the paper's 3D accuracy experiment (Sec. 5) on synthetic meshes:
 Omega = (0,1)^3, delta = 0.1, u = prod x_d (1 - x_d), Kuhn meshes h = 1/m

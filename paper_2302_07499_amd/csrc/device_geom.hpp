@@ -264,11 +264,10 @@ struct HullPt {
 // outside one of them), so the cones from o over its faces that do not
 // contain o tile it: one corner tet for n_in = 3, three tets for n_in = 1, 2
 // (built in cut_build); n = 0 for CUT(0), which samples the whole element.
-// Sub-tet j is (o, v[j][0], v[j][1], v[j][2]) with physical volume vol[j].
+// Sub-tet j is (o, v[j][0], v[j][1], v[j][2]).
 struct CornerGeom {
     int n, o;
     HullPt v[3][3];
-    double vol[3];
 };
 
 __device__ __forceinline__ double det3m(double a0, double a1, double a2, double b0, double b1, double b2, double c0,
@@ -424,19 +423,6 @@ __device__ __forceinline__ void cut_build(const double* Xg, const double* p, dou
         set(0, c2 ? vc : x1, x2, x3);
         set(1, c1 ? vc : x1, c1 ? vd : x2, c1 ? x3 : (alt ? x4 : x3));
         set(2, c1 ? vc : (alt ? x2 : x1), c1 ? x3 : x4, c1 ? x2 : x3);
-        if (c3) {
-            cr->vol[0] = vol * (((1.0 - x1.t) * (1.0 - x2.t)) * (1.0 - x3.t));
-        } else if (c1 || c2) {
-            double R0[4], R1[4], R2[4], R3[4];
-            hull_dense(HullPt{O0, -1, 0.0}, R0);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                hull_dense(cr->v[j][0], R1);
-                hull_dense(cr->v[j][1], R2);
-                hull_dense(cr->v[j][2], R3);
-                cr->vol[j] = vol * fabs(det3_bary(R0, R1, R2, R3));
-            }
-        }
     }
     // subtets of T_I: (h0, h1, h2, alt ? h4 : h5), (h0, alt ? h2 : h1, h4, h5), (h0, h3, h4, h5)
     double XA[4], YB[4];
@@ -574,6 +560,7 @@ __device__ __forceinline__ double dot3f(double ax, double ay, double az, double 
 }
 struct BallForm {
     double c, b1, b2, b3, a11, a12, a13, a22, a23, a33;
+    BallForm() = default;
     __device__ __forceinline__ BallForm(double ex, double ey, double ez, double f1x, double f1y, double f1z, double f2x,
                                         double f2y, double f2z, double f3x, double f3y, double f3z) {
         c = dot3f(ex, ey, ez, ex, ey, ez);
@@ -709,22 +696,29 @@ __device__ __forceinline__ BallForm region_frame(const double* X, const double* 
                     fy[2][2]);
 }
 
-// S += the moments Sj of sub-tet j's coordinates mu mapped to E_m's:
-// lambda = A mu with A[v][r] = component v of point r of the sub-tet
-__device__ inline void region_map_add(const CornerGeom* cr, int j, const double* Sj, double* S) {
+// Folds the sums of sub-tet j's block (n_s samples) into S: its volume (the
+// corner tet's |E| (1 - t_0)(1 - t_1)(1 - t_2), a cone tet's |E| |det of its
+// barycentric rows|), the moments of its coordinates mu at weight |T_j| / n_s,
+// mapped to E_m's as lambda = A mu with A[v][r] = component v of point r:
+// S1 += A M1, S2 += A M2 A^T (as A M2, then times A^T).
+template <typename T>
+__device__ inline void region_fold(const CornerGeom* cr, int j, double vol, int n_s, const McSums& acc, double* S) {
     double A[4][4];
     {
-        double R[4];
-        hull_dense(HullPt{cr->o, -1, 0.0}, R);
+        double R0[4], R1[4], R2[4], R3[4];
+        hull_dense(HullPt{cr->o, -1, 0.0}, R0);
+        hull_dense(cr->v[j][0], R1);
+        hull_dense(cr->v[j][1], R2);
+        hull_dense(cr->v[j][2], R3);
+        vol = cr->n == 1 ? vol * (((1.0 - cr->v[0][0].t) * (1.0 - cr->v[0][1].t)) * (1.0 - cr->v[0][2].t))
+                         : vol * fabs(det3_bary(R0, R1, R2, R3));
 #pragma unroll
-        for (int v = 0; v < 4; ++v) A[v][0] = R[v];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            hull_dense(cr->v[j][l], R);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) A[v][1 + l] = R[v];
+        for (int v = 0; v < 4; ++v) {
+            A[v][0] = R0[v]; A[v][1] = R1[v]; A[v][2] = R2[v]; A[v][3] = R3[v];
         }
     }
+    double Sj[15];
+    acc.finish<T>(vol / (double)n_s, Sj);
     double M2[4][4];
     int k = 5;
 #pragma unroll
@@ -738,22 +732,30 @@ __device__ inline void region_map_add(const CornerGeom* cr, int j, const double*
     S[0] += Sj[0];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        double acc = 0.0;
+        double acc1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc = fma(A[v][r], Sj[1 + r], acc);
-        S[1 + v] += acc;
+        for (int r = 0; r < 4; ++r) acc1 = fma(A[v][r], Sj[1 + r], acc1);
+        S[1 + v] += acc1;
     }
+    double AM[4][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double a = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a = fma(A[v][i], M2[i][r], a);
+            AM[v][r] = a;
+        }
     k = 5;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int w = v; w < 4; ++w) {
-            double acc = 0.0;
+            double a = 0.0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc = fma(A[v][i] * A[w][r], M2[i][r], acc);
-            S[k++] += acc;
+            for (int r = 0; r < 4; ++r) a = fma(AM[v][r], A[w][r], a);
+            S[k++] += a;
         }
 }
 
@@ -791,22 +793,16 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
         const int nb = cr->n;
 #pragma unroll
         for (int i = 0; i < 15; ++i) S[i] = 0.0;
-        BallForm bf = nb > 0 ? region_frame(X, p, cr, 0, pl) : whole_frame(X, p, g, pl);
+        BallForm bf;
         McSums acc;
         // the samples in three segments, the same for every lane of the wave
-        // (N is): the cone tets' blocks; a lane with one frame runs through all
-        // three unchanged, a lane with three folds a block and loads the next
-        // frame between segments
+        // (N is): the cone tets' blocks.  A lane with one frame loads it before
+        // the first segment and folds after the last; a lane with three loads
+        // and folds one per segment.  (One site each keeps the kernel small.)
 #pragma unroll 1
         for (int j = 0; j < 3; ++j) {
             const int s0 = (j * N) / 3, s1 = ((j + 1) * N) / 3;
-            if (j > 0 && nb == 3) {
-                double Sj[15];
-                acc.finish<T>(cr->vol[j - 1] / (double)(s0 - ((j - 1) * N) / 3), Sj);
-                region_map_add(cr, j - 1, Sj, S);
-                acc = McSums();
-                bf = region_frame(X, p, cr, j, pl);
-            }
+            if (j == 0 || nb == 3) bf = nb > 0 ? region_frame(X, p, cr, j, pl) : whole_frame(X, p, g, pl);
             for (int s = s0 & ~1; s < s1; s += 2) {
                 uint32_t w[4];
                 philox4x32_10(q, m, (uint32_t)(s >> 1), 0u, key0, key1, w);
@@ -819,16 +815,15 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
                     }
                 }
             }
-        }
-        // the last block: samples (2N)/3 .. N of cone tet 2, or all N of the one frame
-        const int jl = nb == 3 ? 2 : 0, sb = nb == 3 ? (2 * N) / 3 : 0;
-        double Sj[15];
-        acc.finish<T>((nb > 0 ? cr->vol[jl] : vol) / (double)(N - sb), Sj);
-        if (nb > 0) {
-            region_map_add(cr, jl, Sj, S);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 15; ++i) S[i] = Sj[i];
+            if (j == 2 || nb == 3) {
+                const int n_s = nb == 3 ? s1 - s0 : N;
+                if (nb > 0) {
+                    region_fold<T>(cr, nb == 3 ? j : 0, vol, n_s, acc, S);
+                } else {
+                    acc.finish<T>(vol / (double)N, S);
+                }
+                acc = McSums();
+            }
         }
     }
 }

@@ -302,7 +302,7 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     ALLOC(pl->inner_cnt, int32_t, K + 1);
     ALLOC(pl->outer_pos, int32_t, K + 1);
     HIPCHK(launch_fill_i32(pl->inner_cnt, K, 0, s));
-    HIPCHK(launch_inner_count(pl->pair_m, P, pl->inner_cnt, s));
+    HIPCHK(launch_inner_count(pl->pair_off, no, pl->pair_m, pl->inner_cnt, s));
     HIPCHK(launch_outer_pos(pl->outer_ids, no, pl->outer_pos, K, s));
     {
         std::vector<int32_t> ic(K);

@@ -181,7 +181,8 @@ hipError_t launch_vt_keys(const int32_t* tets, int64_t K, uint64_t* keys, uint32
 hipError_t launch_offsets(const uint64_t* skeys, int64_t n, int64_t n_keys, int64_t* off, hipStream_t s);
 hipError_t launch_inc_keys(const int64_t* ve_off, int64_t n_outer, const int32_t* ve_ids, uint64_t* keys,
                            uint32_t* vals, int32_t* owner, hipStream_t s);
-hipError_t launch_inner_count(const int32_t* pair_m, int64_t P, int32_t* inner_cnt, hipStream_t s);
+hipError_t launch_inner_count(const int64_t* pair_off, int64_t n_outer, const int32_t* pair_m, int32_t* inner_cnt,
+                              hipStream_t s);
 hipError_t launch_outer_pos(const int32_t* outer_ids, int64_t n_outer, int32_t* outer_pos, int64_t K, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

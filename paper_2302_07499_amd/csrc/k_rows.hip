@@ -49,9 +49,42 @@ __global__ void k_inc_keys(const int64_t* ve_off, int64_t n_outer, const int32_t
     }
 }
 
-__global__ void k_inner_count(const int32_t* pair_m, int64_t P, int32_t* inner_cnt) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < P) atomicAdd(&inner_cnt[pair_m[p]], 1);
+// Pairs per inner tet.  A block takes kInnerGroup consecutive outer tets (mesh
+// order: neighbours, whose balls share most of their inner tets), counts their
+// inner tets in an LDS hash and adds each distinct count to inner_cnt once,
+// instead of one global atomic per pair from blocks that all hit the same
+// inner tets at the same time; an inner tet that finds no slot within
+// kInnerProbe probes is added directly.  The counts are exact either way.
+constexpr int kInnerGroup = 8, kInnerHash = 4096, kInnerProbe = 32;
+__global__ __launch_bounds__(256) void k_inner_count(const int64_t* pair_off, int64_t n_outer, const int32_t* pair_m,
+                                                     int32_t* inner_cnt) {
+    __shared__ int32_t key[kInnerHash];
+    __shared__ int32_t cnt[kInnerHash];
+    for (int i = threadIdx.x; i < kInnerHash; i += blockDim.x) {
+        key[i] = -1;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    const int64_t o0 = (int64_t)blockIdx.x * kInnerGroup;
+    const int64_t o1 = o0 + kInnerGroup < n_outer ? o0 + kInnerGroup : n_outer;
+    const int64_t p1 = pair_off[o1];
+    for (int64_t p = pair_off[o0] + threadIdx.x; p < p1; p += blockDim.x) {
+        const int32_t m = pair_m[p];
+        uint32_t h = ((uint32_t)m * 2654435761u) & (kInnerHash - 1);
+        bool done = false;
+        for (int k = 0; k < kInnerProbe && !done; ++k) {
+            const int32_t prev = atomicCAS(&key[h], -1, m);
+            if (prev == -1 || prev == m) {
+                atomicAdd(&cnt[h], 1);
+                done = true;
+            }
+            h = (h + 1) & (kInnerHash - 1);
+        }
+        if (!done) atomicAdd(&inner_cnt[m], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kInnerHash; i += blockDim.x)
+        if (key[i] >= 0) atomicAdd(&inner_cnt[key[i]], cnt[i]);
 }
 
 __global__ void k_outer_pos(const int32_t* outer_ids, int64_t n_outer, int32_t* outer_pos) {
@@ -416,9 +449,11 @@ hipError_t launch_inc_keys(const int64_t* ve_off, int64_t n_outer, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_inner_count(const int32_t* pair_m, int64_t P, int32_t* inner_cnt, hipStream_t s) {
-    if (P <= 0) return hipSuccess;
-    k_inner_count<<<blocks_for(P), 256, 0, s>>>(pair_m, P, inner_cnt);
+hipError_t launch_inner_count(const int64_t* pair_off, int64_t n_outer, const int32_t* pair_m, int32_t* inner_cnt,
+                              hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    const int64_t blocks = (n_outer + kInnerGroup - 1) / kInnerGroup;
+    k_inner_count<<<(unsigned)blocks, 256, 0, s>>>(pair_off, n_outer, pair_m, inner_cnt);
     return hipGetLastError();
 }
 

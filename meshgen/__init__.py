@@ -143,6 +143,7 @@ class Problem:
     cap_sampling: str = "whole"  # cap samples on the whole element, or on E_m minus U_I ("outside_ui")
     tet_region: np.ndarray | None = None  # explicit T_Omega mask; None: tets with a free vertex
     g_poly: np.ndarray | None = None  # g as tensor coefficients [a, b, c] of y1^a y2^b y3^c, when known
+    keying: str = "pair"  # Monte Carlo samples per (point, element) pair ("pair") or per element ("element")
 
 
 def make_problem(name: str, n: int, delta_over_h: float | None = None, delta: float | None = None,

@@ -35,7 +35,8 @@ class OrProblem(C.Structure):
                 ("tet_region", C.c_void_p), ("delta", C.c_double), ("psi", C.c_double),
                 ("mc_samples", C.c_int32), ("seed", C.c_uint64), ("outer_mask", C.c_void_p),
                 ("f_qp", C.c_void_p), ("g_nodal", C.c_void_p), ("strategy", C.c_int32),
-                ("cap_sampling", C.c_int32), ("g_degree", C.c_int32), ("g_coef", C.c_void_p)]
+                ("cap_sampling", C.c_int32), ("g_degree", C.c_int32), ("g_coef", C.c_void_p),
+                ("keying", C.c_int32)]
 
 
 # ball approximation strategies (Sec. 4.1), as numbered in the oracle
@@ -53,6 +54,14 @@ def _caps(cs):
     return CAP_SAMPLING[cs] if isinstance(cs, str) else int(cs)
 
 
+# Monte Carlo sample keying: N samples per (point, element) pair, or per element
+KEYING = {"pair": 0, "element": 1}
+
+
+def _key(kk):
+    return KEYING[kk] if isinstance(kk, str) else int(kk)
+
+
 class OrSystem(C.Structure):
     _fields_ = [("n_free", C.c_int64), ("nnz_ff", C.c_int64), ("nnz_fc", C.c_int64),
                 ("ff_row_ptr", C.POINTER(C.c_int64)), ("ff_col", C.POINTER(C.c_int32)),
@@ -60,7 +69,8 @@ class OrSystem(C.Structure):
                 ("fc_row_ptr", C.POINTER(C.c_int64)), ("fc_col", C.POINTER(C.c_int32)),
                 ("fc_val", C.POINTER(C.c_double)),
                 ("rhs", C.POINTER(C.c_double)), ("free_to_vertex", C.POINTER(C.c_int32)),
-                ("pair_counts", C.c_int64 * 5)]
+                ("pair_counts", C.c_int64 * 5), ("near_ties", C.c_int64),
+                ("tie_allow", C.POINTER(C.c_double)), ("tie_allow_rhs", C.POINTER(C.c_double))]
 
 
 def lib():
@@ -73,6 +83,15 @@ def lib():
         L.or_rule_constants.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.or_philox4x32_10.argtypes = [P, P, P]
         L.or_sample_lambda.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P]
+        L.or_sample_lambda_keyed.argtypes = [C.c_uint64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, P]
+        L.or_pair_moments_keyed.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, C.c_int,
+                                            C.c_uint64, C.c_int, C.c_int, C.c_int, P, P]
+        L.or_pair_moments_keyed.restype = C.c_int
+        L.or_point_moments_keyed.argtypes = [P, P, C.c_int64, C.c_int64, C.c_int, C.c_double, C.c_int,
+                                             C.c_uint64, C.c_int, C.c_int, C.c_int, P, P, P]
+        L.or_pair_samples.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, C.c_int, C.c_uint64,
+                                      C.c_int, C.c_int, P, P, P]
+        L.or_pair_samples.restype = C.c_int
         L.or_outer_point.argtypes = [P, P, C.c_int64, C.c_int, P]
         L.or_classify_point.argtypes = [P, P, C.c_int64, C.c_double, P, P]
         L.or_pair_moments.argtypes = [P, P, C.c_int64, C.c_int, C.c_int64, C.c_double, C.c_int,
@@ -117,9 +136,9 @@ def philox4x32_10(ctr, key):
     return out
 
 
-def sample_lambda(seed, q, m, s):
+def sample_lambda(seed, q, m, s, keying="pair"):
     lam = np.zeros(4)
-    lib().or_sample_lambda(seed, q, m, s, _p(lam))
+    lib().or_sample_lambda_keyed(seed, _key(keying), q, m, s, _p(lam))
     return lam
 
 
@@ -138,22 +157,41 @@ def classify_point(coords, tets, delta, p):
     return out
 
 
-def pair_moments(coords, tets, n, k, m, delta, N, seed, strategy="fullcaps", cap_sampling="whole"):
+def pair_moments(coords, tets, n, k, m, delta, N, seed, strategy="fullcaps", cap_sampling="whole",
+                 keying="pair", with_ties=False):
+    """(class, S[15]) of pair (4 n + k, m); with_ties: (class, S, near ties)."""
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
     S = np.zeros(15)
-    cls = lib().or_pair_moments(_p(coords), _p(tets), n, k, m, delta, N, seed, _strategy(strategy),
-                                _caps(cap_sampling), _p(S))
-    return cls, S
+    ties = C.c_int32()
+    cls = lib().or_pair_moments_keyed(_p(coords), _p(tets), n, k, m, delta, N, seed, _strategy(strategy),
+                                      _caps(cap_sampling), _key(keying), _p(S), C.byref(ties))
+    return (cls, S, ties.value) if with_ties else (cls, S)
 
 
-def point_moments(coords, tets, n, k, delta, N, seed, strategy="fullcaps", cap_sampling="whole"):
+def point_moments(coords, tets, n, k, delta, N, seed, strategy="fullcaps", cap_sampling="whole",
+                  keying="pair", with_ties=False):
+    """Classes [K] and moments [K, 15] of outer point 4 n + k against every
+    tet; with_ties: also the near-tie count of each pair's samples."""
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
     K = tets.shape[0]
     cls = np.zeros(K, dtype=np.int8)
     S = np.zeros((K, 15))
-    lib().or_point_moments(_p(coords), _p(tets), K, n, k, delta, N, seed, _strategy(strategy), _caps(cap_sampling),
-                           _p(cls), _p(S))
-    return cls, S
+    ties = np.zeros(K, dtype=np.int32)
+    lib().or_point_moments_keyed(_p(coords), _p(tets), K, n, k, delta, N, seed, _strategy(strategy),
+                                 _caps(cap_sampling), _key(keying), _p(cls), _p(S), _p(ties))
+    return (cls, S, ties) if with_ties else (cls, S)
+
+
+def pair_samples(coords, tets, n, k, m, delta, N, seed, cap_sampling="whole", keying="pair"):
+    """Per Monte Carlo sample of pair (4 n + k, m): |y - p|^2 as the oracle's
+    sample test evaluates it, accepted, near tie.  (class, rr, acc, tie)."""
+    coords = _c(coords, np.float64); tets = _c(tets, np.int32)
+    rr = np.full(N, np.nan)
+    acc = np.zeros(N, dtype=np.int8)
+    tie = np.zeros(N, dtype=np.int8)
+    cls = lib().or_pair_samples(_p(coords), _p(tets), n, k, m, delta, N, seed, _caps(cap_sampling), _key(keying),
+                                _p(rr), _p(acc), _p(tie))
+    return cls, rr, acc.astype(bool), tie.astype(bool)
 
 
 def pair_geometry(coords, tets, n, k, m, delta):
@@ -189,8 +227,10 @@ def gpoly_coef(g_poly):
 
 
 def assemble(coords, tets, vertex_free, delta, psi, mc_samples, seed, f_qp=None, g_nodal=None,
-             tet_region=None, outer_mask=None, strategy="fullcaps", cap_sampling="whole", g_poly=None):
-    """Full oracle assembly.  Returns a dict of numpy arrays (CSR blocks + rhs).
+             tet_region=None, outer_mask=None, strategy="fullcaps", cap_sampling="whole", g_poly=None,
+             keying="pair"):
+    """Full oracle assembly.  Returns a dict of numpy arrays (CSR blocks + rhs)
+    and the near-tie report (near_ties; tie_allow / tie_allow_rhs per free row).
     With g_poly (tensor coefficients [a, b, c]) the right-hand side uses g
     itself inside the inner integrals over Omega_I (eqs. Fh, F1.5)."""
     coords = _c(coords, np.float64); tets = _c(tets, np.int32)
@@ -199,7 +239,7 @@ def assemble(coords, tets, vertex_free, delta, psi, mc_samples, seed, f_qp=None,
     gdeg, gc = (0, None) if g_poly is None else gpoly_coef(g_poly)
     P = OrProblem(coords.shape[0], tets.shape[0], _p(coords), _p(tets), _p(vf), _p(tr), delta, psi,
                   mc_samples, seed, _p(om), _p(fq), _p(gn), _strategy(strategy), _caps(cap_sampling),
-                  gdeg, _p(gc))
+                  gdeg, _p(gc), _key(keying))
     S = OrSystem()
     rc = lib().or_assemble(C.byref(P), C.byref(S))
     if rc != 0:
@@ -222,6 +262,9 @@ def assemble(coords, tets, vertex_free, delta, psi, mc_samples, seed, f_qp=None,
             "rhs": arr(S.rhs, nf, np.float64),
             "free_to_vertex": arr(S.free_to_vertex, nf, np.int32),
             "pair_counts": np.array(list(S.pair_counts), dtype=np.int64),
+            "near_ties": int(S.near_ties),
+            "tie_allow": arr(S.tie_allow, nf, np.float64),
+            "tie_allow_rhs": arr(S.tie_allow_rhs, nf, np.float64),
         }
         if nf == 0:
             out["ff_row_ptr"] = np.zeros(1, dtype=np.int64)
@@ -249,4 +292,5 @@ def problem_assemble(pb, outer_mask=None, exact_g=False):
                     g_poly=pb.g_poly if exact_g else None,
                     tet_region=getattr(pb, "tet_region", None),
                     strategy=getattr(pb, "strategy", "fullcaps"),
-                    cap_sampling=getattr(pb, "cap_sampling", "whole"))
+                    cap_sampling=getattr(pb, "cap_sampling", "whole"),
+                    keying=getattr(pb, "keying", "pair"))

@@ -89,10 +89,15 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 /* Uniform point in a tetrahedron as barycentric coordinates: the spacings of
  * three sorted uniform integers on [0, 2^21) are a Dirichlet(1,1,1,1) draw
  * (Devroye, Non-Uniform Random Variate Generation, spacings of uniform order
- * statistics).  One Philox call (counter = (q, m, s/2, 0), key = seed) feeds
- * two samples: sample s even uses the top 21 bits of words 0..2; sample s odd
- * uses the top 21 bits of word 3 and two 21-bit fields made of the low bits
- * of words 0,1 and 2,3.  All lambdas are exact multiples of 2^-21.            */
+ * statistics).  One Philox call (key = seed) feeds two samples: sample s even
+ * uses the top 21 bits of words 0..2; sample s odd uses the top 21 bits of
+ * word 3 and two 21-bit fields made of the low bits of words 0,1 and 2,3.  All
+ * lambdas are exact multiples of 2^-21.
+ * Counters (the paper leaves the sampling open, Sec. 4.2.2):
+ *   pair keying    (keying 0): (q, m, floor(s/2), 0) -- N samples of their
+ *                  own for every (outer point, element) pair;
+ *   element keying (keying 1): (m, floor(s/2), 0, 1) -- N samples per element
+ *                  E_m, the same points of E_m for every outer point q.      */
 static void sort3(uint32_t *a, uint32_t *b, uint32_t *c) {
     uint32_t t;
     if (*a > *b) { t = *a; *a = *b; *b = t; }
@@ -100,8 +105,14 @@ static void sort3(uint32_t *a, uint32_t *b, uint32_t *c) {
     if (*a > *b) { t = *a; *a = *b; *b = t; }
 }
 
-void or_sample_lambda(uint64_t seed, uint32_t q, uint32_t m, uint32_t s, double lam[4]) {
+void or_sample_lambda_keyed(uint64_t seed, int keying, uint32_t q, uint32_t m, uint32_t s, double lam[4]) {
     uint32_t ctr[4] = {q, m, s >> 1, 0u};
+    if (keying == 1) {
+        ctr[0] = m;
+        ctr[1] = s >> 1;
+        ctr[2] = 0u;
+        ctr[3] = 1u;
+    }
     uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
     uint32_t w[4];
     or_philox4x32_10(ctr, key, w);
@@ -119,6 +130,10 @@ void or_sample_lambda(uint64_t seed, uint32_t q, uint32_t m, uint32_t s, double 
     lam[1] = (double)(u1 - u0) * sc;
     lam[2] = (double)(u2 - u1) * sc;
     lam[3] = (double)(2097152u - u2) * sc;
+}
+
+void or_sample_lambda(uint64_t seed, uint32_t q, uint32_t m, uint32_t s, double lam[4]) {
+    or_sample_lambda_keyed(seed, 0, q, m, s, lam);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -431,17 +446,10 @@ static void cut_geometry(const double X[4][3], const double p[3], double d2, con
         g->subdet[s] = fabs(det3_bary(g->sub[s][0], g->sub[s][1], g->sub[s][2], g->sub[s][3]));
 }
 
-/* lambda in U_I (closed).  The plane value c . lambda is evaluated with
- * lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3 substituted:
- * c_0 + sum_{l=1..3} lambda_l (c_l - c_0), as an FMA chain over l = 1, 2, 3. */
-static int in_UI(const cutgeom *g, const double lam[4]) {
-    if (g->n_planes == 0) return 0;
-    for (int i = 0; i < g->n_planes; ++i) {
-        const double *c = g->plane[i];
-        double h = fma(lam[3], c[3] - c[0], fma(lam[2], c[2] - c[0], fma(lam[1], c[1] - c[0], c[0])));
-        if (!(h >= 0.0)) return 0;
-    }
-    return 1;
+/* Value of the plane functional c at lambda: c . lambda summed in vertex order,
+ * ((c_0 lambda_0 + c_1 lambda_1) + c_2 lambda_2) + c_3 lambda_3.              */
+static double plane_value(const double c[4], const double lam[4]) {
+    return ((c[0] * lam[0] + c[1] * lam[1]) + c[2] * lam[2]) + c[3] * lam[3];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -464,8 +472,17 @@ typedef struct {
     int N;
     int caps; /* 1: the fullcaps Monte Carlo term is part of the pair */
     int cap_sampling; /* 1: for n_in >= 1 the caps are sampled on E - U_I (cap_region) */
+    int keying;       /* 0: samples per (point, element) pair, 1: per element (or_sample_lambda_keyed) */
     uint64_t seed;
     uint32_t q, m;
+    /* near-tie report (optional, may be NULL): samples whose decision lies
+     * within the rounding band of the sample test, and the sum of their weights */
+    int64_t *ties;
+    double *tie_w;
+    /* per-sample record for tests (optional, may be NULL, indexed by s):
+     * |y - p|^2, accepted, near tie */
+    double *rec_rr;
+    int8_t *rec_acc, *rec_tie;
 } pairctx;
 
 typedef void (*node_fn)(void *user, const double lam[4], double w, int is_mc);
@@ -560,11 +577,6 @@ static int cap_region(const pairctx *c, capregion *r) {
 }
 
 
-/* a . b as the FMA chain fma(a_z, b_z, fma(a_y, b_y, a_x b_x)) */
-static double dotf(const double a[3], const double b[3]) {
-    return fma(a[2], b[2], fma(a[1], b[1], a[0] * b[0]));
-}
-
 static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
     if (c->cls == OR_OUT) return;
     if (c->cls == OR_IN) {
@@ -587,57 +599,82 @@ static void visit_nodes(const pairctx *c, node_fn fn, void *user) {
             fn(user, lam, w, 0);
         }
     }
-    /* Sample test.  With lambda_0 = 1 - lambda_1 - lambda_2 - lambda_3 the sample
-     * point relative to p is y - p = e_0 + sum_{l=1..3} lambda_l F_l, e_0 = X_0 - p,
-     * F_l = (X_l - p) - (X_0 - p); |y - p|^2 is evaluated as its quadratic form in
-     * lambda_1..3 (coefficients below), the U_I planes as FMA chains over l.   */
     if (!c->caps) return;
     /* Sampling region: the whole E (samples in U_I rejected), or, with cap
      * sampling on and n_in >= 1, E - U_I itself (cap_region), no U_I test.
      * Sub-tet j of n takes the samples s with floor(j N / n) <= s <
      * floor((j + 1) N / n), N_j of them (N >= 3), each of weight |T_j| / N_j;
      * a sample's coordinates mu in T_j give its barycentrics in E as
-     * lambda = sum_r mu_r row(T_j, r).                                        */
+     * lambda = sum_r mu_r row(T_j, r).
+     *
+     * Sample test (the fullcap (E - U_I) n B_delta(p), Sec. 4.2.2), in the plain
+     * form: y - p = ((mu_0 e_0 + mu_1 e_1) + mu_2 e_2) + mu_3 e_3 per
+     * coordinate, e_l = (vertex l of the sampled tet) - p; accepted iff
+     * (y - p).(y - p) < delta^2 and lambda is not in U_I.
+     *
+     * Near ties.  A sample whose decision another correct evaluation order of
+     * the same test could reverse is reported (ties, tie_w): the ball test when
+     * |(y - p).(y - p) - delta^2| <= 2^-40 E2, E2 = max_l |e_l|^2, and the U_I
+     * test when some plane value h_i has |h_i| <= 2^-40 sum_l |c_il| while the
+     * other planes hold within their bands and the ball test does not reject
+     * beyond its band.  2^-40 is 8192 units of the last place: above the
+     * rounding error of any evaluation of these few-term sums (a few dozen
+     * roundings of terms no larger than E2, or sum |c|).                    */
     capregion R;
     const int region = c->cap_sampling && cap_region(c, &R);
     const int nb = region ? R.n : 1;
+    const double band = 0x1p-40;
+    double tau_p[2] = {0.0, 0.0};
+    for (int i = 0; i < g->n_planes; ++i)
+        tau_p[i] = band * (((fabs(g->plane[i][0]) + fabs(g->plane[i][1])) + fabs(g->plane[i][2])) +
+                           fabs(g->plane[i][3]));
     for (int j = 0; j < nb; ++j) {
         double e[4][3];
         for (int l = 0; l < 4; ++l)
             for (int i = 0; i < 3; ++i) e[l][i] = region ? R.e[j][l][i] : c->X[l][i] - c->p[i];
-        double f[4][3];
-        for (int l = 1; l < 4; ++l)
-            for (int i = 0; i < 3; ++i) f[l][i] = e[l][i] - e[0][i];
-        /* |y - p|^2 = |e_0 + sum_l mu_l F_l|^2 written out as the quadratic form
-         * q0 + sum_l mu_l (qb_l + qa_ll mu_l + sum_{j>l} qa_lj mu_j) with
-         * q0 = e_0.e_0, qb_l = 2 e_0.F_l, qa_ll = F_l.F_l, qa_lj = 2 F_l.F_j
-         * (dot products as FMA chains over x, y, z), evaluated as three inner FMA
-         * chains and one outer one */
-        double q0 = dotf(e[0], e[0]);
-        double qb[4], qa[4][4];
-        for (int l = 1; l < 4; ++l) {
-            qb[l] = 2.0 * dotf(e[0], f[l]);
-            for (int i = l; i < 4; ++i) qa[l][i] = (i == l ? 1.0 : 2.0) * dotf(f[l], f[i]);
+        double E2 = 0.0;
+        for (int l = 0; l < 4; ++l) {
+            const double r = dot3(e[l], e[l]);
+            if (r > E2) E2 = r;
         }
+        const double tau_b = band * E2;
         const int s0 = (int)(((int64_t)j * c->N) / nb), s1 = (int)(((int64_t)(j + 1) * c->N) / nb);
         const double wmc = (region ? R.vol[j] : c->vol) / (double)(s1 - s0);
         for (int s = s0; s < s1; ++s) {
             double mu[4];
-            or_sample_lambda(c->seed, c->q, c->m, (uint32_t)s, mu);
-            double t1 = fma(qa[1][3], mu[3], fma(qa[1][2], mu[2], fma(qa[1][1], mu[1], qb[1])));
-            double t2 = fma(qa[2][3], mu[3], fma(qa[2][2], mu[2], qb[2]));
-            double t3 = fma(qa[3][3], mu[3], qb[3]);
-            double rr = fma(mu[3], t3, fma(mu[2], t2, fma(mu[1], t1, q0)));
-            if (!(rr < c->d2)) continue;
+            or_sample_lambda_keyed(c->seed, c->keying, c->q, c->m, (uint32_t)s, mu);
+            double d[3];
+            for (int i = 0; i < 3; ++i) d[i] = ((mu[0] * e[0][i] + mu[1] * e[1][i]) + mu[2] * e[2][i]) + mu[3] * e[3][i];
+            const double rr = dot3(d, d);
+            int acc = rr < c->d2;
+            int tie = fabs(rr - c->d2) <= tau_b;
+            double lam[4];
             if (region) {
-                double lam[4];
                 for (int v = 0; v < 4; ++v)
                     lam[v] = ((mu[0] * R.row[j][0][v] + mu[1] * R.row[j][1][v]) + mu[2] * R.row[j][2][v]) +
                              mu[3] * R.row[j][3][v];
-                fn(user, lam, wmc, 1);
-            } else if (!in_UI(g, mu)) {
-                fn(user, mu, wmc, 1);
+            } else {
+                for (int v = 0; v < 4; ++v) lam[v] = mu[v];
+                if (g->n_planes > 0) {
+                    int inU = 1, near = 0, hold = 1;
+                    for (int i = 0; i < g->n_planes; ++i) {
+                        const double h = plane_value(g->plane[i], mu);
+                        if (!(h >= 0.0)) inU = 0;
+                        if (fabs(h) <= tau_p[i]) near = 1;
+                        if (h < -tau_p[i]) hold = 0;
+                    }
+                    if (inU) acc = 0;
+                    if (near && hold && rr < c->d2 + tau_b) tie = 1;
+                }
             }
+            if (c->rec_rr) c->rec_rr[s] = rr;
+            if (c->rec_acc) c->rec_acc[s] = (int8_t)acc;
+            if (c->rec_tie) c->rec_tie[s] = (int8_t)tie;
+            if (tie) {
+                if (c->ties) *c->ties += 1;
+                if (c->tie_w) *c->tie_w += wmc;
+            }
+            if (acc) fn(user, lam, wmc, 1);
         }
     }
 }
@@ -679,7 +716,8 @@ static void mom_node(void *user, const double lam[4], double w, int is_mc) {
 }
 
 static void pair_setup(pairctx *c, const double X[4][3], const double p[3], double delta, int N,
-                       uint64_t seed, uint32_t q, uint32_t m, int strategy, int cap_sampling) {
+                       uint64_t seed, uint32_t q, uint32_t m, int strategy, int cap_sampling, int keying) {
+    memset(c, 0, sizeof *c);
     c->X = X;
     for (int i = 0; i < 3; ++i) c->p[i] = p[i];
     c->d2 = delta * delta;
@@ -691,6 +729,7 @@ static void pair_setup(pairctx *c, const double X[4][3], const double p[3], doub
     c->cls = strategy_class(classify(X, p, c->d2, c->r2), X, p, c->d2, strategy);
     c->caps = strategy == OR_FULLCAPS;
     c->cap_sampling = cap_sampling;
+    c->keying = keying;
     if (c->cls >= OR_CUT0) cut_geometry(X, p, c->d2, c->r2, &c->g);
 }
 
@@ -736,27 +775,69 @@ void or_classify_point(const double *coords, const int32_t *tets, int64_t n_tets
     }
 }
 
-/* moments of pair (outer point q = 4 n + k, inner tet m); returns the class */
-int or_pair_moments(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m,
-                    double delta, int N, uint64_t seed, int strategy, int cap_sampling, double S[15]) {
+/* moments of pair (outer point q = 4 n + k, inner tet m) with sample keying
+ * `keying`; returns the class.  ties (may be NULL) gets the number of its
+ * Monte Carlo samples whose decision lies within the rounding band.        */
+int or_pair_moments_keyed(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m,
+                          double delta, int N, uint64_t seed, int strategy, int cap_sampling, int keying,
+                          double S[15], int32_t *ties) {
     double Xn[4][3], Xm[4][3], p[3];
     rule_init();
     load_tet(coords, tets, n, Xn);
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m, strategy, cap_sampling);
+    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m, strategy, cap_sampling, keying);
+    int64_t nt = 0;
+    c.ties = &nt;
     for (int i = 0; i < 15; ++i) S[i] = 0.0;
     if (c.cls != OR_OUT) pair_moments(&c, S);
+    if (ties) *ties = (int32_t)nt;
     return c.cls;
 }
 
-/* all pairs of one outer point against every tet: class + moments */
+int or_pair_moments(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m,
+                    double delta, int N, uint64_t seed, int strategy, int cap_sampling, double S[15]) {
+    return or_pair_moments_keyed(coords, tets, n, k, m, delta, N, seed, strategy, cap_sampling, 0, S, NULL);
+}
+
+/* all pairs of one outer point against every tet: class + moments (+ near-tie
+ * counts per tet when ties is not NULL) */
+void or_point_moments_keyed(const double *coords, const int32_t *tets, int64_t n_tets, int64_t n, int k,
+                            double delta, int N, uint64_t seed, int strategy, int cap_sampling, int keying,
+                            int8_t *cls, double *S /*[n_tets][15]*/, int32_t *ties /*[n_tets]*/) {
+    for (int64_t m = 0; m < n_tets; ++m)
+        cls[m] = (int8_t)or_pair_moments_keyed(coords, tets, n, k, m, delta, N, seed, strategy, cap_sampling,
+                                               keying, S + 15 * m, ties ? ties + m : NULL);
+}
+
 void or_point_moments(const double *coords, const int32_t *tets, int64_t n_tets, int64_t n, int k,
                       double delta, int N, uint64_t seed, int strategy, int cap_sampling, int8_t *cls,
                       double *S /*[n_tets][15]*/) {
-    for (int64_t m = 0; m < n_tets; ++m)
-        cls[m] = (int8_t)or_pair_moments(coords, tets, n, k, m, delta, N, seed, strategy, cap_sampling, S + 15 * m);
+    or_point_moments_keyed(coords, tets, n_tets, n, k, delta, N, seed, strategy, cap_sampling, 0, cls, S, NULL);
+}
+
+/* Monte Carlo samples of one pair, for tests: per sample s, |y - p|^2 as the
+ * sample test evaluates it, whether it was accepted, and whether it is a near
+ * tie.  Returns the class (samples are recorded for CUT pairs under fullcaps
+ * only; other entries are left untouched).                                  */
+int or_pair_samples(const double *coords, const int32_t *tets, int64_t n, int k, int64_t m, double delta,
+                    int N, uint64_t seed, int cap_sampling, int keying, double *rr, int8_t *acc, int8_t *tie) {
+    double Xn[4][3], Xm[4][3], p[3];
+    rule_init();
+    load_tet(coords, tets, n, Xn);
+    outer_point(Xn, k, p);
+    load_tet(coords, tets, m, Xm);
+    pairctx c;
+    pair_setup(&c, Xm, p, delta, N, seed, (uint32_t)(4 * n + k), (uint32_t)m, OR_FULLCAPS, cap_sampling, keying);
+    c.rec_rr = rr;
+    c.rec_acc = acc;
+    c.rec_tie = tie;
+    if (c.cls >= OR_CUT0) {
+        double S[15];
+        pair_moments(&c, S);
+    }
+    return c.cls;
 }
 
 /* cut geometry of a pair, for geometric pins: returns n_in (or -1 if not CUT) */
@@ -769,7 +850,7 @@ int or_pair_geometry(const double *coords, const int32_t *tets, int64_t n, int k
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, 1, 0, 0, 0, OR_FULLCAPS, 0);
+    pair_setup(&c, Xm, p, delta, 1, 0, 0, 0, OR_FULLCAPS, 0, 0);
     if (c.cls < OR_CUT0) return -1;
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) t_out[4 * a + b] = c.g.t[a][b];
@@ -796,7 +877,7 @@ int or_cap_region(const double *coords, const int32_t *tets, int64_t n, int k, i
     outer_point(Xn, k, p);
     load_tet(coords, tets, m, Xm);
     pairctx c;
-    pair_setup(&c, Xm, p, delta, 3, 0, 0, 0, OR_FULLCAPS, 1);
+    pair_setup(&c, Xm, p, delta, 3, 0, 0, 0, OR_FULLCAPS, 1, 0);
     if (c.cls < OR_CUT0) return -1;
     capregion R;
     if (!cap_region(&c, &R)) return 0;
@@ -827,6 +908,7 @@ typedef struct {
     int32_t g_degree;          /* per-axis degree of g_coef */
     const double *g_coef;      /* optional: g as a tensor polynomial -> the right-hand side of
                                   eq. F1.5 with g itself inside the inner integrals of eq. Fh */
+    int32_t keying;            /* 0: Monte Carlo samples per (point, element) pair, 1: per element */
 } or_problem;
 
 typedef struct {
@@ -840,6 +922,15 @@ typedef struct {
     double *rhs;
     int32_t *free_to_vertex;
     int64_t pair_counts[5]; /* IN, CUT0, CUT1, CUT2, CUT3 */
+    /* Near ties of the Monte Carlo sample test (see visit_nodes): their
+     * number, and per free row the most any matrix entry of the row
+     * (tie_allow) or the right-hand side entry (tie_allow_rhs) can move if
+     * another evaluation order decides every near tie the other way: a sample
+     * of weight w changes K_uv of its pair by at most f_m |psi| w_k w, since
+     * |a_u a_v| <= 1.                                                       */
+    int64_t near_ties;
+    double *tie_allow;
+    double *tie_allow_rhs;
 } or_system;
 
 typedef struct {
@@ -960,6 +1051,7 @@ static int validate(const or_problem *P) {
     if (P->strategy < OR_FULLCAPS || P->strategy > OR_BARYCENTER) return 1;
     if (P->cap_sampling != 0 && P->cap_sampling != 1) return 1;
     if (P->cap_sampling == 1 && P->mc_samples < 3) return 1;
+    if (P->keying != 0 && P->keying != 1) return 1;
     if (P->g_coef && (P->g_degree < 0 || P->g_degree > 4 || P->cap_sampling != 0)) return 1;
     if (P->n_tets > 0 && (!P->coords || !P->tets || !P->vertex_free)) return 1;
     for (int64_t i = 0; i < 4 * P->n_tets; ++i)
@@ -972,6 +1064,7 @@ void or_system_free(or_system *S) {
     free(S->ff_row_ptr); free(S->ff_col); free(S->ff_val);
     free(S->fc_row_ptr); free(S->fc_col); free(S->fc_val);
     free(S->rhs); free(S->free_to_vertex);
+    free(S->tie_allow); free(S->tie_allow_rhs);
     memset(S, 0, sizeof *S);
 }
 
@@ -1004,10 +1097,12 @@ int or_assemble(const or_problem *P, or_system *S) {
     S->n_free = nf;
     S->rhs = (double *)calloc((size_t)(nf > 0 ? nf : 1), sizeof(double));
     S->free_to_vertex = (int32_t *)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(int32_t));
+    S->tie_allow = (double *)calloc((size_t)(nf > 0 ? nf : 1), sizeof(double));
+    S->tie_allow_rhs = (double *)calloc((size_t)(nf > 0 ? nf : 1), sizeof(double));
     tuples T = {0};
     T.cap = 1 << 22;
     T.a = (tuple_t *)malloc((size_t)T.cap * sizeof(tuple_t));
-    if (!S->rhs || !S->free_to_vertex || !T.a) { free(T.a); free(region); free(free_id); or_system_free(S); return 3; }
+    if (!S->rhs || !S->free_to_vertex || !S->tie_allow || !S->tie_allow_rhs || !T.a) { free(T.a); free(region); free(free_id); or_system_free(S); return 3; }
     for (int64_t v = 0; v < V; ++v)
         if (free_id[v] >= 0) S->free_to_vertex[free_id[v]] = (int32_t)v;
 
@@ -1032,6 +1127,7 @@ int or_assemble(const or_problem *P, or_system *S) {
                 double Xm[4][3];
                 load_tet(P->coords, P->tets, m, Xm);
                 pairctx c;
+                memset(&c, 0, sizeof c);
                 c.X = Xm;
                 for (int i = 0; i < 3; ++i) c.p[i] = p[i];
                 c.d2 = d2;
@@ -1041,6 +1137,7 @@ int or_assemble(const or_problem *P, or_system *S) {
                 c.N = P->mc_samples;
                 c.caps = P->strategy == OR_FULLCAPS;
                 c.cap_sampling = P->cap_sampling;
+                c.keying = P->keying;
                 c.seed = P->seed;
                 c.q = (uint32_t)(4 * n + k);
                 c.m = (uint32_t)m;
@@ -1066,13 +1163,34 @@ int or_assemble(const or_problem *P, or_system *S) {
                     }
                     M.jm[found] = j;
                 }
+                int64_t nties = 0;
+                double tie_w = 0.0;
+                c.ties = &nties;
+                c.tie_w = &tie_w;
                 visit_nodes(&c, local_node, &M);
+                c.ties = NULL;
+                c.tie_w = NULL;
                 /* Tuples (i, j, a w) with psi and the kernel factor of the
                  * inner element: 1 on T_Omega (the W term), 2 on T_Omega_I
                  * (the N term together with the Omega_I coupling moved to the
                  * right-hand side through the nodal constraint values).     */
                 double fm = region[m] ? 1.0 : 2.0;
                 double scale = (P->psi * fm) * wk;
+                if (nties > 0) {
+                    /* rows of the pair's free vertices; the right-hand side moves
+                     * through A_fc g over the pair's constrained vertices */
+                    double gsum = 0.0;
+                    for (int v = 0; v < M.nu; ++v)
+                        if (free_id[M.U[v]] < 0 && P->g_nodal) gsum += fabs(P->g_nodal[M.U[v]]);
+                    const double da = fabs(scale) * tie_w;
+                    for (int u = 0; u < M.nu; ++u) {
+                        int32_t fu = free_id[M.U[u]];
+                        if (fu < 0) continue;
+                        S->tie_allow[fu] += da;
+                        S->tie_allow_rhs[fu] += da * gsum;
+                    }
+                    S->near_ties += nties;
+                }
                 if (P->g_coef) {
                     /* eq. F1.5 with F_h of eq. Fh, term by term:
                      * T_Omega inner element: - A_h(phi_j, phi_i) g_j for the

@@ -83,15 +83,8 @@ def test_large_full_properties_and_sampled_points(dev, orc, large):
     for n in rng.choice(outer, size=2, replace=False):
         rec = plan.debug_pairs(4 * int(n), 4 * int(n) + 4)
         for k in range(4):
-            cls, S = orc.point_moments(m.coords, m.tets, int(n), k, pb.delta, pb.mc_samples, pb.seed)
-            sel = rec["q"] == 4 * n + k
-            mm = rec["m"][sel]
-            order = np.argsort(mm)
-            mm = mm[order]
-            assert np.array_equal(mm, np.nonzero(cls)[0])
-            assert np.array_equal(rec["cls"][sel][order], cls[mm])
-            sc = np.maximum(np.abs(S[mm]).max(axis=1, keepdims=True), 1e-300)
-            assert np.max(np.abs(rec["S"][sel][order] - S[mm]) / sc) <= FP32_TOL
+            err, t = H.point_pairs_vs_oracle(orc, m, rec, n, k, pb.delta, pb.mc_samples, pb.seed)
+            assert err <= FP32_TOL, (n, k, err)
     plan.destroy()
 
 

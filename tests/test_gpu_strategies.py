@@ -120,17 +120,12 @@ def test_region_cap_sampling_pair_moments(dev, orc):
     for n in outer[[0, len(outer) // 2]]:
         rec = plan.debug_pairs(4 * int(n), 4 * int(n) + 4)
         for k in range(4):
-            cls, S = orc.point_moments(pb.mesh.coords, pb.mesh.tets, int(n), k, pb.delta, pb.mc_samples, pb.seed,
-                                       cap_sampling="outside_ui")
-            sel = rec["q"] == 4 * n + k
-            mm = rec["m"][sel]
-            order = np.argsort(mm)
-            mm = mm[order]
-            assert np.array_equal(mm, np.nonzero(cls)[0])
-            sc = np.maximum(np.abs(S[mm]).max(axis=1, keepdims=True), 1e-300)
-            assert np.max(np.abs(rec["S"][sel][order] - S[mm]) / sc) <= 1e-12
+            err, t = H.point_pairs_vs_oracle(orc, pb.mesh, rec, n, k, pb.delta, pb.mc_samples, pb.seed,
+                                             cap_sampling="outside_ui")
+            assert err <= 1e-12, (n, k, err)
+            cls = rec["cls"][rec["q"] == 4 * n + k]
             for c in (3, 4, 5):
-                seen[c] += int((cls[mm] == c).sum())
+                seen[c] += int((cls == c).sum())
     assert min(seen.values()) > 0, seen
     plan.destroy()
 

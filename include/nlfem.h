@@ -180,12 +180,27 @@ nlfem_status nlfem_assemble_exact_g(nlfem_plan *plan, const double *f_qp, const 
                                     int64_t *fc_row_ptr, int32_t *fc_col, double *fc_val, double *rhs,
                                     int32_t *free_to_vertex);
 
-/* Unpreconditioned FP64 conjugate gradients on a CSR matrix (DEVICE arrays),
- * x holds x0 on entry and the solution on exit.  Stops when
- * ||r||_2 <= rtol ||b||_2 or after max_iter iterations (host scalars out).  */
+/* Unpreconditioned FP64 conjugate gradients on a CSR matrix (DEVICE arrays):
+ * the solve of the free-node system that ends the main assembly algorithm
+ * (Sec. 4.3).  x holds x0 on entry and the solution on exit.  Stops when
+ * ||r||_2 <= rtol ||b||_2 or after max_iter iterations (host scalars out:
+ * *iters = iterations done, *rel_residual = ||r||_2 / ||b||_2 of the last
+ * recursively updated residual).  The step lengths, norms and the stopping
+ * decision stay on the device; the host polls them every 8 iterations and
+ * the iteration count is exact.  b = 0 gives x = 0.  Returns
+ * NLFEM_E_NOT_CONVERGED (x and the residual still written) at the cap, and
+ * also on a breakdown, p.Ap <= 0 or a non-finite value (the matrix is not
+ * symmetric positive definite); the message says which.  Work vectors (3 n
+ * doubles) are allocated from the context.                                   */
 nlfem_status nlfem_cg(nlfem_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
                       const double *val, const double *b, double *x, double rtol, int32_t max_iter,
                       int32_t *iters, double *rel_residual);
+
+/* nlfem_cg on the plan's own A_ff pattern (row pointers and columns as
+ * nlfem_assemble writes them, n = n_free) with the caller's DEVICE values
+ * ff_val [nnz_ff], right-hand side rhs [n_free] and x [n_free].              */
+nlfem_status nlfem_plan_cg(nlfem_plan *plan, const double *ff_val, const double *rhs, double *x, double rtol,
+                           int32_t max_iter, int32_t *iters, double *rel_residual);
 
 nlfem_status nlfem_plan_destroy(nlfem_plan *plan);
 

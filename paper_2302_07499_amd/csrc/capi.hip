@@ -661,6 +661,52 @@ double time_integrate(nlfem_batch* b, const nlfem_batch::Group& g, int block, in
 
 }  // namespace
 
+namespace {
+
+// CG on the device (k_cg.hip) with a host poll every kCgPoll iterations: the
+// iterations after the stop are no-ops on the device, so *iters is exact.
+constexpr int kCgPoll = 8;
+
+nlfem_status cg_solve(nlfem_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                      const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters, double* rel_res,
+                      double* work) {
+    hipStream_t s = c->stream;
+    const CgState* st = cg_state(work, n);
+    CgState h;
+    auto poll = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(c->pinned, st, kCgPollBytes, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        std::memcpy(&h, c->pinned, kCgPollBytes);
+        return e;
+    };
+    HIPCHK(cg_enqueue_start(n, row_ptr, col, val, b, x, rtol, max_iter, work, s));
+    HIPCHK(poll());
+    int queued = 0;
+    while (h.done == 0 && queued < max_iter) {
+        const int cnt = std::min(kCgPoll, max_iter - queued);
+        HIPCHK(cg_enqueue_iterations(n, row_ptr, col, val, x, queued, cnt, work, s));
+        queued += cnt;
+        HIPCHK(poll());
+    }
+    if (h.done == 4) {  // b = 0: the solution is 0
+        HIPCHK(cg_enqueue_zero(n, x, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *iters = 0;
+        *rel_res = 0.0;
+        return NLFEM_OK;
+    }
+    *iters = h.iter;
+    *rel_res = std::sqrt(h.res2) / h.bnorm;
+    if (h.done == 2)
+        return fail(c, NLFEM_E_NOT_CONVERGED,
+                    "CG breakdown after " + std::to_string(h.iter) + " iterations: p.Ap <= 0 or a non-finite value "
+                    "(the matrix is not symmetric positive definite)");
+    if (h.done != 1) return fail(c, NLFEM_E_NOT_CONVERGED, "CG did not converge");
+    return NLFEM_OK;
+}
+
+}  // namespace
+
 // ============================================================================
 extern "C" {
 
@@ -1215,45 +1261,14 @@ nlfem_status nlfem_cg(nlfem_ctx* c, int64_t n, const int64_t* row_ptr, const int
     *rel_res = 0.0;
     if (n == 0) return NLFEM_OK;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
-    hipStream_t s = c->stream;
-    TMP(t_v, (size_t)3 * n * 8 + 4096 + 8 * 8);
-    double* r = t_v.as<double>();
-    double* p = r + n;
-    double* Ap = p + n;
-    double* partial = Ap + n;       // 512 doubles
-    double* sc = partial + 512;     // sc[0] rr, sc[1] pAp, sc[2] rr_new, sc[3] bb
-    HIPCHK(launch_spmv(n, row_ptr, col, val, x, Ap, s));
-    HIPCHK(launch_cg_init(n, b, Ap, x, r, p, s));
-    HIPCHK(launch_dot(n, r, r, partial, sc + 0, s));
-    HIPCHK(launch_dot(n, b, b, partial, sc + 3, s));
-    double h[4];
-    HIPCHK(hipMemcpyAsync(h, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double bn = std::sqrt(h[3]);
-    if (bn == 0.0) {
-        HIPCHK(launch_fill_zero_f64(x, n, s));
-        HIPCHK(hipStreamSynchronize(s));
-        return NLFEM_OK;
-    }
-    double rr = h[0];
-    bool conv = std::sqrt(rr) <= rtol * bn;
-    int it = 0;
-    while (!conv && it < max_iter) {
-        HIPCHK(launch_spmv(n, row_ptr, col, val, p, Ap, s));
-        HIPCHK(launch_dot(n, p, Ap, partial, sc + 1, s));
-        HIPCHK(launch_cg_xr(n, sc, x, r, p, Ap, s));
-        HIPCHK(launch_dot(n, r, r, partial, sc + 2, s));
-        HIPCHK(hipMemcpyAsync(c->pinned, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(launch_cg_p(n, sc, r, p, s));
-        HIPCHK(hipStreamSynchronize(s));
-        rr = c->pinned[0];
-        ++it;
-        conv = std::sqrt(rr) <= rtol * bn;
-    }
-    *iters = it;
-    *rel_res = std::sqrt(rr) / bn;
-    if (!conv) return fail(c, NLFEM_E_NOT_CONVERGED, "CG did not converge");
-    return NLFEM_OK;
+    TMP(t_v, cg_work_doubles(n) * sizeof(double));
+    return cg_solve(c, n, row_ptr, col, val, b, x, rtol, max_iter, iters, rel_res, t_v.as<double>());
+}
+
+nlfem_status nlfem_plan_cg(nlfem_plan* pl, const double* ff_val, const double* rhs, double* x, double rtol,
+                           int32_t max_iter, int32_t* iters, double* rel_res) {
+    if (!pl) return NLFEM_E_INVALID_ARG;
+    return nlfem_cg(pl->ctx, pl->n_free, pl->ff_row_ptr, pl->ff_col, ff_val, rhs, x, rtol, max_iter, iters, rel_res);
 }
 
 }  // extern "C"

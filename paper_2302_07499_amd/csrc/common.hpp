@@ -196,17 +196,25 @@ size_t row_assemble_static_lds();
 hipError_t launch_row_assemble(const RowPlan& rp, const RowNumeric& nm, int64_t n_rows, hipStream_t s);
 
 // CG (k_cg.hip)
+// Device-side state of one CG solve.  The first 32 bytes are what the host
+// polls.
+struct CgState {
+    int iter, done, max_iter, pad;  // done: 0 running, 1 converged, 2 breakdown, 3 cap, 4 b = 0
+    double res2, bnorm;             // latest ||r||^2, ||b||
+    double rr[2];                   // ||r_i||^2 at iteration parity i & 1
+    double pAp, bb, thr;
+};
+constexpr size_t kCgPollBytes = 32;
+size_t cg_work_doubles(int64_t n);  // r, p, Ap, dot partials, state
 hipError_t launch_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* x,
                        double* y, hipStream_t s);
-hipError_t launch_dot(int64_t n, const double* a, const double* b, double* partial, double* out,
-                      hipStream_t s);
-hipError_t launch_cg_init(int64_t n, const double* b, const double* Ax, double* x, double* r, double* p,
-                          hipStream_t s);
-// x += alpha p; r -= alpha Ap with alpha = sc[0] / sc[1]
-hipError_t launch_cg_xr(int64_t n, const double* sc, double* x, double* r, const double* p, const double* Ap,
-                        hipStream_t s);
-// p = r + beta p with beta = sc[2] / sc[0]; then sc[0] = sc[2]
-hipError_t launch_cg_p(int64_t n, double* sc, const double* r, double* p, hipStream_t s);
-hipError_t launch_copy_scalar(const double* src, double* dst, hipStream_t s);
+// r = b - A x, p = r, ||r||^2, ||b||^2, threshold and the initial decision
+hipError_t cg_enqueue_start(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* b,
+                            double* x, double rtol, int max_iter, double* work, hipStream_t s);
+// iterations it0 .. it0 + count - 1 (no-ops once the state says stop)
+hipError_t cg_enqueue_iterations(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, double* x,
+                                 int it0, int count, double* work, hipStream_t s);
+hipError_t cg_enqueue_zero(int64_t n, double* x, hipStream_t s);
+const CgState* cg_state(const double* work, int64_t n);  // device address of the state in work
 
 }  // namespace nlfem

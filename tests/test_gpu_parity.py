@@ -109,6 +109,47 @@ def test_plain_cg_matches_oracle(plain, orc):
     assert np.max(np.abs(xg - xo)) <= 1e-9 * np.max(np.abs(xo))
 
 
+def test_plain_cg_device_poll_and_plan_form(dev, plain):
+    """The device-side stopping decision gives the same iterations and the
+    same bits through the raw-CSR and the plan entry points; a capped solve
+    reports its exact iteration count."""
+    import paper_2302_07499_amd as P
+    pb, plan, s, g, o = plain
+    x, it, rr, ok = plan.solve(s, rtol=1e-10)
+    t = dev.torch
+    x2 = t.zeros(s.n_free, dtype=t.float64, device=dev.dev)
+    it2, rr2, ok2 = P.nlfem_plan_cg(plan.handle, s.n_free, s.ff_val, s.rhs, x2, rtol=1e-10, ctx=dev.ctx)
+    assert ok and ok2 and it2 == it and rr2 == rr
+    assert t.equal(x, x2)
+    for cap in (1, 3, it - 1):
+        x3 = t.zeros(s.n_free, dtype=t.float64, device=dev.dev)
+        it3, rr3, ok3 = P.nlfem_cg(dev.ctx, s.n_free, s.ff_row_ptr, s.ff_col, s.ff_val, s.rhs, x3, 1e-10, cap)
+        assert not ok3 and it3 == cap and rr3 > 1e-10
+
+
+def test_cg_breakdown_on_indefinite_matrix(dev):
+    """An indefinite matrix makes p.Ap <= 0: the solve stops at once with
+    NLFEM_E_NOT_CONVERGED and a breakdown message instead of running to the cap."""
+    import paper_2302_07499_amd as P
+    t = dev.torch
+    n = 64
+    rp = t.arange(n + 1, dtype=t.int64, device=dev.dev)
+    ci = t.arange(n, dtype=t.int32, device=dev.dev)
+    va = t.ones(n, dtype=t.float64, device=dev.dev)
+    va[1::2] = -1.0
+    b = t.zeros(n, dtype=t.float64, device=dev.dev)
+    b[0], b[1] = 1.0, 1.0
+    x = t.zeros(n, dtype=t.float64, device=dev.dev)
+    it, rr, ok = P.nlfem_cg(dev.ctx, n, rp, ci, va, b, x, 1e-10, 1000)
+    assert not ok and it == 1
+    assert "breakdown" in P.last_error(dev.ctx)
+    # b = 0: x = 0 at once
+    x.fill_(5.0)
+    it, rr, ok = P.nlfem_cg(dev.ctx, n, rp, ci, t.ones(n, dtype=t.float64, device=dev.dev), t.zeros_like(b), x,
+                            1e-10, 10)
+    assert ok and it == 0 and float(x.abs().max()) == 0.0
+
+
 def test_plain_fp32_local(dev, plain):
     pb, plan, s, g, o = plain
     pb32 = mg.plain_problem()

@@ -196,6 +196,19 @@ nlfem_status nlfem_cg(nlfem_ctx *ctx, int64_t n, const int64_t *row_ptr, const i
                       const double *val, const double *b, double *x, double rtol, int32_t max_iter,
                       int32_t *iters, double *rel_residual);
 
+/* nlfem_cg for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, bitwise the same results, but its work vectors live in a
+ * static device array of the library (one per GPU, about 12.6 MB, held until
+ * the process ends) instead of context allocations; it calls no hipMalloc or
+ * hipFree.  n must be at most 524288 (2^19), else NLFEM_E_UNSUPPORTED.  All
+ * calls on one GPU share that array: calls that overlap on one GPU (from
+ * several threads or streams) race and must be serialised by the caller.
+ * Each call initialises the state it reads, so nothing carries over.         */
+nlfem_status nlfem_cg_noalloc(nlfem_ctx *ctx, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                              const double *val, const double *b, double *x, double rtol, int32_t max_iter,
+                              int32_t *iters, double *rel_residual);
+
 /* nlfem_cg on the plan's own A_ff pattern (row pointers and columns as
  * nlfem_assemble writes them, n = n_free) with the caller's DEVICE values
  * ff_val [nnz_ff], right-hand side rhs [n_free] and x [n_free].              */

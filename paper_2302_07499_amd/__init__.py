@@ -94,7 +94,7 @@ class nlfem_server_counters(C.Structure):
 
 EXPORTS = ["nlfem_create", "nlfem_destroy", "nlfem_last_error", "nlfem_memory_in_use", "nlfem_trim",
            "nlfem_rule_constants", "nlfem_plan_create", "nlfem_plan_info", "nlfem_assemble",
-           "nlfem_assemble_exact_g", "nlfem_cg", "nlfem_plan_cg",
+           "nlfem_assemble_exact_g", "nlfem_cg", "nlfem_plan_cg", "nlfem_cg_noalloc",
            "nlfem_plan_destroy", "nlfem_debug_pairs", "nlfem_plan_timings",
            "nlfem_batch_create", "nlfem_batch_info", "nlfem_batch_assemble", "nlfem_batch_system",
            "nlfem_batch_tuning", "nlfem_batch_set_launch", "nlfem_batch_destroy",
@@ -130,6 +130,7 @@ def load():
     L.nlfem_cg.argtypes = [P, i64, P, P, P, P, P, C.c_double, C.c_int32, C.POINTER(C.c_int32),
                            C.POINTER(C.c_double)]
     L.nlfem_plan_cg.argtypes = [P, P, P, P, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.nlfem_cg_noalloc.argtypes = L.nlfem_cg.argtypes
     L.nlfem_plan_destroy.argtypes = [P]
     L.nlfem_debug_pairs.argtypes = [P, i64, i64, P, i64, C.POINTER(i64)]
     L.nlfem_plan_timings.argtypes = [P, C.POINTER(C.c_double)]
@@ -260,6 +261,17 @@ def nlfem_cg(ctx, n, row_ptr, col, val, b, x, rtol=1e-10, max_iter=None):
     it, rr = C.c_int32(), C.c_double()
     st = load().nlfem_cg(ctx, n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(b), _ptr(x), rtol,
                          n if max_iter is None else max_iter, C.byref(it), C.byref(rr))
+    if st not in (NLFEM_OK, NLFEM_E_NOT_CONVERGED):
+        _check(st, ctx)
+    return it.value, rr.value, st == NLFEM_OK
+
+
+def nlfem_cg_noalloc(ctx, n, row_ptr, col, val, b, x, rtol=1e-10, max_iter=None):
+    """nlfem_cg with its work vectors in the library's static device scratch
+    (no device allocation; n <= its maximum, else NlfemError)."""
+    it, rr = C.c_int32(), C.c_double()
+    st = load().nlfem_cg_noalloc(ctx, n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(b), _ptr(x), rtol,
+                                 n if max_iter is None else max_iter, C.byref(it), C.byref(rr))
     if st not in (NLFEM_OK, NLFEM_E_NOT_CONVERGED):
         _check(st, ctx)
     return it.value, rr.value, st == NLFEM_OK

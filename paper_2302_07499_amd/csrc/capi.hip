@@ -725,6 +725,14 @@ nlfem_status nlfem_create(nlfem_ctx** out, int device, void* hip_stream, size_t 
     }
     if (device < 0 || device >= n) return NLFEM_E_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return NLFEM_E_DEVICE;
+    {
+        // the allocation-free CG's device scratch: its address on this device
+        void* scratch = nullptr;
+        if (cg_noalloc_setup(device, &scratch) != hipSuccess || !scratch) {
+            hipGetLastError();
+            return NLFEM_E_DEVICE;
+        }
+    }
     nlfem_ctx* c = new nlfem_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -1263,6 +1271,24 @@ nlfem_status nlfem_cg(nlfem_ctx* c, int64_t n, const int64_t* row_ptr, const int
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
     TMP(t_v, cg_work_doubles(n) * sizeof(double));
     return cg_solve(c, n, row_ptr, col, val, b, x, rtol, max_iter, iters, rel_res, t_v.as<double>());
+}
+
+nlfem_status nlfem_cg_noalloc(nlfem_ctx* c, int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
+                              const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters,
+                              double* rel_res) {
+    if (!c) return NLFEM_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!row_ptr || !col || !val || !b || !x)) || !iters || !rel_res)
+        return fail(c, NLFEM_E_INVALID_ARG, "bad CG argument");
+    if (n > kCgNoAllocMaxN)
+        return fail(c, NLFEM_E_UNSUPPORTED, "nlfem_cg_noalloc: n = " + std::to_string(n) + " exceeds its maximum " +
+                                                std::to_string(kCgNoAllocMaxN) + " (use nlfem_cg)");
+    *iters = 0;
+    *rel_res = 0.0;
+    if (n == 0) return NLFEM_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
+    double* work = (double*)cg_noalloc_scratch(c->device);
+    if (!work) return fail(c, NLFEM_E_DEVICE, "nlfem_cg_noalloc: device scratch not resolved for this device");
+    return cg_solve(c, n, row_ptr, col, val, b, x, rtol, max_iter, iters, rel_res, work);
 }
 
 nlfem_status nlfem_plan_cg(nlfem_plan* pl, const double* ff_val, const double* rhs, double* x, double rtol,

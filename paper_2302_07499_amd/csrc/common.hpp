@@ -205,6 +205,9 @@ struct CgState {
     double pAp, bb, thr;
 };
 constexpr size_t kCgPollBytes = 32;
+// largest n of the allocation-free CG (its static device scratch holds 3 n doubles)
+constexpr int64_t kCgNoAllocMaxN = (int64_t)1 << 19;
+constexpr int kMaxDevices = 64;
 size_t cg_work_doubles(int64_t n);  // r, p, Ap, dot partials, state
 hipError_t launch_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* x,
                        double* y, hipStream_t s);
@@ -216,5 +219,9 @@ hipError_t cg_enqueue_iterations(int64_t n, const int64_t* rp, const int32_t* ci
                                  int it0, int count, double* work, hipStream_t s);
 hipError_t cg_enqueue_zero(int64_t n, double* x, hipStream_t s);
 const CgState* cg_state(const double* work, int64_t n);  // device address of the state in work
+// the allocation-free CG's scratch on `device` (the current device): resolved
+// once per device with hipGetSymbolAddress
+hipError_t cg_noalloc_setup(int device, void** out);
+void* cg_noalloc_scratch(int device);  // nullptr before setup
 
 }  // namespace nlfem

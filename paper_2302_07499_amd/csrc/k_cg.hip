@@ -7,7 +7,10 @@
 // which keeps the iteration count exact however many iterations are queued.
 //
 // The work vectors come from the caller: a scratch block of cg_work_doubles(n)
-// doubles allocated by the library.
+// doubles, either allocated by the library (nlfem_cg) or the file-scope
+// device array below (nlfem_cg_noalloc, for callers that cannot allocate).
+#include <mutex>
+
 #include "common.hpp"
 
 namespace nlfem {
@@ -15,6 +18,12 @@ namespace nlfem {
 namespace {
 
 constexpr int DOT_BLOCKS = 512;
+
+// Device scratch of the allocation-free CG: r, p, Ap for up to kCgNoAllocMaxN
+// rows, the dot partials and the state.  One copy per GPU, held until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) static double scratch[3 * (size_t)kCgNoAllocMaxN + DOT_BLOCKS + 64];
 
 // done: 0 running, 1 converged, 2 breakdown (p.Ap <= 0 or a non-finite
 // value), 3 iteration cap reached, 4 zero right-hand side
@@ -145,9 +154,32 @@ inline unsigned update_blocks(int64_t n) {
     return (unsigned)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
 
 size_t cg_work_doubles(int64_t n) { return (size_t)3 * (size_t)n + DOT_BLOCKS + 64; }
+
+hipError_t cg_noalloc_setup(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+void* cg_noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 hipError_t launch_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, const double* x, double* y,
                        hipStream_t s) {

@@ -79,6 +79,19 @@ typedef enum {
                                      open); needs mc_samples >= 3 (else NLFEM_E_INVALID_ARG)      */
 } nlfem_cap_sampling;
 
+/* Which Philox counters key the fullcaps Monte Carlo samples (Sec. 4.2.2
+ * leaves the sampling method open).  Sample pair j = floor(s / 2) of the pair
+ * (outer point q = 4 n + k, element m) uses counter
+ *   NLFEM_KEY_PAIR:    (q, m, j, 0) -- N samples of its own for every pair;
+ *   NLFEM_KEY_ELEMENT: (m, j, 0, 1) -- N samples per element, the same points
+ *                      of E_m for every outer point, so one sample stream
+ *                      serves all outer points of an outer tet (correlated
+ *                      across points, unbiased for each).                     */
+typedef enum {
+    NLFEM_KEY_PAIR = 0,
+    NLFEM_KEY_ELEMENT = 1
+} nlfem_keying;
+
 /* Tetrahedral mesh of Omega u Omega_I (Sec. 3.1: coinciding triangulations of
  * Omega and Omega_I; P1 nodes on the boundary of Omega and in Omega_I carry the
  * volume constraint, Sec. 3.2).                                              */
@@ -93,7 +106,8 @@ typedef struct {
 } nlfem_mesh;
 
 /* Method parameters (Sec. 2.1 kernel gamma = psi * indicator of B_delta(x);
- * Sec. 4.2.2 fullcaps with N Monte Carlo samples per cut (point, element) pair). */
+ * Sec. 4.2.2 fullcaps with N Monte Carlo samples per cut (point, element) pair,
+ * or per cut element with element keying). */
 typedef struct {
     double delta;                /* horizon > 0                                                       */
     double psi;                  /* kernel constant; the operator is L u = 2 int_B (u(y)-u(x)) psi dy */
@@ -104,6 +118,7 @@ typedef struct {
                                     as an outer element (subset runs); NULL = all T_Omega tets        */
     int32_t strategy;            /* nlfem_strategy (0 = fullcaps)                                     */
     int32_t cap_sampling;        /* nlfem_cap_sampling (0 = whole element)                            */
+    int32_t keying;              /* nlfem_keying (0 = per pair); unknown values: NLFEM_E_INVALID_ARG  */
 } nlfem_params;
 
 /* ---- context ------------------------------------------------------------ */
@@ -252,7 +267,8 @@ nlfem_status nlfem_debug_pairs(nlfem_plan *plan, int64_t q_begin, int64_t q_end,
 typedef struct nlfem_batch nlfem_batch;
 
 /* meshes[n], params[n] (HOST arrays of structs; the mesh arrays they point to
- * follow mem_kind).  All params must use the same precision.                  */
+ * follow mem_kind).  All params must use the same precision, cap sampling and
+ * keying.                                                                     */
 nlfem_status nlfem_batch_create(nlfem_ctx *ctx, int32_t n, const nlfem_mesh *meshes,
                                 const nlfem_params *params, nlfem_batch **batch);
 nlfem_status nlfem_batch_info(const nlfem_batch *batch, int32_t i, int64_t *n_free, int64_t *nnz_ff,

@@ -31,6 +31,16 @@ NLFEM_MAX_MC_SAMPLES = 2047  # sample sums stay exact 32/64-bit integers
 STRATEGIES = {"fullcaps": 0, "nocaps": 1, "overlap": 2, "inside": 3, "barycenter": 4}
 # where the cap samples are drawn (nlfem_cap_sampling)
 CAP_SAMPLING = {"whole": 0, "outside_ui": 1}
+# Monte Carlo keying (nlfem_keying): samples per (point, element) pair or per element
+KEYING = {"pair": 0, "element": 1}
+
+
+def keying_id(kk):
+    if isinstance(kk, str):
+        if kk not in KEYING:
+            raise ValueError(f"unknown keying {kk!r}")
+        return KEYING[kk]
+    return int(kk)
 
 
 def cap_sampling_id(cs):
@@ -61,7 +71,7 @@ class nlfem_mesh(C.Structure):
 class nlfem_params(C.Structure):
     _fields_ = [("delta", C.c_double), ("psi", C.c_double), ("mc_samples", C.c_int32),
                 ("seed", C.c_uint64), ("precision", C.c_int32), ("outer_mask", C.c_void_p),
-                ("strategy", C.c_int32), ("cap_sampling", C.c_int32)]
+                ("strategy", C.c_int32), ("cap_sampling", C.c_int32), ("keying", C.c_int32)]
 
 
 class nlfem_pair_record(C.Structure):
@@ -368,13 +378,13 @@ class Device:
         return m, keep
 
     def plan(self, coords, tets, vertex_free, delta, psi, mc_samples, seed, precision="fp64", tet_region=None,
-             outer_mask=None, strategy="fullcaps", cap_sampling="whole"):
+             outer_mask=None, strategy="fullcaps", cap_sampling="whole", keying="pair"):
         m, keep = self.mesh(coords, tets, vertex_free, tet_region)
         om = None if outer_mask is None else self.to_dev(outer_mask, self.torch.uint8)
         prm = nlfem_params(float(delta), float(psi), int(mc_samples), int(seed),
                            NLFEM_FP32_LOCAL if precision == "fp32" else NLFEM_FP64,
                            None if om is None else om.data_ptr(), strategy_id(strategy),
-                           cap_sampling_id(cap_sampling))
+                           cap_sampling_id(cap_sampling), keying_id(keying))
         plan = nlfem_plan_create(self.ctx, m, prm)
         return Plan(self, plan)
 
@@ -383,7 +393,8 @@ class Device:
         return self.plan(mm.coords, mm.tets, pb.vertex_free, pb.delta, pb.psi, pb.mc_samples, pb.seed,
                          precision=pb.precision, outer_mask=outer_mask, tet_region=getattr(pb, "tet_region", None),
                          strategy=getattr(pb, "strategy", "fullcaps"),
-                         cap_sampling=getattr(pb, "cap_sampling", "whole"))
+                         cap_sampling=getattr(pb, "cap_sampling", "whole"),
+                         keying=getattr(pb, "keying", "pair"))
 
 
 class Plan:
@@ -467,7 +478,8 @@ class Batch:
                                      NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
                                      None if om is None else om.data_ptr(),
                                      strategy_id(getattr(pb, "strategy", "fullcaps")),
-                                     cap_sampling_id(getattr(pb, "cap_sampling", "whole")))
+                                     cap_sampling_id(getattr(pb, "cap_sampling", "whole")),
+                                     keying_id(getattr(pb, "keying", "pair")))
         h = C.c_void_p()
         _check(load().nlfem_batch_create(dev.ctx, self.n, meshes, params, C.byref(h)), dev.ctx)
         self.handle = h
@@ -564,7 +576,8 @@ class Server:
         prm = nlfem_params(float(pb.delta), float(pb.psi), int(pb.mc_samples), int(pb.seed),
                            NLFEM_FP32_LOCAL if pb.precision == "fp32" else NLFEM_FP64,
                            None if om is None else om.ctypes.data, strategy_id(getattr(pb, "strategy", "fullcaps")),
-                           cap_sampling_id(getattr(pb, "cap_sampling", "whole")))
+                           cap_sampling_id(getattr(pb, "cap_sampling", "whole")),
+                           keying_id(getattr(pb, "keying", "pair")))
         sp = nlfem_solve_params(rtol, max_iter)
         t = C.c_uint64()
         self._err(load().nlfem_server_submit(self.handle, C.byref(m), C.byref(prm),

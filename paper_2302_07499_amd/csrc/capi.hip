@@ -45,7 +45,7 @@ struct nlfem_plan {
     int umax = 0, max_row = 0, fx_shift = 0, g_shift = 0, w_shift = 0, row_shift = 0;
     int64_t pair_counts[5] = {0, 0, 0, 0, 0};
     double delta = 0, psi = 0;
-    int mc = 1, precision = 0, strategy = 0, cap_sampling = 0;
+    int mc = 1, precision = 0, strategy = 0, cap_sampling = 0, keying = 0;
     uint64_t seed = 0;
     // device arrays: mesh and ball query
     double *tetX = nullptr, *vol = nullptr;
@@ -492,6 +492,7 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.mc_samples = pl->mc;
     a.caps = pl->strategy == NLFEM_FULLCAPS ? 1 : 0;
     a.vr = pl->cap_sampling == NLFEM_CAPS_OUTSIDE_UI ? 1 : 0;
+    a.keying = pl->keying;
     a.key0 = (uint32_t)(pl->seed & 0xFFFFFFFFull);
     a.key1 = (uint32_t)(pl->seed >> 32);
     a.fx_shift = pl->fx_shift;
@@ -528,8 +529,9 @@ nlfem_status enqueue_rows(nlfem_ctx* c, nlfem_plan* pl, const double* g_nodal, d
 // Autotuner cache: shape class -> (block, workgroups per CU), shared by all
 // batches of the process.
 struct TuneKey {
-    int log2_pairs, log2_items, mc, fp32, per_cu;
+    int log2_pairs, log2_items, mc, fp32, per_cu, keying;
     bool operator<(const TuneKey& o) const {
+        if (keying != o.keying) return keying < o.keying;
         if (log2_pairs != o.log2_pairs) return log2_pairs < o.log2_pairs;
         if (log2_items != o.log2_items) return log2_items < o.log2_items;
         if (mc != o.mc) return mc < o.mc;
@@ -596,6 +598,7 @@ struct nlfem_batch {
     int n_cu = 256;
     bool fp32 = false;
     bool vr = false;
+    int keying = 0;
     bool tuned = false;
     hipStream_t gs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -634,10 +637,10 @@ nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStre
     for (nlfem_plan* pl : b->plans) HIPCHK(launch_fill_u64(pl->gacc, 22 * pl->K, s));
     for (const nlfem_batch::Group& g : b->groups) {
         if (g.grid > 0)
-            HIPCHK(launch_integrate_batch(b->d_descs, g.d_items, g.n_items, g.d_head, g.umax, b->fp32, b->vr, g.block,
+            HIPCHK(launch_integrate_batch(b->d_descs, g.d_items, g.n_items, g.d_head, g.umax, b->fp32, b->vr, b->keying, g.block,
                                           g.grid, s));
         else
-            HIPCHK(launch_integrate_items(b->d_descs, g.d_items, g.n_items, g.umax, b->fp32, b->vr, g.block, s));
+            HIPCHK(launch_integrate_items(b->d_descs, g.d_items, g.n_items, g.umax, b->fp32, b->vr, b->keying, g.block, s));
     }
     for (size_t i = 0; i < b->plans.size(); ++i) {
         const nlfem_batch::Out& o = b->outs[i];
@@ -652,9 +655,9 @@ nlfem_status batch_enqueue(nlfem_batch* b, const double* const* g_nodal, hipStre
 double time_integrate(nlfem_batch* b, const nlfem_batch::Group& g, int block, int grid) {
     Timer t(b->gs);
     const hipError_t e =
-        grid > 0 ? launch_integrate_batch(b->d_descs, g.d_sample, g.n_sample, g.d_head, g.umax, b->fp32, b->vr, block,
+        grid > 0 ? launch_integrate_batch(b->d_descs, g.d_sample, g.n_sample, g.d_head, g.umax, b->fp32, b->vr, b->keying, block,
                                           grid, b->gs)
-                 : launch_integrate_items(b->d_descs, g.d_sample, g.n_sample, g.umax, b->fp32, b->vr, block, b->gs);
+                 : launch_integrate_items(b->d_descs, g.d_sample, g.n_sample, g.umax, b->fp32, b->vr, b->keying, block, b->gs);
     if (e != hipSuccess) return 1e30;
     return t.stop();
 }
@@ -800,6 +803,8 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
         return fail(c, NLFEM_E_INVALID_ARG, "unknown cap sampling mode");
     if (prm->cap_sampling == NLFEM_CAPS_OUTSIDE_UI && prm->mc_samples < 3)
         return fail(c, NLFEM_E_INVALID_ARG, "cap sampling on E_m minus U_I needs mc_samples >= 3");
+    if (prm->keying != NLFEM_KEY_PAIR && prm->keying != NLFEM_KEY_ELEMENT)
+        return fail(c, NLFEM_E_INVALID_ARG, "unknown Monte Carlo keying");
     if (mesh->n_tets >= (int64_t)1 << 31 || mesh->n_vertices >= (int64_t)1 << 31)
         return fail(c, NLFEM_E_UNSUPPORTED, "mesh larger than 2^31 entities");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
@@ -812,6 +817,7 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
     pl->precision = prm->precision;
     pl->strategy = prm->strategy;
     pl->cap_sampling = prm->cap_sampling;
+    pl->keying = prm->keying;
     nlfem_status st = build_plan(c, pl, mesh, prm);
     if (st != NLFEM_OK) {
         hipStreamSynchronize(c->stream);
@@ -966,6 +972,8 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
             return fail(c, NLFEM_E_INVALID_ARG, "all meshes of a batch must use the same precision");
         if (params[i].cap_sampling != params[0].cap_sampling)
             return fail(c, NLFEM_E_INVALID_ARG, "all meshes of a batch must use the same cap sampling");
+        if (params[i].keying != params[0].keying)
+            return fail(c, NLFEM_E_INVALID_ARG, "all meshes of a batch must use the same Monte Carlo keying");
     }
     nlfem_batch* b = new nlfem_batch();
     b->ctx = c;
@@ -978,6 +986,7 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     } guard{b};
     b->fp32 = n > 0 && params[0].precision == NLFEM_FP32_LOCAL;
     b->vr = n > 0 && params[0].cap_sampling == NLFEM_CAPS_OUTSIDE_UI;
+    b->keying = n > 0 ? params[0].keying : 0;
     hipDeviceProp_t prop;
     size_t lds_cu = 160 * 1024;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
@@ -1126,7 +1135,7 @@ nlfem_status nlfem_batch_assemble(nlfem_batch* b, const double* const* f_qp, con
     if (!b->tuned) {
         for (nlfem_batch::Group& G : b->groups) {
             TuneKey key{ilog2(std::max<int64_t>(G.pairs, 1)), ilog2(std::max<int64_t>(G.n_items, 1)),
-                        n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0, G.per_cu};
+                        n ? b->plans[0]->mc : 0, b->fp32 ? 1 : 0, G.per_cu, b->keying};
             TuneVal tv{0, 0, 0.0};
             {
                 std::lock_guard<std::mutex> lk(tune_mutex());

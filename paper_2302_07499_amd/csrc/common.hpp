@@ -111,6 +111,7 @@ struct IntegrateArgs {
     int mc_samples;
     int caps;  // 1: cut points add the fullcaps Monte Carlo term (strategy fullcaps)
     int vr;    // 1: caps of cut pairs with n_in >= 1 sampled on E_m minus U_I (cone tets)
+    int keying;  // 0: N samples per (outer point, element) pair; 1: N samples per element
     uint32_t key0, key1;
     int fx_shift;  // scale 2^fx_shift of the LDS sums T0 and R
     int g_shift;   // scale of the cut part of G_m (global accumulators)
@@ -125,11 +126,11 @@ hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 // persistent: grid workgroups pull (mesh, outer position) items from a device
 // queue (head reset by the launch); block 128 or 256
 hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
-                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
-                                  hipStream_t s);
+                                  unsigned long long* head, int umax, bool fp32, bool vr, int keying, int block,
+                                  int grid, hipStream_t s);
 // one workgroup per work item (mesh, outer position), in list order; block 128 or 256
 hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
-                                  bool vr, int block, hipStream_t s);
+                                  bool vr, int keying, int block, hipStream_t s);
 size_t integrate_lds_bytes(int umax);
 // adds the exact-g defect of the T_Omega_I inner integrals to the load terms
 // in oblk (tensor polynomial g of degree deg per axis, coefficients on the

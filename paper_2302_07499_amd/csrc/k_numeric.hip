@@ -21,6 +21,9 @@
 #ifndef NLFEM_INTEGRATE_WAVES
 #define NLFEM_INTEGRATE_WAVES 3  // minimum waves per SIMD requested for k_integrate (register cap)
 #endif
+#ifndef NLFEM_INTEGRATE_EK_WAVES
+#define NLFEM_INTEGRATE_EK_WAVES 2  // the same for the element-keyed form
+#endif
 
 namespace nlfem {
 
@@ -84,7 +87,7 @@ __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned 
 // the thread index behind an empty asm so that a caller's loop cannot hoist
 // the per-thread addresses out of it (they would stay live across the whole
 // item loop of a persistent kernel and spill).
-template <typename T, int BLOCK, bool VR, typename A, bool OPAQUE_TID = false>
+template <typename T, int BLOCK, bool VR, int KEY, typename A, bool OPAQUE_TID = false>
 __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
     const int umax = a.umax;
@@ -156,8 +159,8 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             CornerGeom cr;
             cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
             if (a.caps) {
-                cut_mc<T, VR>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
-                              (uint32_t)m, S, &cr);
+                cut_mc<T, VR, KEY>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
+                                   (uint32_t)m, S, &cr);
             } else {
                 for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
             }
@@ -207,12 +210,234 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     }
 }
 
-// VR: the caps of n_in = 3 pairs are sampled on E_m minus U_I (a corner tet)
-template <typename T, bool VR>
-__global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
+// a value the same in every lane, held in scalar registers
+__device__ __forceinline__ double uniform_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Element keying (whole-element cap sampling): the samples of E_m are the
+// same points for every outer point, so a thread runs ONE sample loop per
+// (outer tet, inner tet) pair and tests each sample against every cut outer
+// point of it (ek_accept), instead of one loop per cut point.  The Philox
+// call, the spacings and the sample point are shared; per cut point remain
+// three FMAs of the ball test, the U_I planes and the integer sums.  The
+// deterministic part of each cut point (T_I) is folded before the loop, its
+// Monte Carlo moments after it; LDS layout and reductions as integrate_outer.
+template <typename T, int BLOCK, typename A, bool OPAQUE_TID = false>
+__device__ __forceinline__ void integrate_outer_ek(const A& a, int64_t oi, unsigned long long* smem64,
+                                                   double (*P)[3]) {
+    const int umax = a.umax;
+    unsigned long long* R = smem64;             // coarse [4][umax]
+    unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax]
+    unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
+    unsigned long long* T0l = T0 + 4;           // fine   [4]
+    unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
+    int32_t* ve = (int32_t*)(T0p + 8 * BLOCK);
+    const int n = a.outer_ids[oi];
+    const int64_t vb = a.ve_off[oi];
+    const int U = (int)(a.ve_off[oi + 1] - vb);
+    int t = threadIdx.x;
+    if constexpr (OPAQUE_TID) asm volatile("" : "+v"(t));
+    for (int i = t; i < U; i += BLOCK) ve[i] = a.ve_ids[vb + i];
+    for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
+    for (int i = 0; i < 8; ++i) T0p[i * BLOCK + t] = 0ull;
+    if (t < 4) {
+        double Xn[12];
+        for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
+        outer_point(Xn, t, P[t]);
+    }
+    const double w = a.vol[n] * 0.25;
+    const double pw = a.psi * w;
+    __syncthreads();
+    const double d2 = a.delta * a.delta;
+    const double fx = ldexp(1.0, a.fx_shift);
+    const double gfx = ldexp(1.0, a.g_shift);
+    const double wfx = ldexp(1.0, a.w_shift);
+    const int N = a.mc_samples;
+    // the workgroup's frame of the shared sample test (ek_outer): origin O =
+    // vertex 0 of the outer tet, and per outer point 2 (p_k - O) and
+    // delta^2 - |p_k - O|^2, all uniform over the workgroup
+    double O[3];
+    EkOuter o0, o1, o2, o3;
+    {
+        double Xn[12];
+        for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
+        for (int i = 0; i < 3; ++i) O[i] = uniform_f64(Xn[i]);
+        EkOuter* ok[4] = {&o0, &o1, &o2, &o3};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double pk[3];
+            outer_point(Xn, k, pk);
+            const EkOuter e = ek_outer(pk, O, d2);
+            *ok[k] = EkOuter{uniform_f64(e.P2x), uniform_f64(e.P2y), uniform_f64(e.P2z), uniform_f64(e.rho)};
+        }
+    }
+    const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
+    const int64_t ks = a.gstride;
+    for (int64_t p = p0 + t; p < p1; p += BLOCK) {
+        const int m = a.pair_m[p];
+        const uint32_t code = a.pair_cls[p];
+        const double* X = a.tetX + 12 * (int64_t)m;
+        unsigned long long* ga = a.gacc + (int64_t)m;  // word-major G accumulators of E_m
+        // local positions of E_m's vertices in Ve, and the fold of S0, S1 of
+        // outer point k into T0 and R
+        int lv[4];
+        for (int j = 0; j < 4; ++j) lv[j] = lower_bound_i32(ve, U, a.tets[4 * (int64_t)m + j]);
+        auto fold = [&](int k, const double* S) {
+            const double fm = a.region[m] != 0 ? 1.0 : 2.0;
+            {
+                unsigned long long h, l;
+                fx_split(fm * S[0], fx, h, l);
+                T0p[(2 * k) * BLOCK + t] += h;
+                T0p[(2 * k + 1) * BLOCK + t] += l;
+            }
+            for (int j = 0; j < 4; ++j)
+                if (lv[j] < U) fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
+        };
+        // T_Omega inner elements: psi w f_m S2 into G_m (the T_I part before the
+        // sample loop, the Monte Carlo part after it: nothing held across it)
+        auto add_g = [&](const double* g) {
+            for (int i = 0; i < 10; ++i) fxs_add_global(&ga[(2 * i) * ks], &ga[(2 * i + 1) * ks], pw * g[i], gfx);
+        };
+        EkPlanes e0, e1, e2, e3;
+        unsigned cut = 0u;
+        {
+            const double volm = a.vol[m];
+            double g[10];
+            for (int i = 0; i < 10; ++i) g[i] = 0.0;
+            int n_in = 0, n_cut = 0;
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                const int c = (int)((code >> (3 * k)) & 7u);
+                if (c == C_OUT) continue;
+                if (c == C_IN) {
+                    double S[15];
+                    in_moments(volm, S);
+                    fold(k, S);
+                    ++n_in;
+                    continue;
+                }
+                ++n_cut;
+                CutGeom cg;
+                double D[5];
+                cut_det<T>(X, volm, P[k], d2, cg, D, g);
+                fold(k, D);
+                if (a.caps) {
+                    cut |= 1u << k;
+                    EkPlanes e;
+                    ek_planes(cg, e);
+                    if (k == 0) e0 = e;
+                    else if (k == 1) e1 = e;
+                    else if (k == 2) e2 = e;
+                    else e3 = e;
+                }
+            }
+            if (a.region[m] != 0) {
+                if (n_in) fxs_add_global(&ga[20 * ks], &ga[21 * ks], pw * (double)n_in, wfx);
+                if (n_cut) add_g(g);
+            }
+        }
+        if (cut) {
+            EkFirst f0, f1, f2, f3;
+            EkSecond sec;
+            {
+                const EkFrame fr(X, O);
+                for (int s = 0; s < N; s += 2) {
+                    uint32_t wd[4];
+                    mc_philox<1>(0u, (uint32_t)m, (uint32_t)(s >> 1), a.key0, a.key1, wd);
+                    // the two samples of the call one after the other (not
+                    // interleaved: that would hold both samples' values at once)
+#pragma unroll 1
+                    for (int h = 0; h < 2; ++h) {
+                        if (s + h < N) {
+                            uint32_t L[4];
+                            lambda_u(wd, h, L);
+                            const EkSample y = fr.at(L);
+                            uint32_t na = 0u;
+                            if (cut & 1u) na += f0.take(ek_accept(o0, e0, y), L);
+                            if (cut & 2u) na += f1.take(ek_accept(o1, e1, y), L);
+                            if (cut & 4u) na += f2.take(ek_accept(o2, e2, y), L);
+                            if (cut & 8u) na += f3.take(ek_accept(o3, e3, y), L);
+                            sec.take(na, L);
+                        }
+                    }
+                }
+            }
+            const double scale = a.vol[m] / (double)N;
+            auto finish = [&](int k, const EkFirst& acc) {
+                double S[5];
+                acc.moments(scale, S);
+                fold(k, S);
+            };
+            if (cut & 1u) finish(0, f0);
+            if (cut & 2u) finish(1, f1);
+            if (cut & 4u) finish(2, f2);
+            if (cut & 8u) finish(3, f3);
+            if (a.region[m] != 0) {
+                const uint64_t cnt = (uint64_t)f0.cnt + f1.cnt + f2.cnt + f3.cnt;
+                const uint64_t A1 = (uint64_t)f0.a1 + f1.a1 + f2.a1 + f3.a1;
+                const uint64_t A2 = (uint64_t)f0.a2 + f1.a2 + f2.a2 + f3.a2;
+                const uint64_t A3 = (uint64_t)f0.a3 + f1.a3 + f2.a3 + f3.a3;
+                double g[10];
+                sec.moments(scale, cnt, A1, A2, A3, g);
+                add_g(g);
+            }
+        }
+    }
+    __syncthreads();
+    if (t < 8) {
+        unsigned long long v = 0ull;
+        for (int i = 0; i < BLOCK; ++i) v += T0p[t * BLOCK + i];
+        if (t & 1) T0l[t >> 1] = v;
+        else T0[t >> 1] = v;
+    }
+    __syncthreads();
+    const int sh = a.fx_shift;
+    double* cb = a.cblk + 4 * vb;
+    for (int r = t; r < 4 * U; r += BLOCK) {
+        const int i = r >> 2, j = r & 3;
+        double cR = 0.0;
+        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
+        cb[r] = -(pw * cR);
+    }
+    double* ob = a.oblk + 20 * oi;
+    if (t < 16) {
+        const int j = t >> 2, jj = t & 3;
+        double O = 0.0;
+        for (int k = 0; k < 4; ++k) O += (rule_w(k, j) * rule_w(k, jj)) * fx_value(T0[k], T0l[k], sh);
+        ob[t] = pw * O;
+    } else if (t < 20) {
+        const int j = t - 16;
+        double f = 0.0;
+        if (a.f_qp)
+            for (int k = 0; k < 4; ++k) f += (w * rule_w(k, j)) * a.f_qp[4 * (int64_t)n + k];
+        ob[t] = f;
+    }
+}
+
+// the form of one outer tet's integration: element keying on whole elements
+// shares its sample loop across the outer points, everything else loops per point
+template <typename T, int BLOCK, bool VR, int KEY, typename A, bool OPAQUE_TID = false>
+__device__ __forceinline__ void integrate_any(const A& a, int64_t oi, unsigned long long* smem64, double (*P)[3]) {
+    if constexpr (KEY == 1 && !VR) integrate_outer_ek<T, BLOCK, A, OPAQUE_TID>(a, oi, smem64, P);
+    else integrate_outer<T, BLOCK, VR, KEY, A, OPAQUE_TID>(a, oi, smem64, P);
+}
+
+// waves per SIMD the register cap is set for: the shared-sample loop keeps
+// four outer points' sample tests and sums live and takes the registers of 2
+// (form = 2 KEY + VR: one argument, so that it passes through __launch_bounds__)
+constexpr int integrate_waves(int form) { return form == 2 ? NLFEM_INTEGRATE_EK_WAVES : NLFEM_INTEGRATE_WAVES; }
+
+// VR: the caps of cut pairs with n_in >= 1 are sampled on E_m minus U_I;
+// KEY: pair (0) or element (1) keying of the Monte Carlo samples
+template <typename T, bool VR, int KEY>
+__global__ __launch_bounds__(256, integrate_waves(2 * KEY + VR)) void k_integrate(IntegrateArgs a) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
-    integrate_outer<T, 256, VR>(a, (int64_t)blockIdx.x, smem64, P);
+    integrate_any<T, 256, VR, KEY>(a, (int64_t)blockIdx.x, smem64, P);
 }
 
 // descriptors of a batch are read-only for the whole launch: read through the
@@ -223,8 +448,8 @@ typedef const __attribute__((address_space(4))) IntegrateArgs ConstArgs;
 // Persistent batched integration: a grid sized to the machine pulls work
 // items (mesh, outer position) from a device queue, longest first, until it
 // is empty; each item's results depend on the item only.
-template <typename T, int BLOCK, bool VR>
-__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batch(const IntegrateArgs* descs,
+template <typename T, int BLOCK, bool VR, int KEY>
+__global__ __launch_bounds__(BLOCK, integrate_waves(2 * KEY + VR)) void k_integrate_batch(const IntegrateArgs* descs,
                                                                                  const int2* items, int64_t n_items,
                                                                                  unsigned long long* head) {
     extern __shared__ unsigned long long smem64[];
@@ -241,7 +466,7 @@ __global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batc
         const int mesh = __builtin_amdgcn_readfirstlane(item.x);
         const int pos = __builtin_amdgcn_readfirstlane(item.y);
         ConstArgs* d = (ConstArgs*)(descs + mesh);
-        integrate_outer<T, BLOCK, VR, ConstArgs, true>(*d, (int64_t)pos, smem64, P);
+        integrate_any<T, BLOCK, VR, KEY, ConstArgs, true>(*d, (int64_t)pos, smem64, P);
         __syncthreads();
     }
 }
@@ -251,8 +476,8 @@ __global__ void k_reset_u64(unsigned long long* p) { *p = 0ull; }
 // One workgroup per work item (mesh, outer position), in list order: the
 // dispatcher starts workgroups in increasing index as slots free up, so a
 // longest-first list is taken longest first without a software queue.
-template <typename T, int BLOCK, bool VR>
-__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_items(const IntegrateArgs* descs,
+template <typename T, int BLOCK, bool VR, int KEY>
+__global__ __launch_bounds__(BLOCK, integrate_waves(2 * KEY + VR)) void k_integrate_items(const IntegrateArgs* descs,
                                                                                  const int2* items) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
@@ -260,7 +485,7 @@ __global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_item
     const int mesh = __builtin_amdgcn_readfirstlane(item.x);
     const int pos = __builtin_amdgcn_readfirstlane(item.y);
     ConstArgs* d = (ConstArgs*)(descs + mesh);
-    integrate_outer<T, BLOCK, VR>(*d, (int64_t)pos, smem64, P);
+    integrate_any<T, BLOCK, VR, KEY>(*d, (int64_t)pos, smem64, P);
 }
 
 
@@ -290,6 +515,8 @@ __global__ __launch_bounds__(kExactGBlock, 2) void k_exact_g(IntegrateArgs a, co
     }
     __syncthreads();
     const double d2 = a.delta * a.delta;
+    double O[3];
+    for (int i = 0; i < 3; ++i) O[i] = a.tetX[12 * (int64_t)n + i];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = a.pair_off[oi] + t; p < a.pair_off[oi + 1]; p += kExactGBlock) {
         const int m = a.pair_m[p];
@@ -302,8 +529,8 @@ __global__ __launch_bounds__(kExactGBlock, 2) void k_exact_g(IntegrateArgs a, co
         for (int k = 0; k < 4; ++k) {
             const int c = (int)((code >> (3 * k)) & 7u);
             if (c == C_OUT) continue;
-            acc[k] += pair_g_defect<DEG>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1,
-                                         (uint32_t)(4 * n + k), (uint32_t)m, gv, cf);
+            acc[k] += pair_g_defect<DEG>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.keying, a.key0, a.key1,
+                                         (uint32_t)(4 * n + k), (uint32_t)m, gv, cf, O);
         }
     }
     for (int k = 0; k < 4; ++k) red[k][t] = acc[k];
@@ -322,7 +549,7 @@ __global__ __launch_bounds__(kExactGBlock, 2) void k_exact_g(IntegrateArgs a, co
 }
 
 // per-pair moments for outer positions [o_lo, o_hi): slot (p - pair_off[o_lo])*4 + k
-template <typename T, bool VR>
+template <typename T, bool VR, int KEY>
 __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_lo, double* out_S, int32_t* out_qm) {
     const int64_t oi = o_lo + blockIdx.x;
     const int n = a.outer_ids[oi];
@@ -345,8 +572,8 @@ __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_
             out_qm[3 * idx + 2] = c;
             if (c == C_OUT) continue;
             double S[15];
-            pair_moments<T, VR>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1, (uint32_t)(4 * n + k),
-                            (uint32_t)m, S);
+            pair_moments<T, VR, KEY>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1,
+                                     (uint32_t)(4 * n + k), (uint32_t)m, S, Xn);
             for (int i = 0; i < 15; ++i) out_S[15 * idx + i] = S[i];
         }
     }
@@ -396,23 +623,41 @@ inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 
 size_t integrate_lds_bytes(int umax) { return (size_t)umax * 68 + 64 + 8 * 256 * sizeof(unsigned long long); }
 
+// kernel selection over (precision, cap sampling, keying)
+#define NLFEM_DISPATCH3(fp32, vr, key, LAUNCH)                 \
+    do {                                                        \
+        if (vr) {                                               \
+            if (key) {                                          \
+                if (fp32) LAUNCH(float, true, 1);               \
+                else LAUNCH(double, true, 1);                   \
+            } else {                                            \
+                if (fp32) LAUNCH(float, true, 0);               \
+                else LAUNCH(double, true, 0);                   \
+            }                                                   \
+        } else {                                                \
+            if (key) {                                          \
+                if (fp32) LAUNCH(float, false, 1);              \
+                else LAUNCH(double, false, 1);                  \
+            } else {                                            \
+                if (fp32) LAUNCH(float, false, 0);              \
+                else LAUNCH(double, false, 0);                  \
+            }                                                   \
+        }                                                       \
+    } while (0)
+
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;
     size_t sh = integrate_lds_bytes(a.umax);
     const unsigned g = (unsigned)a.n_outer;
-    if (a.vr) {
-        if (fp32) k_integrate<float, true><<<g, 256, sh, s>>>(a);
-        else k_integrate<double, true><<<g, 256, sh, s>>>(a);
-    } else {
-        if (fp32) k_integrate<float, false><<<g, 256, sh, s>>>(a);
-        else k_integrate<double, false><<<g, 256, sh, s>>>(a);
-    }
+#define L_ONE(T, VR, KEY) k_integrate<T, VR, KEY><<<g, 256, sh, s>>>(a)
+    NLFEM_DISPATCH3(fp32, a.vr, a.keying, L_ONE);
+#undef L_ONE
     return hipGetLastError();
 }
 
 hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items, int64_t n_items,
-                                  unsigned long long* head, int umax, bool fp32, bool vr, int block, int grid,
-                                  hipStream_t s) {
+                                  unsigned long long* head, int umax, bool fp32, bool vr, int keying, int block,
+                                  int grid, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (n_items > 0x7fffffff || grid <= 0) return hipErrorInvalidValue;
     const size_t sh = integrate_lds_bytes(umax);
@@ -420,47 +665,31 @@ hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items,
     k_reset_u64<<<1, 1, 0, s>>>(head);
     const unsigned g = (unsigned)grid;
     if (block == 128) {
-        if (vr) {
-            if (fp32) k_integrate_batch<float, 128, true><<<g, 128, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 128, true><<<g, 128, sh, s>>>(descs, items, n_items, head);
-        } else {
-            if (fp32) k_integrate_batch<float, 128, false><<<g, 128, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 128, false><<<g, 128, sh, s>>>(descs, items, n_items, head);
-        }
+#define L_B128(T, VR, KEY) k_integrate_batch<T, 128, VR, KEY><<<g, 128, sh, s>>>(descs, items, n_items, head)
+        NLFEM_DISPATCH3(fp32, vr, keying, L_B128);
+#undef L_B128
     } else {
-        if (vr) {
-            if (fp32) k_integrate_batch<float, 256, true><<<g, 256, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 256, true><<<g, 256, sh, s>>>(descs, items, n_items, head);
-        } else {
-            if (fp32) k_integrate_batch<float, 256, false><<<g, 256, sh, s>>>(descs, items, n_items, head);
-            else k_integrate_batch<double, 256, false><<<g, 256, sh, s>>>(descs, items, n_items, head);
-        }
+#define L_B256(T, VR, KEY) k_integrate_batch<T, 256, VR, KEY><<<g, 256, sh, s>>>(descs, items, n_items, head)
+        NLFEM_DISPATCH3(fp32, vr, keying, L_B256);
+#undef L_B256
     }
     return hipGetLastError();
 }
 
 hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
-                                  bool vr, int block, hipStream_t s) {
+                                  bool vr, int keying, int block, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (n_items > 0x7fffffff) return hipErrorInvalidValue;
     const size_t sh = integrate_lds_bytes(umax);
     const unsigned g = (unsigned)n_items;
     if (block == 128) {
-        if (vr) {
-            if (fp32) k_integrate_items<float, 128, true><<<g, 128, sh, s>>>(descs, items);
-            else k_integrate_items<double, 128, true><<<g, 128, sh, s>>>(descs, items);
-        } else {
-            if (fp32) k_integrate_items<float, 128, false><<<g, 128, sh, s>>>(descs, items);
-            else k_integrate_items<double, 128, false><<<g, 128, sh, s>>>(descs, items);
-        }
+#define L_I128(T, VR, KEY) k_integrate_items<T, 128, VR, KEY><<<g, 128, sh, s>>>(descs, items)
+        NLFEM_DISPATCH3(fp32, vr, keying, L_I128);
+#undef L_I128
     } else {
-        if (vr) {
-            if (fp32) k_integrate_items<float, 256, true><<<g, 256, sh, s>>>(descs, items);
-            else k_integrate_items<double, 256, true><<<g, 256, sh, s>>>(descs, items);
-        } else {
-            if (fp32) k_integrate_items<float, 256, false><<<g, 256, sh, s>>>(descs, items);
-            else k_integrate_items<double, 256, false><<<g, 256, sh, s>>>(descs, items);
-        }
+#define L_I256(T, VR, KEY) k_integrate_items<T, 256, VR, KEY><<<g, 256, sh, s>>>(descs, items)
+        NLFEM_DISPATCH3(fp32, vr, keying, L_I256);
+#undef L_I256
     }
     return hipGetLastError();
 }
@@ -469,18 +698,11 @@ hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, i
                               int32_t* out_qm, hipStream_t s) {
     if (o_hi <= o_lo) return hipSuccess;
     const unsigned g = (unsigned)(o_hi - o_lo);
-    if (a.vr) {
-        if (fp32) k_debug_pairs<float, true><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
-        else k_debug_pairs<double, true><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
-    } else {
-        if (fp32) k_debug_pairs<float, false><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
-        else k_debug_pairs<double, false><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm);
-    }
+#define L_DBG(T, VR, KEY) k_debug_pairs<T, VR, KEY><<<g, 256, 0, s>>>(a, o_lo, out_S, out_qm)
+    NLFEM_DISPATCH3(fp32, a.vr, a.keying, L_DBG);
+#undef L_DBG
     return hipGetLastError();
 }
-
-
-
 
 hipError_t launch_exact_g(const IntegrateArgs& a, const double* g_nodal, const double* coef, int deg, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;

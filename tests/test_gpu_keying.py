@@ -1,0 +1,167 @@
+"""Element keying of the fullcaps Monte Carlo samples (N samples per element,
+the same points of E_m for every outer point; Sec. 4.2.2 leaves the sampling
+open) against the oracle's element-keyed assembly: classification, pair
+lists and CSR pattern bit-exact, FP64 entries within 1e-12 of the row scale
+after the near-tie allowance, per-pair moments within 1e-14, the batch
+bitwise equal to single plans, the cap-region sampler and the paper-exact
+right-hand side in the same keying, and the two keyings differing."""
+import sys
+
+import numpy as np
+import pytest
+
+import helpers as H
+import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _say(msg):
+    sys.stdout.write(f"[gpu-test] {msg}\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_07499_amd as P
+    d = P.Device(0)
+    yield d
+    d.close()
+
+
+def _system(dev, pb, outer_mask=None):
+    import paper_2302_07499_amd as P
+    _say(f"plan {pb.name} K={pb.mesh.n_tets} delta={pb.delta:.5g} N={pb.mc_samples} {pb.precision} "
+         f"keying={pb.keying} caps={pb.cap_sampling}")
+    plan = dev.plan_problem(pb, outer_mask=outer_mask)
+    s = plan.assemble(pb.f_qp, pb.g_nodal)
+    return plan, P.system_to_numpy(s)
+
+
+def _check_values(g, o, tol, what):
+    e = H.value_errors(g, o)
+    _say(f"{what} errors {e}")
+    assert e["ff_abs"] <= tol and e["fc_abs"] <= tol and e["rhs"] <= tol
+    return e
+
+
+@pytest.fixture(scope="module")
+def plain_elem(dev, orc):
+    pb = mg.plain_problem()
+    pb.keying = "element"
+    plan, g = _system(dev, pb)
+    o = orc.problem_assemble(pb)
+    yield pb, plan, g, o
+    plan.destroy()
+
+
+def test_plain_element_keying_vs_oracle(plain_elem):
+    pb, plan, g, o = plain_elem
+    assert np.array_equal(g["pair_counts"], o["pair_counts"])
+    H.pattern_equal(g, o)
+    e = _check_values(g, o, FP64_TOL, "plain element-keyed fp64")
+    assert e["ff_rel"] <= FP64_TOL and e["fc_rel"] <= FP64_TOL
+    tot, mag = H.row_sums(g)
+    assert np.all(np.abs(tot) <= 1e-12 * mag)
+
+
+def test_plain_element_keying_pair_moments(plain_elem, orc):
+    pb, plan, g, o = plain_elem
+    m = pb.mesh
+    region = np.array([pb.vertex_free[t].any() for t in m.tets])
+    outer = np.nonzero(region)[0]
+    ties = 0
+    for n in outer[:: max(1, len(outer) // 6)]:
+        rec = plan.debug_pairs(4 * int(n), 4 * int(n) + 4)
+        for k in range(4):
+            err, t = H.point_pairs_vs_oracle(orc, m, rec, n, k, pb.delta, pb.mc_samples, pb.seed, keying="element")
+            ties += t
+            assert err <= 1e-14, (n, k, err)
+    _say(f"plain element-keyed pair moments: near ties {ties}")
+
+
+def test_keyings_differ_and_both_are_deterministic(dev, plain_elem):
+    import paper_2302_07499_amd as P
+    pb, plan, g, o = plain_elem
+    pbp = mg.plain_problem()
+    plan_p, gp = _system(dev, pbp)
+    assert np.array_equal(gp["ff_col"], g["ff_col"])
+    assert not np.array_equal(gp["ff_val"], g["ff_val"])
+    g2 = P.system_to_numpy(plan.assemble(pb.f_qp, pb.g_nodal))
+    for k in ["ff_val", "fc_val", "rhs"]:
+        assert np.array_equal(g[k], g2[k]), k
+    plan_p.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_precision_subset_element_keying(dev, orc, precision):
+    pb = mg.precision_problem(precision)
+    pb.keying = "element"
+    mask = mg.outer_subset_mask(pb.mesh.n_tets, 0.0015, seed=11)
+    plan, g = _system(dev, pb, outer_mask=mask)
+    _say("oracle on the subset ...")
+    o = orc.problem_assemble(pb, outer_mask=mask)
+    assert np.array_equal(g["pair_counts"], o["pair_counts"])
+    H.pattern_equal(g, o)
+    _check_values(g, o, FP64_TOL if precision == "fp64" else FP32_TOL, f"precision subset element-keyed {precision}")
+    plan.destroy()
+
+
+def test_element_keying_cap_region_sampling(dev, orc):
+    pb = mg.plain_problem()
+    pb.keying = "element"
+    pb.cap_sampling = "outside_ui"
+    plan, g = _system(dev, pb)
+    o = orc.problem_assemble(pb)
+    H.pattern_equal(g, o)
+    _check_values(g, o, FP64_TOL, "plain element-keyed cap-region")
+    plan.destroy()
+
+
+def test_element_keying_exact_g(dev, orc):
+    import paper_2302_07499_amd as P
+    pb = mg.convergence_problem(6, mc_samples=64)
+    pb.keying = "element"
+    plan = dev.plan_problem(pb)
+    b = P.system_to_numpy(plan.assemble(pb.f_qp, pb.g_nodal, g_poly=pb.g_poly))
+    plan.destroy()
+    o = orc.problem_assemble(pb, exact_g=True)
+    H.pattern_equal(b, o)
+    scale = float(np.max(np.abs(o["rhs"])))
+    err = float(np.max(np.maximum(np.abs(b["rhs"] - o["rhs"]) - o["tie_allow_rhs"], 0.0))) / scale
+    _say(f"element-keyed exact-g rhs error {err:.3e}")
+    assert err <= FP64_TOL
+
+
+def test_element_keying_batch_equals_single(dev):
+    import paper_2302_07499_amd as P
+    pbs = []
+    for b, (n, r, N) in enumerate([(6, 2.0, 16), (8, 3.0, 33), (5, 4.0, 8), (9, 2.0, 64)]):
+        pb = mg.make_problem(f"ek{b}", n, delta_over_h=r, jitter=0.15, jitter_seed=700 + b, mc_samples=N, seed=b)
+        pb.keying = "element"
+        pbs.append(pb)
+    batch = P.Batch(dev, pbs)
+    batch.set_inputs([pb.f_qp for pb in pbs], [pb.g_nodal for pb in pbs])
+    for rep in range(2):
+        batch.assemble()
+        for i, pb in enumerate(pbs):
+            plan, e = _system(dev, pb)
+            plan.destroy()
+            g = batch.system_numpy(i)
+            for k in ["ff_val", "fc_val", "rhs"]:
+                assert np.array_equal(g[k], e[k]), (rep, i, k)
+    batch.destroy()
+
+
+def test_unknown_keying_rejected(dev):
+    import paper_2302_07499_amd as P
+    pb = mg.plain_problem()
+    pb.keying = 2
+    with pytest.raises(P.NlfemError):
+        dev.plan_problem(pb)

@@ -28,10 +28,22 @@ Omega = (0,1)^3, delta = 0.1, u = prod x_d (1 - x_d), Kuhn meshes h = 1/m
 the assembly time, CG iterations, L2 error, observed order and the paper's
 efficiency ratio lambda.
 
-Serving: requests (n ~ U{8..40}, delta/h ~ U[2,5], N in {32,64}, FP64 /
-FP32-local 50/50) through the request server: saturation throughput with all
-requests queued at once, then a Poisson stream at 0.9x that rate for the
-latency percentiles (arrival -> solution in host memory).
+Element keying: the main workload with N samples per element shared by the
+outer points of an outer tet (FP64 and FP32-local), with the integration
+kernel's roofline fraction.
+
+Large: 64^3 Kuhn cubes (1,572,864 tets), jitter 0.2h, delta = 4h, N = 128,
+FP64 and FP32-local: pairs/s, phase times, roofline fraction, CG.
+
+Serving: a stream of 500 requests (n ~ U{8..40}, delta/h ~ U[2,5], N in
+{32,64}, FP64 / FP32-local 50/50) through the request server: saturation
+throughput with all requests queued at once, then Poisson streams at 0.5x
+and 0.9x that rate for the latency percentiles (arrival -> solution in host
+memory).
+
+CPU baseline: the oracle (serial FP64 brute force) on a seeded 0.2 % subset of
+the main workload's outer tets, with the host CPU model; the library's FP64,
+FP32-local and element-keyed results on the same subset against it.
 
 Prints one JSON line.
 """
@@ -117,6 +129,20 @@ def recorded_traffic():
         return None, f"no usable counter record ({e.__class__.__name__})"
 
 
+def host_cpu():
+    """Model and logical CPU count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def log(msg):
     sys.stderr.write(f"[bench] {msg}\n")
     sys.stderr.flush()
@@ -126,35 +152,53 @@ def pct(a, q):
     return round(float(np.percentile(np.asarray(a), q)), 3) if len(a) else None
 
 
-def run_precision(P, mg, dev, args):
-    import torch
-    pb = mg.precision_problem()
-    mesh = pb.mesh
-    t = torch
-    d_coords = dev.to_dev(mesh.coords, t.float64)
-    d_tets = dev.to_dev(mesh.tets, t.int32)
-    d_free = dev.to_dev(pb.vertex_free, t.uint8)
-    d_f = dev.to_dev(pb.f_qp, t.float64)
-    d_g = dev.to_dev(pb.g_nodal, t.float64)
-    m = P.nlfem_mesh(mesh.n_vertices, mesh.n_tets, d_coords.data_ptr(), d_tets.data_ptr(), d_free.data_ptr(),
-                     None, 1)
+def flops_of(info, N):
+    """Algorithmic FLOPs of one integration launch (per-unit model above)."""
+    cut = int(sum(info["pair_counts"][1:]))
+    inn = int(info["pair_counts"][0])
+    return FLOP_PER_SAMPLE * cut * N + FLOP_PER_CUT_PAIR * cut + FLOP_PER_IN_PAIR * inn
 
-    def run(precision, steps, warmup, strategy="fullcaps", cap_sampling="whole", seed=None):
-        prm = P.nlfem_params(pb.delta, pb.psi, pb.mc_samples, pb.seed if seed is None else seed,
-                             P.NLFEM_FP32_LOCAL if precision == "fp32" else P.NLFEM_FP64, None,
-                             P.strategy_id(strategy), P.cap_sampling_id(cap_sampling))
+
+class Stepper:
+    """One workload resident in HBM; a step is plan_create + assemble on it
+    (the whole assembly path), timed with a synchronised wall clock, with the
+    library's HIP-event phase timings beside it."""
+
+    def __init__(self, P, dev, pb, label):
+        import torch
+        self.P, self.dev, self.pb, self.label, self.torch = P, dev, pb, label, torch
+        mesh = pb.mesh
+        t = torch
+        self.keep = [dev.to_dev(mesh.coords, t.float64), dev.to_dev(mesh.tets, t.int32),
+                     dev.to_dev(pb.vertex_free, t.uint8)]
+        self.d_f = dev.to_dev(pb.f_qp, t.float64)
+        self.d_g = dev.to_dev(pb.g_nodal, t.float64)
+        self.m = P.nlfem_mesh(mesh.n_vertices, mesh.n_tets, self.keep[0].data_ptr(), self.keep[1].data_ptr(),
+                              self.keep[2].data_ptr(), None, 1)
+
+    def params(self, precision, strategy="fullcaps", cap_sampling="whole", seed=None, keying="pair", mask=None):
+        P, pb = self.P, self.pb
+        return P.nlfem_params(pb.delta, pb.psi, pb.mc_samples, pb.seed if seed is None else seed,
+                              P.NLFEM_FP32_LOCAL if precision == "fp32" else P.NLFEM_FP64,
+                              None if mask is None else mask.data_ptr(), P.strategy_id(strategy),
+                              P.cap_sampling_id(cap_sampling), P.keying_id(keying))
+
+    def run(self, precision, steps, warmup, keep_last=True, **kw):
+        P, dev, torch = self.P, self.dev, self.torch
+        prm = self.params(precision, **kw)
         # allocate outputs once (sizes are the same every step)
-        plan = P.Plan(dev, P.nlfem_plan_create(dev.ctx, m, prm))
+        plan = P.Plan(dev, P.nlfem_plan_create(dev.ctx, self.m, prm))
         sysm = plan.alloc_system()
         plan.destroy()
         times, tk = [], []
         info = None
+        last = None
         for i in range(warmup + steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            h = P.nlfem_plan_create(dev.ctx, m, prm)
-            P.nlfem_assemble(h, d_f, d_g, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.fc_row_ptr, sysm.fc_col,
-                             sysm.fc_val, sysm.rhs, sysm.free_to_vertex, ctx=dev.ctx)
+            h = P.nlfem_plan_create(dev.ctx, self.m, prm)
+            P.nlfem_assemble(h, self.d_f, self.d_g, sysm.ff_row_ptr, sysm.ff_col, sysm.ff_val, sysm.fc_row_ptr,
+                             sysm.fc_col, sysm.fc_val, sysm.rhs, sysm.free_to_vertex, ctx=dev.ctx)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             if i >= warmup:
@@ -162,12 +206,34 @@ def run_precision(P, mg, dev, args):
                 tk.append(P.nlfem_plan_timings(h))
             if info is None:
                 info = P.nlfem_plan_info(h)
-            if i == warmup + steps - 1:
-                plan = P.Plan(dev, h)
+            if i == warmup + steps - 1 and keep_last:
+                last = P.Plan(dev, h)
             else:
                 P.nlfem_plan_destroy(h)
-            log(f"precision {precision} {strategy} step {i} {1e3 * (t1 - t0):.1f} ms")
-        return times, np.array(tk), info, plan, sysm
+            desc = {k: v for k, v in kw.items() if k != "mask"}
+            log(f"{self.label} {precision} {desc} step {i} {1e3 * (t1 - t0):.1f} ms")
+        return times, np.array(tk), info, last, sysm
+
+    def line(self, times, tk, info):
+        """pairs/s, ms per step, phase ms and the integration roofline of a run."""
+        pairs = int(sum(info["pair_counts"]))
+        ms = 1e3 * float(np.mean(times))
+        t_int = float(np.mean(tk[:, 3])) * 1e-3
+        ach = flops_of(info, self.pb.mc_samples) / t_int / 1e12
+        return {"value": round(pairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
+                "pairs_per_step": pairs, "integrate_ms": round(t_int * 1e3, 3),
+                "plan_ms": round(float(np.mean(tk[:, 0])), 3), "rows_ms": round(float(np.mean(tk[:, 4])), 3),
+                "integrate_frac_fp64_peak": round(ach / PEAK_FP64_TFLOPS, 4)}
+
+
+def run_precision(P, mg, dev, args):
+    import torch
+    pb = mg.precision_problem()
+    st = Stepper(P, dev, pb, "precision")
+
+    def run(precision, steps, warmup, strategy="fullcaps", cap_sampling="whole", seed=None, keying="pair"):
+        return st.run(precision, steps, warmup, strategy=strategy, cap_sampling=cap_sampling, seed=seed,
+                      keying=keying)
 
     times64, tk64, info, plan64, sys64 = run("fp64", args.steps, args.warmup)
     times32, tk32, info32, plan32, sys32 = run("fp32", args.steps, args.warmup)
@@ -176,6 +242,7 @@ def run_precision(P, mg, dev, args):
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import helpers as H
     e32 = H.value_errors(a32, a64)
+    x, it, rr, ok = plan64.solve(sys64, rtol=1e-10)  # first call: work vectors allocated
     torch.cuda.synchronize()
     c0 = time.perf_counter()
     x, it, rr, ok = plan64.solve(sys64, rtol=1e-10)
@@ -187,17 +254,59 @@ def run_precision(P, mg, dev, args):
     plan64.destroy()
     plan32.destroy()
     del sys64, sys32, x, x32
+    # element keying: N samples per element shared by the outer points
+    keyed = {}
+    for prec in ["fp64", "fp32"]:
+        ts, tks, inf, pl, sm = run(prec, max(2, args.steps // 2), 1, keying="element")
+        pl.destroy()
+        del sm
+        keyed[prec] = st.line(ts, tks, inf)
+    # the plain workload whole, FP64 and FP32-local, solved by CG: compared with
+    # the oracle's system and CG solution after the device is closed
+    plain = {}
+    pbp = mg.plain_problem()
+    for prec in ["fp64", "fp32"]:
+        pbp.precision = prec
+        pl = dev.plan_problem(pbp)
+        sm = pl.assemble(pbp.f_qp, pbp.g_nodal)
+        xs, its, rrs, oks = pl.solve(sm, rtol=1e-10)
+        plain[prec] = (P.system_to_numpy(sm), xs.cpu().numpy())
+        pl.destroy()
+        del sm
+
+    def plain_vs_oracle(oracle, H):
+        pbq = mg.plain_problem()
+        So = oracle.problem_assemble(pbq)
+        xo, _, _, _ = oracle.cg(So["ff_row_ptr"], So["ff_col"], So["ff_val"], So["rhs"], rtol=1e-12)
+        res = {}
+        for prec, (g, xg) in plain.items():
+            e = H.value_errors(g, So)
+            res[prec] = {"max_entry_err_rowscale": max(e["ff_abs"], e["fc_abs"]), "rhs_err": e["rhs"],
+                         "solution_err": float(np.max(np.abs(xg - xo)) / max(np.max(np.abs(xo)), 1e-300))}
+        return res
+    # the library on the outer-tet subset the oracle times (cpu_baseline), kept
+    # for the per-entry errors against the oracle
+    subset = None
+    if not args.no_cpu_baseline:
+        mask = mg.outer_subset_mask(pb.mesh.n_tets, args.cpu_fraction, seed=13)
+        d_mask = dev.to_dev(mask, torch.uint8)
+        subset = {"mask": mask}
+        for key, prec, kk in [("fp64", "fp64", "pair"), ("fp32", "fp32", "pair"), ("fp64_element", "fp64", "element")]:
+            _, _, _, pl, sm = st.run(prec, 1, 0, keying=kk, mask=d_mask)
+            subset[key] = P.system_to_numpy(sm)
+            pl.destroy()
+            del sm
     # the other ball approximation strategies on the same workload (FP64)
     strategies = None
     if not args.no_strategies:
         strategies = {}
-        for st in ["nocaps", "overlap", "inside", "barycenter"]:
-            ts, tks, inf, pl, sm = run("fp64", 2, 1, st)
+        for sname in ["nocaps", "overlap", "inside", "barycenter"]:
+            ts, tks, inf, pl, sm = run("fp64", 2, 1, sname)
             pl.destroy()
             del sm
             npairs = int(sum(inf["pair_counts"]))
             ms = 1e3 * float(np.mean(ts))
-            strategies[st] = {"value": round(npairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
+            strategies[sname] = {"value": round(npairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_step": round(ms, 3),
                               "pairs_per_step": npairs, "integrate_ms": round(float(np.mean(tks[:, 3])), 3)}
         # fullcaps with the caps sampled on E - U_I (corner tet or three cone tets), and the
         # seed-to-seed spread of the matrix entries in both sampling modes
@@ -223,7 +332,46 @@ def run_precision(P, mg, dev, args):
             "spread_ratio": round(spread["outside_ui"] / max(spread["whole"], 1e-300), 4)}
     return {"pb": pb, "times64": times64, "tk64": tk64, "times32": times32, "tk32": tk32, "info": info,
             "e32": e32, "sol_err32": sol_err, "cg": {"iters": it, "rel_residual": rr, "converged": bool(ok),
-                                                     "ms": round(cg_ms, 2)}, "strategies": strategies}
+                                                     "ms": round(cg_ms, 2)}, "strategies": strategies,
+            "element_keying": keyed, "subset": subset, "plain_vs_oracle": plain_vs_oracle}
+
+
+def run_large(P, mg, dev, args):
+    """The large single-mesh workload: 64^3 Kuhn cubes (1,572,864 tets),
+    jitter 0.2h, delta = 4h, N = 128; FP64 and FP32-local, assemble + CG."""
+    import torch
+    pb = mg.large_problem()
+    st = Stepper(P, dev, pb, "large")
+    out = {"workload": "64^3 Kuhn cubes (1,572,864 tets), jitter 0.2h seed 1, delta=4h, N=128 MC per cut pair"}
+    sysd = {}
+    for prec in ["fp64", "fp32"]:
+        ts, tks, inf, pl, sm = st.run(prec, args.large_steps, 1)
+        line = st.line(ts, tks, inf)
+        line["cut_pairs"] = int(sum(inf["pair_counts"][1:]))
+        line["in_pairs"] = int(inf["pair_counts"][0])
+        line["n_free"] = inf["n_free"]
+        line["nnz_ff"] = inf["nnz_ff"]
+        x, it, rr, ok = pl.solve(sm, rtol=1e-10)  # first call: work vectors allocated
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        x, it, rr, ok = pl.solve(sm, rtol=1e-10)
+        torch.cuda.synchronize()
+        line["cg"] = {"iters": it, "rel_residual": rr, "converged": bool(ok),
+                      "ms": round(1e3 * (time.perf_counter() - c0), 2)}
+        log(f"large {prec}: {line['ms_per_step']:.1f} ms/step, integrate {line['integrate_ms']:.1f} ms, "
+            f"CG {it} it {line['cg']['ms']:.1f} ms")
+        sysd[prec] = (P.system_to_numpy(sm), x.cpu().numpy())
+        out[prec] = line
+        pl.destroy()
+        del sm, x
+        P.nlfem_trim(dev.ctx)
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import helpers as H
+    e = H.value_errors(sysd["fp32"][0], sysd["fp64"][0])
+    xa, xb = sysd["fp64"][1], sysd["fp32"][1]
+    out["fp32_local_vs_fp64"] = {"max_entry_err_rowscale": max(e["ff_abs"], e["fc_abs"]), "rhs_err": e["rhs"],
+                                 "solution_err": float(np.max(np.abs(xb - xa)) / max(np.max(np.abs(xa)), 1e-300))}
+    return out
 
 
 def run_convergence(P, mg, dev, args):
@@ -328,6 +476,8 @@ def run_batched(P, mg, dev, args):
     P.nlfem_trim(dev.ctx)
     ms = 1e3 * float(np.mean(ts))
     return {"value": round(pairs / (ms * 1e-3), 1), "unit": "pairs/s", "ms_per_replay": round(ms, 2),
+            "value_end_to_end": round(pairs / (t_create + ms * 1e-3), 1),
+            "end_to_end_note": "pairs / (symbolic phase of all meshes + one graph replay); value: replay only",
             "meshes": len(pbs), "tets": int(sum(p.mesh.n_tets for p in pbs)), "pairs": pairs,
             "dtype": "fp32-local/f64-accumulate", "plan_create_s": round(t_create, 2),
             "first_call_s": round(t_first, 2), "tuned": tune, "device_bytes": int(mem)}
@@ -402,8 +552,10 @@ def main():
     ap.add_argument("--batched-count", type=int, default=256)
     ap.add_argument("--batched-replays", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serving-count", type=int, default=48)
-    ap.add_argument("--serving-full", action="store_true", help="500 requests at 0.5x and 0.9x saturation")
+    ap.add_argument("--serving-count", type=int, default=500)
+    ap.add_argument("--serving-quick", action="store_true", help="48 requests at 0.9x saturation only")
+    ap.add_argument("--no-large", action="store_true", help="skip the 64^3 large workload")
+    ap.add_argument("--large-steps", type=int, default=1)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-strategies", action="store_true", help="skip the nocaps/overlap/inside/barycenter lines")
     ap.add_argument("--no-convergence", action="store_true", help="skip the L2-error convergence study")
@@ -455,7 +607,7 @@ def main():
     traffic, tinfo = recorded_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_integrate<double, false>", "kernel_ms": round(t_int * 1e3, 3)}
+                "kernel": "k_integrate<double, false, 0>", "kernel_ms": round(t_int * 1e3, 3)}
     if traffic is None:
         roofline["traffic_note"] = tinfo
     else:
@@ -478,19 +630,27 @@ def main():
         log("batched workload")
         batched = run_batched(P, mg, dev, args)
     P.nlfem_trim(dev.ctx)
+
+    large = None
+    if not args.no_large:
+        log("large workload")
+        large = run_large(P, mg, dev, args)
+        P.nlfem_trim(dev.ctx)
     dev.close()
 
     serving = None
     if not args.no_serving:
-        count = 500 if args.serving_full else args.serving_count
-        fractions = [0.5, 0.9] if args.serving_full else [0.9]
+        count = 48 if args.serving_quick else args.serving_count
+        fractions = [0.9] if args.serving_quick else [0.5, 0.9]
         serving = run_serving(P, mg, args, count, fractions)
 
     cpu = None
+    vs_oracle = None
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        mask = mg.outer_subset_mask(pb.mesh.n_tets, args.cpu_fraction, seed=13)
+        sub = pr["subset"]
+        mask = sub["mask"]
         region = np.array([pb.vertex_free[tt].any() for tt in pb.mesh.tets])
         n_outer = int((mask.astype(bool) & region).sum())
         log(f"oracle on {n_outer} outer tets")
@@ -500,7 +660,26 @@ def main():
         opairs = int(S["pair_counts"].sum())
         cpu = {"value": round(opairs / dt, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "sample": f"precision workload, {n_outer} of {int(region.sum())} outer tets "
-                         f"(seeded subset), {opairs} pairs in {dt:.1f} s, serial FP64 brute force"}
+                         f"(seeded subset), {opairs} pairs in {dt:.1f} s, serial FP64 brute force",
+               "host": host_cpu()}
+        # the library's results on the same subset against the oracle's: per-entry
+        # error (after the near-tie allowance) and the CG solution error
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import helpers as H
+        vs_oracle = {"subset": f"precision workload, {n_outer} outer tets", "near_ties": int(S["near_ties"])}
+        for key in ["fp64", "fp32"]:
+            e = H.value_errors(sub[key], S)
+            vs_oracle[key] = {"max_entry_err_rowscale": max(e["ff_abs"], e["fc_abs"]),
+                              "max_entry_rel_err": max(e["ff_rel"], e["fc_rel"]), "rhs_err": e["rhs"]}
+        # whole systems and CG solutions: the plain workload, against the oracle
+        vs_oracle["plain_solution"] = pr["plain_vs_oracle"](oracle, H)
+        # element keying against the element-keyed oracle
+        pbe = mg.precision_problem()
+        pbe.keying = "element"
+        Sk = oracle.problem_assemble(pbe, outer_mask=mask)
+        e = H.value_errors(sub["fp64_element"], Sk)
+        vs_oracle["fp64_element"] = {"max_entry_err_rowscale": max(e["ff_abs"], e["fc_abs"]),
+                                     "max_entry_rel_err": max(e["ff_rel"], e["fc_rel"]), "rhs_err": e["rhs"]}
 
     lat = np.array(pr["times64"]) * 1e3
     e32 = pr["e32"]
@@ -533,10 +712,13 @@ def main():
                            "integrate": round(float(np.mean(tk64[:, 3])), 3),
                            "rows": round(float(np.mean(tk64[:, 4])), 3),
                            "assemble": round(float(np.mean(tk64[:, 5])), 3)},
+        "element_keying": pr["element_keying"],
+        "errors_vs_oracle_subset": vs_oracle,
         "cg": pr["cg"],
         "strategies_fp64": pr["strategies"],
         "convergence": convergence,
         "batched": batched,
+        "large": large,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -77,16 +77,34 @@ __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned 
     atomicAdd(lo, (unsigned long long)__double2ull_rn(r * 281474976710656.0));
 }
 
+// Cut (pair, outer point) items are taken in chunks of kChunk pairs.
+constexpr int kChunk = 256;
+// LDS beyond R, T0 and the per-thread T0 words: the chunk's item prefix sums
+// (kChunk + 1 ints, padded to 8 bytes) and its pairs' local vertex positions
+// (kChunk x 4 u16), before Ve
+constexpr size_t kChunkLds = ((size_t)(kChunk + 1) * 4 + 7) / 8 * 8 + (size_t)kChunk * 8;
+
 // One workgroup of BLOCK threads integrates one outer tet.  LDS: R [4][umax]
 // and T0 [4] as two-word fixed-point sums (coarse words, then fine words),
 // each thread's own T0 words [4][2][BLOCK] (every fold of a wave targets the
 // same T0[k], so the threads sum privately and the block adds the slots up at
-// the end: the same integers, without same-address atomics), Ve [umax], and
-// the 4 outer points.  A is IntegrateArgs, or the same type in the constant
-// address space for descriptors read from a device table.  OPAQUE_TID hides
-// the thread index behind an empty asm so that a caller's loop cannot hoist
-// the per-thread addresses out of it (they would stay live across the whole
-// item loop of a persistent kernel and spill).
+// the end: the same integers, without same-address atomics), the chunk
+// tables, Ve [umax], and the 4 outer points.  A is IntegrateArgs, or the same
+// type in the constant address space for descriptors read from a device
+// table.  OPAQUE_TID hides the thread index behind an empty asm so that a
+// caller's loop cannot hoist the per-thread addresses out of it (they would
+// stay live across the whole item loop of a persistent kernel and spill).
+//
+// The pair list is walked in chunks of kChunk pairs.  First each thread takes
+// whole pairs: their inside points are folded at once and their cut points
+// counted.  Then the chunk's cut points are enumerated as (pair, point) items
+// through a prefix sum, and lane it of the workgroup takes item it: one cut
+// setup and one sample loop per lane, so a wave's lanes are all busy whatever
+// the mix of cut masks (one thread per pair looping over its cut points keeps
+// a fifth of them idle).  Items of one pair sit in neighbouring lanes; their
+// S2 sums for G_m are added across those lanes (a fixed tree over at most
+// four lanes, by item index modulo 64 and chunk, so independent of BLOCK)
+// and sent to the global accumulators once per pair and wave.
 template <typename T, int BLOCK, bool VR, int KEY, typename A, bool OPAQUE_TID = false>
 __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
@@ -96,7 +114,9 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
     unsigned long long* T0l = T0 + 4;           // fine   [4]
     unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
-    int32_t* ve = (int32_t*)(T0p + 8 * BLOCK);
+    int32_t* cs = (int32_t*)(T0p + 8 * BLOCK);  // [kChunk + 1] item prefix sums of the chunk
+    uint16_t* lvs = (uint16_t*)((char*)cs + (kChunkLds - (size_t)kChunk * 8));  // [kChunk][4]
+    int32_t* ve = (int32_t*)((char*)cs + kChunkLds);
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
     const int U = (int)(a.ve_off[oi + 1] - vb);
@@ -112,72 +132,145 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     }
     const double w = a.vol[n] * 0.25;
     const double pw = a.psi * w;
+    const int64_t ks = a.gstride;
     __syncthreads();
     const double d2 = a.delta * a.delta;
     const double fx = ldexp(1.0, a.fx_shift);
     const double gfx = ldexp(1.0, a.g_shift);
     const double wfx = ldexp(1.0, a.w_shift);
+    const int lane = t & 63;
+    // folds S0, S1 of outer point k's moments into T0 and R (lv: local
+    // positions of the inner tet's vertices in Ve, all present)
+    auto fold = [&](int k, const double* S, const int* lv, double fm) {
+        {
+            unsigned long long h, l;
+            fx_split(fm * S[0], fx, h, l);
+            T0p[(2 * k) * BLOCK + t] += h;
+            T0p[(2 * k + 1) * BLOCK + t] += l;
+        }
+        for (int j = 0; j < 4; ++j)
+            if (lv[j] < U) fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
+    };
     const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
-    for (int64_t p = p0 + t; p < p1; p += BLOCK) {
-        const int m = a.pair_m[p];
-        const uint32_t code = a.pair_cls[p];
-        const double volm = a.vol[m];
-        const bool omega = a.region[m] != 0;
-        const double fm = omega ? 1.0 : 2.0;
-        int lv[4];
-        for (int j = 0; j < 4; ++j) lv[j] = lower_bound_i32(ve, U, a.tets[4 * (int64_t)m + j]);
-        double g[10];
-        for (int i = 0; i < 10; ++i) g[i] = 0.0;
-        int n_in = 0, n_cut = 0;
-        // folds S0, S1 of outer point k's moments into T0 and R
-        auto fold = [&](int k, const double* S) {
-            {
-                unsigned long long h, l;
-                fx_split(fm * S[0], fx, h, l);
-                T0p[(2 * k) * BLOCK + t] += h;
-                T0p[(2 * k + 1) * BLOCK + t] += l;
-            }
-            for (int j = 0; j < 4; ++j)
-                if (lv[j] < U)  // always true: Ve holds every vertex of the pair list's tets
-                    fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
-        };
+    for (int64_t c0 = p0; c0 < p1; c0 += kChunk) {
+        const int nc = (int)(p1 - c0 < (int64_t)kChunk ? p1 - c0 : (int64_t)kChunk);
+        // (a) whole pairs: inside points, cut-point counts, local vertex positions
+        for (int i = t; i < kChunk; i += BLOCK) {
+            int ncut = 0;
+            if (i < nc) {
+                const int64_t p = c0 + i;
+                const int m = a.pair_m[p];
+                const uint32_t code = a.pair_cls[p];
+                int lv[4];
+                for (int j = 0; j < 4; ++j) {
+                    lv[j] = lower_bound_i32(ve, U, a.tets[4 * (int64_t)m + j]);
+                    lvs[4 * i + j] = (uint16_t)lv[j];
+                }
+                const bool omega = a.region[m] != 0;
+                int n_in = 0;
 #pragma unroll 1
-        for (int k = 0; k < 4; ++k) {
-            const int c = (int)((code >> (3 * k)) & 7u);
-            if (c == C_OUT) continue;
-            double S[15];
-            if (c == C_IN) {
-                in_moments(volm, S);
-                fold(k, S);
-                ++n_in;
-                continue;
+                for (int k = 0; k < 4; ++k) {
+                    const int c = (int)((code >> (3 * k)) & 7u);
+                    if (c == C_IN) {
+                        double S[15];
+                        in_moments(a.vol[m], S);
+                        fold(k, S, lv, omega ? 1.0 : 2.0);
+                        ++n_in;
+                    }
+                    ncut += c >= C_CUT0 ? 1 : 0;
+                }
+                if (omega && n_in) {
+                    unsigned long long* ga = a.gacc + (int64_t)m;
+                    fxs_add_global(&ga[20 * ks], &ga[21 * ks], pw * (double)n_in, wfx);
+                }
             }
-            ++n_cut;
-            const double* X = a.tetX + 12 * (int64_t)m;
-            CutGeom cg;
-            double D[5];
-            CornerGeom cr;
-            cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
-            if (a.caps) {
-                cut_mc<T, VR, KEY>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
-                                   (uint32_t)m, S, &cr);
-            } else {
-                for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
-            }
-            for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
-            fold(k, S);
-            for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
+            cs[i] = ncut;
         }
-        if (omega) {
-            // word-major accumulators: lanes with nearby m update nearby addresses
-            unsigned long long* ga = a.gacc + (int64_t)m;
-            const int64_t ks = a.gstride;
-            if (n_in) fxs_add_global(&ga[20 * ks], &ga[21 * ks], pw * (double)n_in, wfx);
-            if (n_cut)
+        __syncthreads();
+        // exclusive prefix sum of the counts (one wave; four entries per lane)
+        if (t < 64) {
+            const int v0 = cs[4 * t], v1 = cs[4 * t + 1], v2 = cs[4 * t + 2], v3 = cs[4 * t + 3];
+            const int sum = ((v0 + v1) + v2) + v3;
+            int incl = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int o = __shfl_up(incl, off, 64);
+                if (t >= off) incl += o;
+            }
+            const int ex = incl - sum;
+            cs[4 * t] = ex;
+            cs[4 * t + 1] = ex + v0;
+            cs[4 * t + 2] = ex + v0 + v1;
+            cs[4 * t + 3] = ex + v0 + v1 + v2;
+            if (t == 63) cs[kChunk] = incl;
+        }
+        __syncthreads();
+        const int n_items = cs[kChunk];
+        // (b) the chunk's cut (pair, point) items, one per lane
+        for (int ib = 0; ib < n_items; ib += BLOCK) {
+            const int it = ib + t;
+            const bool valid = it < n_items;
+            int pi = -1;
+            double g[10];
+            for (int i = 0; i < 10; ++i) g[i] = 0.0;
+            int m = 0;
+            bool omega = false;
+            if (valid) {
+                // the pair: the last chunk position whose prefix is <= it
+                int lo = 0, hi = nc;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (cs[mid] <= it) lo = mid;
+                    else hi = mid;
+                }
+                pi = lo;
+                const int64_t p = c0 + pi;
+                m = a.pair_m[p];
+                const uint32_t code = a.pair_cls[p];
+                unsigned cm = 0u;
+                for (int k = 0; k < 4; ++k) cm |= (((code >> (3 * k)) & 7u) >= (uint32_t)C_CUT0 ? 1u : 0u) << k;
+                const int k = nth_bit(cm, it - cs[pi]);
+                const double volm = a.vol[m];
+                omega = a.region[m] != 0;
+                int lv[4];
+                for (int j = 0; j < 4; ++j) lv[j] = lvs[4 * pi + j];
+                const double* X = a.tetX + 12 * (int64_t)m;
+                CutGeom cg;
+                double D[5];
+                CornerGeom cr;
+                double S[15];
+                cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
+                if (a.caps) {
+                    cut_mc<T, VR, KEY>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
+                                       (uint32_t)m, S, &cr);
+                } else {
+                    for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
+                }
+                for (int i = 0; i < 5; ++i) S[i] = D[i] + S[i];
+                fold(k, S, lv, omega ? 1.0 : 2.0);
+                for (int i = 0; i < 10; ++i) g[i] += S[5 + i];
+            }
+            // G_m: the items of one pair (at most four neighbouring lanes) summed
+            // over the lanes, then sent by the pair's first lane in the wave
+            const bool gl = valid && omega;
+#pragma unroll
+            for (int off = 1; off <= 2; off <<= 1) {
+                const int opi = __shfl_down(pi, off, 64);
+                const int og = __shfl_down(gl ? 1 : 0, off, 64);
+                const bool take = gl && lane + off < 64 && og && opi == pi;
+#pragma unroll
+                for (int i = 0; i < 10; ++i) {
+                    const double o = __shfl_down(g[i], off, 64);
+                    if (take) g[i] += o;
+                }
+            }
+            const int ppi = __shfl_up(pi, 1, 64);
+            if (gl && (lane == 0 || ppi != pi)) {
+                unsigned long long* ga = a.gacc + (int64_t)m;
                 for (int i = 0; i < 10; ++i) fxs_add_global(&ga[(2 * i) * ks], &ga[(2 * i + 1) * ks], pw * g[i], gfx);
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
     if (t < 8) {
         unsigned long long v = 0ull;
         for (int i = 0; i < BLOCK; ++i) v += T0p[t * BLOCK + i];
@@ -621,7 +714,9 @@ inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 
 }  // namespace
 
-size_t integrate_lds_bytes(int umax) { return (size_t)umax * 68 + 64 + 8 * 256 * sizeof(unsigned long long); }
+size_t integrate_lds_bytes(int umax) {
+    return (size_t)umax * 68 + 64 + 8 * 256 * sizeof(unsigned long long) + kChunkLds;
+}
 
 // kernel selection over (precision, cap sampling, keying)
 #define NLFEM_DISPATCH3(fp32, vr, key, LAUNCH)                 \

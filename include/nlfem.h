@@ -147,7 +147,11 @@ void nlfem_rule_constants(double *alpha, double *beta);
  * ball exactly in FP64 (IN / CUT(n_in) / OUT; Def. "simplex's dividing
  * strategy"), and builds the local vertex set of every outer tet, the
  * vertex-keyed lists that gather each matrix row, and the CSR pattern of the
- * free rows.  Mesh and mask are read during the call only.                  */
+ * free rows.  Mesh and mask are read during the call only.
+ * Horizons whose local vertex sets or matrix rows do not fit in LDS (in 3D
+ * about delta > 5h) keep those fixed-point sums in device memory instead
+ * (slower, the same results); the environment variable NLFEM_GLOBAL_SUMS=1
+ * forces that form for any plan (for checks).  Batches need the LDS form.  */
 nlfem_status nlfem_plan_create(nlfem_ctx *ctx, const nlfem_mesh *mesh, const nlfem_params *params,
                                nlfem_plan **plan);
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -66,6 +67,10 @@ struct nlfem_plan {
     // numeric workspace
     double *cblk = nullptr, *oblk = nullptr, *gvals = nullptr, *fc_val_int = nullptr;
     unsigned long long* gacc = nullptr;
+    // sums in global memory where LDS is too small (else nullptr)
+    bool global_r = false, global_rows = false;
+    unsigned long long* rglob = nullptr;  // [ve_total][8] R words of the integration
+    unsigned long long* racc = nullptr;   // [3 (nnz_ff + nnz_fc)] row sums
     double times[6] = {0, 0, 0, 0, 0, 0};
 
     template <typename Tp>
@@ -332,8 +337,13 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     pl->umax = (int)read_i64(c, (int64_t*)(small + 8));
     pl->ve_total = read_i64(c, pl->ve_off + no);
     const int64_t VT = pl->ve_total;
-    if (integrate_lds_bytes(pl->umax) > c->lds_max)
-        return fail(c, NLFEM_E_UNSUPPORTED, "ball vertex set of one outer tet too large for LDS");
+    // local vertex sets beyond LDS: the integration keeps its R sums in global memory
+    // (NLFEM_GLOBAL_SUMS=1 in the environment forces both global forms, for checks)
+    const char* force_global = std::getenv("NLFEM_GLOBAL_SUMS");
+    const bool force = force_global && force_global[0] == '1';
+    pl->global_r = force || integrate_lds_bytes(pl->umax) > c->lds_max;
+    if (pl->global_r && (pl->umax >= 65536 || integrate_global_lds_bytes() > c->lds_max))
+        return fail(c, NLFEM_E_UNSUPPORTED, "ball vertex set of one outer tet beyond 65535 vertices");
     if (VT >= (int64_t)0xFFFFFFFFll || 4 * K >= (int64_t)0xFFFFFFFFll)
         return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 local vertex set entries");
     ALLOC(pl->ve_ids, int32_t, VT + 1);
@@ -408,8 +418,8 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
         HIPCHK(hipStreamSynchronize(s));
         for (int64_t r = 0; r < nf; ++r) pl->max_row = (int)std::max<int64_t>(pl->max_row, a[r] + b[r]);
     }
-    if (row_assemble_lds_bytes(pl->max_row) + row_assemble_static_lds() > c->lds_max)
-        return fail(c, NLFEM_E_UNSUPPORTED, "matrix row too large for LDS accumulation");
+    // rows beyond LDS: the row assembly keeps its sums in global memory
+    pl->global_rows = force || row_assemble_lds_bytes(pl->max_row) + row_assemble_static_lds() > c->lds_max;
     ALLOC(pl->ff_col, int32_t, pl->nnz_ff + 1);
     ALLOC(pl->fc_col, int32_t, pl->nnz_fc + 1);
     ALLOC(pl->all_cols, int32_t, pl->nnz_ff + pl->nnz_fc + 1);
@@ -423,6 +433,8 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     ALLOC(pl->gacc, unsigned long long, 22 * K + 22);
     ALLOC(pl->gvals, double, 10 * K + 10);
     ALLOC(pl->fc_val_int, double, pl->nnz_fc + 1);
+    if (pl->global_r) ALLOC(pl->rglob, unsigned long long, 8 * VT + 8);
+    if (pl->global_rows) ALLOC(pl->racc, unsigned long long, 3 * (pl->nnz_ff + pl->nnz_fc) + 3);
     // fixed-point scales (each sum stays below 2^62 in units of its coarse word):
     //  T0_k, R_k(v) <= B_R = sum over the pair list of f_m S0 <= 4 max_pairs max|E|
     //    (S0 <= 2 |E_m| for one pair: subtets plus a Monte Carlo count of at most N)
@@ -503,6 +515,7 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.oblk = pl->oblk;
     a.gacc = pl->gacc;
     a.gstride = pl->K;
+    a.rglob = pl->rglob;
     return a;
 }
 
@@ -521,7 +534,8 @@ nlfem_status enqueue_rows(nlfem_ctx* c, nlfem_plan* pl, const double* g_nodal, d
     nm.ff_val = ff_val;
     nm.fc_val = fc_val ? fc_val : pl->fc_val_int;
     nm.rhs = rhs;
-    HIPCHK(launch_row_assemble(rp, nm, pl->n_free, s));
+    if (pl->racc) HIPCHK(launch_row_assemble_global(rp, nm, pl->racc, pl->n_free, s));
+    else HIPCHK(launch_row_assemble(rp, nm, pl->n_free, s));
     return NLFEM_OK;
 }
 

@@ -121,6 +121,9 @@ struct IntegrateArgs {
     double* oblk;              // [n_outer][20]: 4x4 outer-outer block, then 4 load-vector terms
     unsigned long long* gacc;  // [22][gstride] two-word sums: 10 cut S2 sums, then the inside weight
     int64_t gstride;           // = K
+    // R sums in global memory, [sum |Ve|][8] words (coarse k = 0..3, fine k = 0..3)
+    // at 8 * (ve_off + i): for local vertex sets too large for LDS; nullptr: in LDS
+    unsigned long long* rglob;
 };
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 // persistent: grid workgroups pull (mesh, outer position) items from a device
@@ -132,6 +135,8 @@ hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items,
 hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
                                   bool vr, int keying, int block, hipStream_t s);
 size_t integrate_lds_bytes(int umax);
+// LDS of the integration with its R sums in global memory (independent of umax)
+size_t integrate_global_lds_bytes();
 // adds the exact-g defect of the T_Omega_I inner integrals to the load terms
 // in oblk (tensor polynomial g of degree deg per axis, coefficients on the
 // device; whole-element cap sampling only)
@@ -193,6 +198,11 @@ hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int 
 hipError_t launch_g_finalize(int64_t K, const uint8_t* region, const int32_t* inner_cnt, const double* vol,
                              const unsigned long long* gacc, int g_shift, int w_shift, double* gvals, hipStream_t s);
 size_t row_assemble_lds_bytes(int max_row);  // dynamic part
+// rows too long for LDS: their three-word sums in global memory, 3 words per
+// nonzero of the row at 3 * (ff_row_ptr[r] + fc_row_ptr[r]) (racc), the
+// columns read from all_cols
+hipError_t launch_row_assemble_global(const RowPlan& rp, const RowNumeric& nm, unsigned long long* racc,
+                                      int64_t n_rows, hipStream_t s);
 size_t row_assemble_static_lds();
 hipError_t launch_row_assemble(const RowPlan& rp, const RowNumeric& nm, int64_t n_rows, hipStream_t s);
 

@@ -913,11 +913,12 @@ __device__ inline void region_fold(const CornerGeom* cr, int j, double vol, int 
 // ek_accept (the arithmetic of the element-keyed integration kernel).
 // Every lane runs the same sample loop (lanes of other classes in the wave
 // do not serialise it).
-// (O: the origin of the element-keyed test, the outer tet's vertex 0)
+// (cr: the cap region, used with VR; O: the origin of the element-keyed test,
+// the outer tet's vertex 0, used with element keying on whole elements)
 template <typename T, bool VR = false, int KEY = 0>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
-                              const CornerGeom* cr = nullptr, const double* O = nullptr) {
+                              const CornerGeom* cr, const double* O) {
     double pl[8];
     if constexpr (!VR && KEY == 1) {
         const EkOuter o = ek_outer(p, O, d2);

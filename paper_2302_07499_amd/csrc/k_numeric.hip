@@ -105,25 +105,36 @@ constexpr size_t kChunkLds = ((size_t)(kChunk + 1) * 4 + 7) / 8 * 8 + (size_t)kC
 // S2 sums for G_m are added across those lanes (a fixed tree over at most
 // four lanes, by item index modulo 64 and chunk, so independent of BLOCK)
 // and sent to the global accumulators once per pair and wave.
-template <typename T, int BLOCK, bool VR, int KEY, typename A, bool OPAQUE_TID = false>
+// GR: the R sums in global memory (a.rglob) and Ve read from global memory,
+// for local vertex sets too large for LDS; the same integers either way.
+template <typename T, int BLOCK, bool VR, int KEY, typename A, bool OPAQUE_TID = false, bool GR = false>
 __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned long long* smem64,
                                                 double (*P)[3]) {
-    const int umax = a.umax;
-    unsigned long long* R = smem64;             // coarse [4][umax]
-    unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax]
+    const int umax = GR ? 0 : a.umax;           // LDS words per R row
+    unsigned long long* R = smem64;             // coarse [4][umax] (LDS mode)
+    unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax] (LDS mode)
     unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
     unsigned long long* T0l = T0 + 4;           // fine   [4]
     unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
     int32_t* cs = (int32_t*)(T0p + 8 * BLOCK);  // [kChunk + 1] item prefix sums of the chunk
     uint16_t* lvs = (uint16_t*)((char*)cs + (kChunkLds - (size_t)kChunk * 8));  // [kChunk][4]
-    int32_t* ve = (int32_t*)((char*)cs + kChunkLds);
+    int32_t* ve_lds = (int32_t*)((char*)cs + kChunkLds);
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
     const int U = (int)(a.ve_off[oi + 1] - vb);
+    unsigned long long* rg = GR ? a.rglob + 8 * vb : nullptr;  // [U][8] (global mode)
+    const int32_t* ve = GR ? a.ve_ids + vb : ve_lds;
+    // coarse and fine word of R_k at local vertex position i
+    auto rco = [&](int k, int i) { return GR ? rg + 8 * i + k : R + k * umax + i; };
+    auto rfi = [&](int k, int i) { return GR ? rg + 8 * i + 4 + k : Rl + k * umax + i; };
     int t = threadIdx.x;
     if constexpr (OPAQUE_TID) asm volatile("" : "+v"(t));
-    for (int i = t; i < U; i += BLOCK) ve[i] = a.ve_ids[vb + i];
-    for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
+    if constexpr (GR) {
+        for (int i = t; i < 8 * U; i += BLOCK) rg[i] = 0ull;
+    } else {
+        for (int i = t; i < U; i += BLOCK) ve_lds[i] = a.ve_ids[vb + i];
+        for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
+    }
     for (int i = 0; i < 8; ++i) T0p[i * BLOCK + t] = 0ull;
     if (t < 4) {
         double Xn[12];
@@ -133,6 +144,8 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     const double w = a.vol[n] * 0.25;
     const double pw = a.psi * w;
     const int64_t ks = a.gstride;
+    // the outer tet's vertex 0: origin of the element-keyed sample test
+    const double* Xo = a.tetX + 12 * (int64_t)n;
     __syncthreads();
     const double d2 = a.delta * a.delta;
     const double fx = ldexp(1.0, a.fx_shift);
@@ -149,7 +162,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             T0p[(2 * k + 1) * BLOCK + t] += l;
         }
         for (int j = 0; j < 4; ++j)
-            if (lv[j] < U) fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
+            if (lv[j] < U) fx_add(rco(k, lv[j]), rfi(k, lv[j]), fm * S[1 + j], fx);
     };
     const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
     for (int64_t c0 = p0; c0 < p1; c0 += kChunk) {
@@ -241,7 +254,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
                 cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
                 if (a.caps) {
                     cut_mc<T, VR, KEY>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
-                                       (uint32_t)m, S, &cr);
+                                       (uint32_t)m, S, &cr, Xo);
                 } else {
                     for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
                 }
@@ -284,7 +297,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     for (int r = t; r < 4 * U; r += BLOCK) {
         const int i = r >> 2, j = r & 3;
         double cR = 0.0;
-        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
+        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(*rco(k, i), *rfi(k, i), sh);
         cb[r] = -(pw * cR);
     }
     // outer block and load vector (sum_k w c_kj f(p_k))
@@ -519,6 +532,15 @@ __device__ __forceinline__ void integrate_any(const A& a, int64_t oi, unsigned l
     else integrate_outer<T, BLOCK, VR, KEY, A, OPAQUE_TID>(a, oi, smem64, P);
 }
 
+// Local vertex sets beyond LDS: the R sums in global memory, one (pair, cut
+// point) item per lane for either keying.
+template <typename T, bool VR, int KEY>
+__global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate_global(IntegrateArgs a) {
+    extern __shared__ unsigned long long smem64[];
+    __shared__ double P[4][3];
+    integrate_outer<T, 256, VR, KEY, IntegrateArgs, false, true>(a, (int64_t)blockIdx.x, smem64, P);
+}
+
 // waves per SIMD the register cap is set for: the shared-sample loop keeps
 // four outer points' sample tests and sums live and takes the registers of 2
 // (form = 2 KEY + VR: one argument, so that it passes through __launch_bounds__)
@@ -717,6 +739,7 @@ inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 
 size_t integrate_lds_bytes(int umax) {
     return (size_t)umax * 68 + 64 + 8 * 256 * sizeof(unsigned long long) + kChunkLds;
 }
+size_t integrate_global_lds_bytes() { return 64 + 8 * 256 * sizeof(unsigned long long) + kChunkLds; }
 
 // kernel selection over (precision, cap sampling, keying)
 #define NLFEM_DISPATCH3(fp32, vr, key, LAUNCH)                 \
@@ -742,8 +765,15 @@ size_t integrate_lds_bytes(int umax) {
 
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;
-    size_t sh = integrate_lds_bytes(a.umax);
     const unsigned g = (unsigned)a.n_outer;
+    if (a.rglob) {
+        const size_t sh = integrate_global_lds_bytes();
+#define L_GLB(T, VR, KEY) k_integrate_global<T, VR, KEY><<<g, 256, sh, s>>>(a)
+        NLFEM_DISPATCH3(fp32, a.vr, a.keying, L_GLB);
+#undef L_GLB
+        return hipGetLastError();
+    }
+    size_t sh = integrate_lds_bytes(a.umax);
 #define L_ONE(T, VR, KEY) k_integrate<T, VR, KEY><<<g, 256, sh, s>>>(a)
     NLFEM_DISPATCH3(fp32, a.vr, a.keying, L_ONE);
 #undef L_ONE

@@ -330,19 +330,23 @@ __global__ void k_g_finalize(int64_t K, const uint8_t* region, const int32_t* in
         gvals[10 * e + i] = fxs_value(a[2 * i * K], a[(2 * i + 1) * K], g_shift) + win * s2[i];
 }
 
-// One block per free row.
-__global__ __launch_bounds__(256) void k_row_assemble(RowPlan rp, RowNumeric nm) {
+// One block per free row.  GLOBAL: the row's three-word sums in global
+// memory (racc, at 3 ab with stride L) and its columns read from all_cols,
+// for rows too long for LDS; the same integers either way.
+template <bool GLOBAL>
+__global__ __launch_bounds__(256) void k_row_assemble(RowPlan rp, RowNumeric nm, unsigned long long* racc) {
     extern __shared__ unsigned long long sm[];
     const int64_t r = blockIdx.x;
     const int t = threadIdx.x;
     const int32_t u = rp.free_to_vertex[r];
     const int64_t ab = rp.ff_row_ptr[r] + rp.fc_row_ptr[r];
     const int L = (int)(rp.ff_row_ptr[r + 1] + rp.fc_row_ptr[r + 1] - ab);
-    const int st = rp.max_row;  // word stride of the accumulators
-    unsigned long long* acc = sm;
-    int32_t* cols = (int32_t*)(sm + 3 * st);
+    const int st = GLOBAL ? L : rp.max_row;  // word stride of the accumulators
+    unsigned long long* acc = GLOBAL ? racc + 3 * ab : sm;
+    int32_t* cols_lds = (int32_t*)(sm + 3 * st);
+    const int32_t* cols = GLOBAL ? rp.all_cols + ab : cols_lds;
     for (int i = t; i < L; i += 256) {
-        cols[i] = rp.all_cols[ab + i];
+        if constexpr (!GLOBAL) cols_lds[i] = rp.all_cols[ab + i];
         acc[i] = 0ull;
         acc[st + i] = 0ull;
         acc[2 * st + i] = 0ull;
@@ -501,7 +505,14 @@ size_t row_assemble_static_lds() { return 256 * (sizeof(int) + sizeof(double)) +
 
 hipError_t launch_row_assemble(const RowPlan& rp, const RowNumeric& nm, int64_t n_rows, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
-    k_row_assemble<<<(unsigned)n_rows, 256, row_assemble_lds_bytes(rp.max_row), s>>>(rp, nm);
+    k_row_assemble<false><<<(unsigned)n_rows, 256, row_assemble_lds_bytes(rp.max_row), s>>>(rp, nm, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_assemble_global(const RowPlan& rp, const RowNumeric& nm, unsigned long long* racc,
+                                      int64_t n_rows, hipStream_t s) {
+    if (n_rows <= 0) return hipSuccess;
+    k_row_assemble<true><<<(unsigned)n_rows, 256, 0, s>>>(rp, nm, racc);
     return hipGetLastError();
 }
 

@@ -322,7 +322,10 @@ nlfem_status nlfem_plan_timings(const nlfem_plan *plan, double times[6]);
  * vectors stay on the device for the whole request.  Queued requests are
  * admitted in arrival order, first fit, when a slot is free and their
  * estimated footprint fits in the pool next to the running ones (a request
- * passed over 16 times holds the others back until it fits).  A request that
+ * passed over 16 times holds the others back until it fits).  The estimate is
+ * a geometric model of the plan's sizes, scaled down by the largest measured
+ * peak / model ratio of finished requests with a similar model value (plus
+ * 15 %), never above the model.  A request that
  * runs out of pool memory is re-queued with its measured need, and fails with
  * NLFEM_E_OOM only when it does not fit alone.  Requests overlap on the
  * device (continuous batching); each request's solution is bitwise the one it

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <thread>
 
@@ -41,7 +42,10 @@ struct Request {
     double rtol = 1e-10;
     int32_t max_iter = 0;
     // scheduling
-    size_t est = 0;
+    size_t est = 0;      // admission estimate (pool bytes)
+    size_t est_raw = 0;  // the geometric estimate before calibration
+    int est_class = 0;   // calibration class: quarter-octave of est_raw
+    bool measured = false;  // est comes from a measured need (re-queue), not the model
     int skipped = 0;
     Clock::time_point t_arrival, t_admit, t_plan, t_assemble, t_done;
     double queue_s = 0, plan_s = 0, assemble_s = 0, solve_s = 0;
@@ -119,6 +123,9 @@ struct nlfem_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> queue;
+    // calibration of the footprint model: per class of raw estimate, the
+    // largest measured peak / raw estimate of a finished request
+    std::map<int, double> ratio;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     uint64_t next_ticket = 1;
     bool stopping = false;
@@ -130,11 +137,30 @@ struct nlfem_server {
 
 namespace {
 
+// Admission estimate: the geometric model scaled by the largest peak / model
+// ratio measured so far on requests of the same class (raw estimates within a
+// quarter octave), with a 15 % margin; the model alone until a request of the
+// class has finished, and never above it (an underestimate that runs out of
+// pool memory is re-queued with its measured need).
+constexpr double kEstMargin = 1.15;
+
+int est_class_of(size_t est_raw) { return (int)std::floor(4.0 * std::log2((double)std::max<size_t>(est_raw, 1))); }
+
+void calibrate(nlfem_server* s, Request* r) {
+    if (r->measured) return;
+    const auto it = s->ratio.find(r->est_class);
+    double f = 1.0;
+    if (it != s->ratio.end()) f = std::min(1.0, it->second * kEstMargin);
+    r->est = std::min((size_t)((double)r->est_raw * f), s->pool.size);
+    r->info.est_bytes = r->est;
+}
+
 // picks the next request that fits (first fit in arrival order); a head that
 // has been passed over 16 times blocks the others until it fits
 Request* pick(nlfem_server* s) {
     for (size_t i = 0; i < s->queue.size(); ++i) {
         Request* r = s->queue[i];
+        calibrate(s, r);
         if (s->reserved + r->est <= s->pool.size) {
             s->queue.erase(s->queue.begin() + (long)i);
             return r;
@@ -262,6 +288,7 @@ void worker(nlfem_server* s, int slot_id) {
                 const size_t need = std::max<size_t>(2 * r->est, slot.ctx->peak + slot.ctx->peak / 2);
                 r->est = std::min(need, s->pool.size);
                 r->info.est_bytes = r->est;
+                r->measured = true;
                 r->info.state = 0;
                 r->skipped = 0;
                 s->queue.push_front(r);
@@ -276,6 +303,10 @@ void worker(nlfem_server* s, int slot_id) {
                     r->info.solve_s = seconds_between(r->t_assemble, t_end);
                 }
                 r->info.latency_s = seconds_between(r->t_arrival, t_end);
+                if (st == NLFEM_OK && r->est_raw > 0) {
+                    double& q = s->ratio[r->est_class];
+                    q = std::max(q, (double)r->info.peak_bytes / (double)r->est_raw);
+                }
                 if (st == NLFEM_OK) ++s->n_done;
                 else {
                     ++s->n_failed;
@@ -373,7 +404,9 @@ nlfem_status nlfem_server_submit(nlfem_server* s, const nlfem_mesh* mesh, const 
         r->rtol = solve->rtol;
         r->max_iter = solve->max_iter;
     }
-    r->est = std::min(estimate_footprint(*r), s->pool.size);
+    r->est_raw = estimate_footprint(*r);
+    r->est_class = est_class_of(r->est_raw);
+    r->est = std::min(r->est_raw, s->pool.size);
     r->info.est_bytes = r->est;
     {
         std::lock_guard<std::mutex> lk(s->mu);

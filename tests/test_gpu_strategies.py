@@ -15,7 +15,7 @@ import helpers as H
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
-FP32_TOL = 1e-5
+FP32_TOL = 1e-6  # the form reaches about 1e-7 of the row scale on outer subsets (float subtet moments)
 STRATS = ["nocaps", "overlap", "inside", "barycenter"]
 
 

@@ -628,14 +628,6 @@ struct McSums {
         B11 += (uint64_t)x1 * x1; B12 += (uint64_t)x1 * x2; B13 += (uint64_t)x1 * x3;
         B22 += (uint64_t)x2 * x2; B23 += (uint64_t)x2 * x3; B33 += (uint64_t)x3 * x3;
     }
-    // sample L with its acceptance decided by the caller
-    __device__ __forceinline__ void take(bool acc, const uint32_t* L) {
-        const uint32_t x1 = acc ? L[1] : 0u, x2 = acc ? L[2] : 0u, x3 = acc ? L[3] : 0u;
-        icnt += acc ? 1u : 0u;
-        ia1 += x1; ia2 += x2; ia3 += x3;
-        B11 += (uint64_t)x1 * L[1]; B12 += (uint64_t)x1 * L[2]; B13 += (uint64_t)x1 * L[3];
-        B22 += (uint64_t)x2 * L[2]; B23 += (uint64_t)x2 * L[3]; B33 += (uint64_t)x3 * L[3];
-    }
     // moments of the accepted samples' coordinates, times scale, to S[15]
     template <typename T>
     __device__ __forceinline__ void finish(double scale, double* S) const {
@@ -672,131 +664,6 @@ struct McSums {
         S[0] = scale * dc; S[1] = scale * d0; S[2] = scale * d1; S[3] = scale * d2s; S[4] = scale * d3;
         S[5] = scale * c00; S[6] = scale * c01; S[7] = scale * c02; S[8] = scale * c03; S[9] = scale * c11;
         S[10] = scale * c12; S[11] = scale * c13; S[12] = scale * c22; S[13] = scale * c23; S[14] = scale * c33;
-    }
-};
-
-// Sample test of element keying.  The samples of E_m are shared by all outer
-// points of an outer tet, so each sample point is formed once, relative to an
-// origin O that the outer tet fixes (its vertex 0):
-//   Y = (X_0 - O) + sum_{l=1..3} L_l F_l,  F_l = (X_l - X_0) 2^-21  (= y - O),
-// and outer point p tests |Y - (p - O)|^2 < delta^2 as
-//   Y.Y - Y.(2 (p - O)) < delta^2 - |p - O|^2,
-// whose right-hand factors depend on the outer point only (EkOuter: uniform
-// over a workgroup).  The U_I planes keep the prescaled lambda_0-eliminated
-// form of whole_frame.  Every term is at most a few tens of times
-// max_l |X_l - p|^2, so the rounding stays far below the margin at which
-// another evaluation order of the same test could decide otherwise.
-struct EkOuter {
-    double P2x, P2y, P2z, rho;  // 2 (p - O), delta^2 - |p - O|^2
-};
-
-__device__ __forceinline__ EkOuter ek_outer(const double* p, const double* O, double d2) {
-    const double vx = p[0] - O[0], vy = p[1] - O[1], vz = p[2] - O[2];
-    return EkOuter{2.0 * vx, 2.0 * vy, 2.0 * vz, d2 - ((vx * vx + vy * vy) + vz * vz)};
-}
-
-// U_I planes of one cut point: pl[0] + sum_l L_l pl[l] >= 0 and pl[4] + ... >= 0 means in U_I
-struct EkPlanes {
-    double pl[8];
-};
-
-__device__ __forceinline__ void ek_planes(const CutGeom& g, EkPlanes& e) {
-    const double u = 1.0 / 2097152.0;
-    e.pl[0] = g.c0[0]; e.pl[1] = (g.c0[1] - g.c0[0]) * u; e.pl[2] = (g.c0[2] - g.c0[0]) * u;
-    e.pl[3] = (g.c0[3] - g.c0[0]) * u;
-    e.pl[4] = g.c1[0]; e.pl[5] = (g.c1[1] - g.c1[0]) * u; e.pl[6] = (g.c1[2] - g.c1[0]) * u;
-    e.pl[7] = (g.c1[3] - g.c1[0]) * u;
-}
-
-// shared part of one sample: Y = y - O and Y.Y
-struct EkSample {
-    double l1, l2, l3, Yx, Yy, Yz, Y2;
-};
-
-struct EkFrame {
-    double x0, y0, z0;  // X_0 - O
-    double f1x, f1y, f1z, f2x, f2y, f2z, f3x, f3y, f3z;
-    __device__ __forceinline__ EkFrame(const double* X, const double* O) {
-        const double u = 1.0 / 2097152.0;
-        x0 = X[0] - O[0]; y0 = X[1] - O[1]; z0 = X[2] - O[2];
-        f1x = (X[3] - X[0]) * u; f1y = (X[4] - X[1]) * u; f1z = (X[5] - X[2]) * u;
-        f2x = (X[6] - X[0]) * u; f2y = (X[7] - X[1]) * u; f2z = (X[8] - X[2]) * u;
-        f3x = (X[9] - X[0]) * u; f3y = (X[10] - X[1]) * u; f3z = (X[11] - X[2]) * u;
-    }
-    __device__ __forceinline__ EkSample at(const uint32_t* L) const {
-        EkSample y;
-        y.l1 = (double)L[1];
-        y.l2 = (double)L[2];
-        y.l3 = (double)L[3];
-        y.Yx = fma(y.l3, f3x, fma(y.l2, f2x, fma(y.l1, f1x, x0)));
-        y.Yy = fma(y.l3, f3y, fma(y.l2, f2y, fma(y.l1, f1y, y0)));
-        y.Yz = fma(y.l3, f3z, fma(y.l2, f2z, fma(y.l1, f1z, z0)));
-        y.Y2 = fma(y.Yz, y.Yz, fma(y.Yy, y.Yy, y.Yx * y.Yx));
-        return y;
-    }
-};
-
-// accepted by outer point o: inside the open ball and not in U_I
-__device__ __forceinline__ bool ek_accept(const EkOuter& o, const EkPlanes& e, const EkSample& y) {
-    const double t = fma(y.Yz, o.P2z, fma(y.Yy, o.P2y, y.Yx * o.P2x));
-    const double h0 = fma(y.l3, e.pl[3], fma(y.l2, e.pl[2], fma(y.l1, e.pl[1], e.pl[0])));
-    const double h1 = fma(y.l3, e.pl[7], fma(y.l2, e.pl[6], fma(y.l1, e.pl[5], e.pl[4])));
-    // all three tests evaluated (no short circuit: no branches in the sample loop)
-    const unsigned ball = (y.Y2 - t) < o.rho ? 1u : 0u;
-    const unsigned in0 = h0 >= 0.0 ? 1u : 0u, in1 = h1 >= 0.0 ? 1u : 0u;
-    return (ball & ~(in0 & in1) & 1u) != 0u;
-}
-
-// Monte Carlo sums of the element-keyed loop.  An outer tet's cut points need
-// their own S0 and S1 (they enter T0_k and R_k with the point's rule row),
-// but S2 only summed over the points (it enters G_m with the common weight
-// psi f_m w): per point the count and sum L_j (32 bits each), and over the
-// points the sums of a(s) L_i L_j, a(s) = the number of points accepting
-// sample s (64 bits; at most 4 N 2^42 < 2^55).  All integers, exact.
-struct EkFirst {
-    uint32_t cnt = 0, a1 = 0, a2 = 0, a3 = 0;
-    __device__ __forceinline__ uint32_t take(bool acc, const uint32_t* L) {
-        const uint32_t one = acc ? 1u : 0u;
-        cnt += one;
-        a1 += acc ? L[1] : 0u;
-        a2 += acc ? L[2] : 0u;
-        a3 += acc ? L[3] : 0u;
-        return one;
-    }
-    // S0, S1 of this point (S[0..4]) at weight scale
-    __device__ __forceinline__ void moments(double scale, double* S) const {
-        const double u = 1.0 / 2097152.0;
-        const uint32_t a0 = cnt * 2097152u - a1 - a2 - a3;  // exact: below 2^32 for N <= 2047
-        S[0] = scale * (double)cnt;
-        S[1] = scale * ((double)a0 * u);
-        S[2] = scale * ((double)a1 * u);
-        S[3] = scale * ((double)a2 * u);
-        S[4] = scale * ((double)a3 * u);
-    }
-};
-
-struct EkSecond {
-    uint64_t B11 = 0, B12 = 0, B13 = 0, B22 = 0, B23 = 0, B33 = 0;
-    __device__ __forceinline__ void take(uint32_t a, const uint32_t* L) {
-        // a <= 4 and L < 2^21: 24-bit products
-        const uint32_t x1 = __umul24(a, L[1]), x2 = __umul24(a, L[2]), x3 = __umul24(a, L[3]);
-        B11 += (uint64_t)x1 * L[1]; B12 += (uint64_t)x1 * L[2]; B13 += (uint64_t)x1 * L[3];
-        B22 += (uint64_t)x2 * L[2]; B23 += (uint64_t)x2 * L[3]; B33 += (uint64_t)x3 * L[3];
-    }
-    // the ten second moments summed over the points (S2 upper triangle,
-    // 00,01,02,03,11,12,13,22,23,33) at weight scale; A = sum over the points
-    // of their count and sum L_j (the L_0 terms follow from sum_l L_l = 2^21)
-    __device__ __forceinline__ void moments(double scale, uint64_t cnt, uint64_t A1, uint64_t A2, uint64_t A3,
-                                            double* G) const {
-        const double u2 = 1.0 / 4398046511104.0;  // 2^-42
-        const uint64_t TT = 2097152ull;
-        const uint64_t A0 = cnt * TT - A1 - A2 - A3;
-        const uint64_t B01 = A1 * TT - B11 - B12 - B13, B02 = A2 * TT - B12 - B22 - B23,
-                       B03 = A3 * TT - B13 - B23 - B33;
-        const uint64_t B00 = A0 * TT - B01 - B02 - B03;
-        const uint64_t b[10] = {B00, B01, B02, B03, B11, B12, B13, B22, B23, B33};
-#pragma unroll
-        for (int i = 0; i < 10; ++i) G[i] = scale * ((double)b[i] * u2);
     }
 };
 
@@ -909,37 +776,15 @@ __device__ inline void region_fold(const CornerGeom* cr, int j, double vol, int 
 // takes the samples floor(j N / n) <= s < floor((j + 1) N / n), N_j of them
 // (N >= 3), with weight |T_j| / N_j and no U_I test, and its moments in the
 // sub-tet's coordinates mu map to E_m's as lambda = sum_r mu_r row(T_j, r).
-// Element keying on the whole element uses the shared-sample test of
-// ek_accept (the arithmetic of the element-keyed integration kernel).
 // Every lane runs the same sample loop (lanes of other classes in the wave
 // do not serialise it).
-// (cr: the cap region, used with VR; O: the origin of the element-keyed test,
-// the outer tet's vertex 0, used with element keying on whole elements)
+// (cr: the cap region, used with VR)
 template <typename T, bool VR = false, int KEY = 0>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
-                              const CornerGeom* cr, const double* O) {
+                              const CornerGeom* cr) {
     double pl[8];
-    if constexpr (!VR && KEY == 1) {
-        const EkOuter o = ek_outer(p, O, d2);
-        EkPlanes e;
-        ek_planes(g, e);
-        const EkFrame fr(X, O);
-        McSums acc;
-        for (int s = 0; s < N; s += 2) {
-            uint32_t w[4];
-            mc_philox<KEY>(q, m, (uint32_t)(s >> 1), key0, key1, w);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (s + h < N) {
-                    uint32_t L[4];
-                    lambda_u(w, h, L);
-                    acc.take(ek_accept(o, e, fr.at(L)), L);
-                }
-            }
-        }
-        acc.finish<T>(vol / (double)N, S);
-    } else if constexpr (!VR) {
+    if constexpr (!VR) {
         const BallForm bf = whole_frame(X, p, g, pl);
         McSums acc;
         for (int s = 0; s < N; s += 2) {
@@ -998,8 +843,7 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
 // whole-pair moments (the sum of the pieces), as the oracle reports them
 template <typename T, bool VR = false, int KEY = 0>
 __device__ inline void pair_moments(const double* X, double vol, const double* p, double d2, int code, int N,
-                                    bool caps, uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
-                                    const double* O) {
+                                    bool caps, uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S) {
     if (code == C_IN) {
         in_moments(vol, S);
         return;
@@ -1011,7 +855,7 @@ __device__ inline void pair_moments(const double* X, double vol, const double* p
     CornerGeom cr;
     cut_det<T>(X, vol, p, d2, g, D, G, VR ? &cr : nullptr);
     if (caps) {
-        cut_mc<T, VR, KEY>(X, vol, p, d2, g, N, key0, key1, q, m, S, &cr, O);
+        cut_mc<T, VR, KEY>(X, vol, p, d2, g, N, key0, key1, q, m, S, &cr);
     } else {
 #pragma unroll
         for (int i = 0; i < 15; ++i) S[i] = 0.0;
@@ -1066,7 +910,7 @@ __device__ __forceinline__ double g_defect_at(const double* X, const double* lam
 template <int DEG, typename CP>
 __device__ inline double pair_g_defect(const double* X, double vol, const double* p, double d2, int code, int N,
                                        bool caps, int keying, uint32_t key0, uint32_t key1, uint32_t q, uint32_t m,
-                                       const double* gv, CP coef, const double* O) {
+                                       const double* gv, CP coef) {
     double acc = 0.0;
     if (code == C_IN) {
         const double w = vol * 0.25;
@@ -1108,26 +952,13 @@ __device__ inline double pair_g_defect(const double* X, double vol, const double
             sum += g_defect_at<DEG>(X, lam, gv, coef);
         }
     };
-    if (keying) {
-        const EkOuter o = ek_outer(p, O, d2);
-        EkPlanes e;
-        ek_planes(g, e);
-        const EkFrame fr(X, O);
-        for (int s = 0; s < N; s += 2) {
-            uint32_t w[4];
-            mc_philox<1>(q, m, (uint32_t)(s >> 1), key0, key1, w);
-            for (int h = 0; h < 2 && s + h < N; ++h) {
-                uint32_t L[4];
-                lambda_u(w, h, L);
-                take(ek_accept(o, e, fr.at(L)), L);
-            }
-        }
-    } else {
+    {
         double pl[8];
         const BallForm bf = whole_frame(X, p, g, pl);
         for (int s = 0; s < N; s += 2) {
             uint32_t w[4];
-            mc_philox<0>(q, m, (uint32_t)(s >> 1), key0, key1, w);
+            if (keying) mc_philox<1>(q, m, (uint32_t)(s >> 1), key0, key1, w);
+            else mc_philox<0>(q, m, (uint32_t)(s >> 1), key0, key1, w);
             for (int h = 0; h < 2 && s + h < N; ++h) {
                 uint32_t L[4];
                 lambda_u(w, h, L);

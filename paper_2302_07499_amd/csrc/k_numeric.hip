@@ -21,9 +21,6 @@
 #ifndef NLFEM_INTEGRATE_WAVES
 #define NLFEM_INTEGRATE_WAVES 3  // minimum waves per SIMD requested for k_integrate (register cap)
 #endif
-#ifndef NLFEM_INTEGRATE_EK_WAVES
-#define NLFEM_INTEGRATE_EK_WAVES 2  // the same for the element-keyed form
-#endif
 
 namespace nlfem {
 
@@ -144,8 +141,6 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     const double w = a.vol[n] * 0.25;
     const double pw = a.psi * w;
     const int64_t ks = a.gstride;
-    // the outer tet's vertex 0: origin of the element-keyed sample test
-    const double* Xo = a.tetX + 12 * (int64_t)n;
     __syncthreads();
     const double d2 = a.delta * a.delta;
     const double fx = ldexp(1.0, a.fx_shift);
@@ -240,7 +235,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
                 m = a.pair_m[p];
                 const uint32_t code = a.pair_cls[p];
                 unsigned cm = 0u;
-                for (int k = 0; k < 4; ++k) cm |= (((code >> (3 * k)) & 7u) >= (uint32_t)C_CUT0 ? 1u : 0u) << k;
+                for (int kk = 0; kk < 4; ++kk) cm |= (((code >> (3 * kk)) & 7u) >= (uint32_t)C_CUT0 ? 1u : 0u) << kk;
                 const int k = nth_bit(cm, it - cs[pi]);
                 const double volm = a.vol[m];
                 omega = a.region[m] != 0;
@@ -254,7 +249,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
                 cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
                 if (a.caps) {
                     cut_mc<T, VR, KEY>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
-                                       (uint32_t)m, S, &cr, Xo);
+                                       (uint32_t)m, S, &cr);
                 } else {
                     for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
                 }
@@ -316,220 +311,9 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     }
 }
 
-// a value the same in every lane, held in scalar registers
-__device__ __forceinline__ double uniform_f64(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Element keying (whole-element cap sampling): the samples of E_m are the
-// same points for every outer point, so a thread runs ONE sample loop per
-// (outer tet, inner tet) pair and tests each sample against every cut outer
-// point of it (ek_accept), instead of one loop per cut point.  The Philox
-// call, the spacings and the sample point are shared; per cut point remain
-// three FMAs of the ball test, the U_I planes and the integer sums.  The
-// deterministic part of each cut point (T_I) is folded before the loop, its
-// Monte Carlo moments after it; LDS layout and reductions as integrate_outer.
-template <typename T, int BLOCK, typename A, bool OPAQUE_TID = false>
-__device__ __forceinline__ void integrate_outer_ek(const A& a, int64_t oi, unsigned long long* smem64,
-                                                   double (*P)[3]) {
-    const int umax = a.umax;
-    unsigned long long* R = smem64;             // coarse [4][umax]
-    unsigned long long* Rl = R + 4 * umax;      // fine   [4][umax]
-    unsigned long long* T0 = Rl + 4 * umax;     // coarse [4]
-    unsigned long long* T0l = T0 + 4;           // fine   [4]
-    unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
-    int32_t* ve = (int32_t*)(T0p + 8 * BLOCK);
-    const int n = a.outer_ids[oi];
-    const int64_t vb = a.ve_off[oi];
-    const int U = (int)(a.ve_off[oi + 1] - vb);
-    int t = threadIdx.x;
-    if constexpr (OPAQUE_TID) asm volatile("" : "+v"(t));
-    for (int i = t; i < U; i += BLOCK) ve[i] = a.ve_ids[vb + i];
-    for (int i = t; i < 8 * umax; i += BLOCK) R[i] = 0ull;
-    for (int i = 0; i < 8; ++i) T0p[i * BLOCK + t] = 0ull;
-    if (t < 4) {
-        double Xn[12];
-        for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
-        outer_point(Xn, t, P[t]);
-    }
-    const double w = a.vol[n] * 0.25;
-    const double pw = a.psi * w;
-    __syncthreads();
-    const double d2 = a.delta * a.delta;
-    const double fx = ldexp(1.0, a.fx_shift);
-    const double gfx = ldexp(1.0, a.g_shift);
-    const double wfx = ldexp(1.0, a.w_shift);
-    const int N = a.mc_samples;
-    // the workgroup's frame of the shared sample test (ek_outer): origin O =
-    // vertex 0 of the outer tet, and per outer point 2 (p_k - O) and
-    // delta^2 - |p_k - O|^2, all uniform over the workgroup
-    double O[3];
-    EkOuter o0, o1, o2, o3;
-    {
-        double Xn[12];
-        for (int i = 0; i < 12; ++i) Xn[i] = a.tetX[12 * (int64_t)n + i];
-        for (int i = 0; i < 3; ++i) O[i] = uniform_f64(Xn[i]);
-        EkOuter* ok[4] = {&o0, &o1, &o2, &o3};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double pk[3];
-            outer_point(Xn, k, pk);
-            const EkOuter e = ek_outer(pk, O, d2);
-            *ok[k] = EkOuter{uniform_f64(e.P2x), uniform_f64(e.P2y), uniform_f64(e.P2z), uniform_f64(e.rho)};
-        }
-    }
-    const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
-    const int64_t ks = a.gstride;
-    for (int64_t p = p0 + t; p < p1; p += BLOCK) {
-        const int m = a.pair_m[p];
-        const uint32_t code = a.pair_cls[p];
-        const double* X = a.tetX + 12 * (int64_t)m;
-        unsigned long long* ga = a.gacc + (int64_t)m;  // word-major G accumulators of E_m
-        // local positions of E_m's vertices in Ve, and the fold of S0, S1 of
-        // outer point k into T0 and R
-        int lv[4];
-        for (int j = 0; j < 4; ++j) lv[j] = lower_bound_i32(ve, U, a.tets[4 * (int64_t)m + j]);
-        auto fold = [&](int k, const double* S) {
-            const double fm = a.region[m] != 0 ? 1.0 : 2.0;
-            {
-                unsigned long long h, l;
-                fx_split(fm * S[0], fx, h, l);
-                T0p[(2 * k) * BLOCK + t] += h;
-                T0p[(2 * k + 1) * BLOCK + t] += l;
-            }
-            for (int j = 0; j < 4; ++j)
-                if (lv[j] < U) fx_add(&R[k * umax + lv[j]], &Rl[k * umax + lv[j]], fm * S[1 + j], fx);
-        };
-        // T_Omega inner elements: psi w f_m S2 into G_m (the T_I part before the
-        // sample loop, the Monte Carlo part after it: nothing held across it)
-        auto add_g = [&](const double* g) {
-            for (int i = 0; i < 10; ++i) fxs_add_global(&ga[(2 * i) * ks], &ga[(2 * i + 1) * ks], pw * g[i], gfx);
-        };
-        EkPlanes e0, e1, e2, e3;
-        unsigned cut = 0u;
-        {
-            const double volm = a.vol[m];
-            double g[10];
-            for (int i = 0; i < 10; ++i) g[i] = 0.0;
-            int n_in = 0, n_cut = 0;
-#pragma unroll 1
-            for (int k = 0; k < 4; ++k) {
-                const int c = (int)((code >> (3 * k)) & 7u);
-                if (c == C_OUT) continue;
-                if (c == C_IN) {
-                    double S[15];
-                    in_moments(volm, S);
-                    fold(k, S);
-                    ++n_in;
-                    continue;
-                }
-                ++n_cut;
-                CutGeom cg;
-                double D[5];
-                cut_det<T>(X, volm, P[k], d2, cg, D, g);
-                fold(k, D);
-                if (a.caps) {
-                    cut |= 1u << k;
-                    EkPlanes e;
-                    ek_planes(cg, e);
-                    if (k == 0) e0 = e;
-                    else if (k == 1) e1 = e;
-                    else if (k == 2) e2 = e;
-                    else e3 = e;
-                }
-            }
-            if (a.region[m] != 0) {
-                if (n_in) fxs_add_global(&ga[20 * ks], &ga[21 * ks], pw * (double)n_in, wfx);
-                if (n_cut) add_g(g);
-            }
-        }
-        if (cut) {
-            EkFirst f0, f1, f2, f3;
-            EkSecond sec;
-            {
-                const EkFrame fr(X, O);
-                for (int s = 0; s < N; s += 2) {
-                    uint32_t wd[4];
-                    mc_philox<1>(0u, (uint32_t)m, (uint32_t)(s >> 1), a.key0, a.key1, wd);
-                    // the two samples of the call one after the other (not
-                    // interleaved: that would hold both samples' values at once)
-#pragma unroll 1
-                    for (int h = 0; h < 2; ++h) {
-                        if (s + h < N) {
-                            uint32_t L[4];
-                            lambda_u(wd, h, L);
-                            const EkSample y = fr.at(L);
-                            uint32_t na = 0u;
-                            if (cut & 1u) na += f0.take(ek_accept(o0, e0, y), L);
-                            if (cut & 2u) na += f1.take(ek_accept(o1, e1, y), L);
-                            if (cut & 4u) na += f2.take(ek_accept(o2, e2, y), L);
-                            if (cut & 8u) na += f3.take(ek_accept(o3, e3, y), L);
-                            sec.take(na, L);
-                        }
-                    }
-                }
-            }
-            const double scale = a.vol[m] / (double)N;
-            auto finish = [&](int k, const EkFirst& acc) {
-                double S[5];
-                acc.moments(scale, S);
-                fold(k, S);
-            };
-            if (cut & 1u) finish(0, f0);
-            if (cut & 2u) finish(1, f1);
-            if (cut & 4u) finish(2, f2);
-            if (cut & 8u) finish(3, f3);
-            if (a.region[m] != 0) {
-                const uint64_t cnt = (uint64_t)f0.cnt + f1.cnt + f2.cnt + f3.cnt;
-                const uint64_t A1 = (uint64_t)f0.a1 + f1.a1 + f2.a1 + f3.a1;
-                const uint64_t A2 = (uint64_t)f0.a2 + f1.a2 + f2.a2 + f3.a2;
-                const uint64_t A3 = (uint64_t)f0.a3 + f1.a3 + f2.a3 + f3.a3;
-                double g[10];
-                sec.moments(scale, cnt, A1, A2, A3, g);
-                add_g(g);
-            }
-        }
-    }
-    __syncthreads();
-    if (t < 8) {
-        unsigned long long v = 0ull;
-        for (int i = 0; i < BLOCK; ++i) v += T0p[t * BLOCK + i];
-        if (t & 1) T0l[t >> 1] = v;
-        else T0[t >> 1] = v;
-    }
-    __syncthreads();
-    const int sh = a.fx_shift;
-    double* cb = a.cblk + 4 * vb;
-    for (int r = t; r < 4 * U; r += BLOCK) {
-        const int i = r >> 2, j = r & 3;
-        double cR = 0.0;
-        for (int k = 0; k < 4; ++k) cR += rule_w(k, j) * fx_value(R[k * umax + i], Rl[k * umax + i], sh);
-        cb[r] = -(pw * cR);
-    }
-    double* ob = a.oblk + 20 * oi;
-    if (t < 16) {
-        const int j = t >> 2, jj = t & 3;
-        double O = 0.0;
-        for (int k = 0; k < 4; ++k) O += (rule_w(k, j) * rule_w(k, jj)) * fx_value(T0[k], T0l[k], sh);
-        ob[t] = pw * O;
-    } else if (t < 20) {
-        const int j = t - 16;
-        double f = 0.0;
-        if (a.f_qp)
-            for (int k = 0; k < 4; ++k) f += (w * rule_w(k, j)) * a.f_qp[4 * (int64_t)n + k];
-        ob[t] = f;
-    }
-}
-
-// the form of one outer tet's integration: element keying on whole elements
-// shares its sample loop across the outer points, everything else loops per point
 template <typename T, int BLOCK, bool VR, int KEY, typename A, bool OPAQUE_TID = false>
 __device__ __forceinline__ void integrate_any(const A& a, int64_t oi, unsigned long long* smem64, double (*P)[3]) {
-    if constexpr (KEY == 1 && !VR) integrate_outer_ek<T, BLOCK, A, OPAQUE_TID>(a, oi, smem64, P);
-    else integrate_outer<T, BLOCK, VR, KEY, A, OPAQUE_TID>(a, oi, smem64, P);
+    integrate_outer<T, BLOCK, VR, KEY, A, OPAQUE_TID>(a, oi, smem64, P);
 }
 
 // Local vertex sets beyond LDS: the R sums in global memory, one (pair, cut
@@ -541,15 +325,10 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate_global
     integrate_outer<T, 256, VR, KEY, IntegrateArgs, false, true>(a, (int64_t)blockIdx.x, smem64, P);
 }
 
-// waves per SIMD the register cap is set for: the shared-sample loop keeps
-// four outer points' sample tests and sums live and takes the registers of 2
-// (form = 2 KEY + VR: one argument, so that it passes through __launch_bounds__)
-constexpr int integrate_waves(int form) { return form == 2 ? NLFEM_INTEGRATE_EK_WAVES : NLFEM_INTEGRATE_WAVES; }
-
 // VR: the caps of cut pairs with n_in >= 1 are sampled on E_m minus U_I;
 // KEY: pair (0) or element (1) keying of the Monte Carlo samples
 template <typename T, bool VR, int KEY>
-__global__ __launch_bounds__(256, integrate_waves(2 * KEY + VR)) void k_integrate(IntegrateArgs a) {
+__global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
     integrate_any<T, 256, VR, KEY>(a, (int64_t)blockIdx.x, smem64, P);
@@ -564,7 +343,7 @@ typedef const __attribute__((address_space(4))) IntegrateArgs ConstArgs;
 // items (mesh, outer position) from a device queue, longest first, until it
 // is empty; each item's results depend on the item only.
 template <typename T, int BLOCK, bool VR, int KEY>
-__global__ __launch_bounds__(BLOCK, integrate_waves(2 * KEY + VR)) void k_integrate_batch(const IntegrateArgs* descs,
+__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_batch(const IntegrateArgs* descs,
                                                                                  const int2* items, int64_t n_items,
                                                                                  unsigned long long* head) {
     extern __shared__ unsigned long long smem64[];
@@ -592,7 +371,7 @@ __global__ void k_reset_u64(unsigned long long* p) { *p = 0ull; }
 // dispatcher starts workgroups in increasing index as slots free up, so a
 // longest-first list is taken longest first without a software queue.
 template <typename T, int BLOCK, bool VR, int KEY>
-__global__ __launch_bounds__(BLOCK, integrate_waves(2 * KEY + VR)) void k_integrate_items(const IntegrateArgs* descs,
+__global__ __launch_bounds__(BLOCK, NLFEM_INTEGRATE_WAVES) void k_integrate_items(const IntegrateArgs* descs,
                                                                                  const int2* items) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
@@ -630,8 +409,6 @@ __global__ __launch_bounds__(kExactGBlock, 2) void k_exact_g(IntegrateArgs a, co
     }
     __syncthreads();
     const double d2 = a.delta * a.delta;
-    double O[3];
-    for (int i = 0; i < 3; ++i) O[i] = a.tetX[12 * (int64_t)n + i];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = a.pair_off[oi] + t; p < a.pair_off[oi + 1]; p += kExactGBlock) {
         const int m = a.pair_m[p];
@@ -645,7 +422,7 @@ __global__ __launch_bounds__(kExactGBlock, 2) void k_exact_g(IntegrateArgs a, co
             const int c = (int)((code >> (3 * k)) & 7u);
             if (c == C_OUT) continue;
             acc[k] += pair_g_defect<DEG>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.keying, a.key0, a.key1,
-                                         (uint32_t)(4 * n + k), (uint32_t)m, gv, cf, O);
+                                         (uint32_t)(4 * n + k), (uint32_t)m, gv, cf);
         }
     }
     for (int k = 0; k < 4; ++k) red[k][t] = acc[k];
@@ -688,7 +465,7 @@ __global__ __launch_bounds__(256) void k_debug_pairs(IntegrateArgs a, int64_t o_
             if (c == C_OUT) continue;
             double S[15];
             pair_moments<T, VR, KEY>(X, a.vol[m], P[k], d2, c, a.mc_samples, a.caps != 0, a.key0, a.key1,
-                                     (uint32_t)(4 * n + k), (uint32_t)m, S, Xn);
+                                     (uint32_t)(4 * n + k), (uint32_t)m, S);
             for (int i = 0; i < 15; ++i) out_S[15 * idx + i] = S[i];
         }
     }

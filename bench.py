@@ -256,7 +256,7 @@ def run_precision(P, mg, dev, args):
     del sys64, sys32, x, x32
     # element keying: N samples per element shared by the outer points
     keyed = {}
-    for prec in ["fp64", "fp32"]:
+    for prec in ([] if args.no_element_keying else ["fp64", "fp32"]):
         ts, tks, inf, pl, sm = run(prec, max(2, args.steps // 2), 1, keying="element")
         pl.destroy()
         del sm
@@ -555,6 +555,7 @@ def main():
     ap.add_argument("--serving-count", type=int, default=500)
     ap.add_argument("--serving-quick", action="store_true", help="48 requests at 0.9x saturation only")
     ap.add_argument("--no-large", action="store_true", help="skip the 64^3 large workload")
+    ap.add_argument("--no-element-keying", action="store_true", help="skip the element-keyed lines")
     ap.add_argument("--large-steps", type=int, default=1)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-strategies", action="store_true", help="skip the nocaps/overlap/inside/barycenter lines")

@@ -71,6 +71,8 @@ struct nlfem_plan {
     bool global_r = false, global_rows = false;
     unsigned long long* rglob = nullptr;  // [ve_total][8] R words of the integration
     unsigned long long* racc = nullptr;   // [3 (nnz_ff + nnz_fc)] row sums
+    unsigned long long* stab = nullptr;   // element keying: [K][stab_stride] samples
+    int64_t stab_stride = 0;
     double times[6] = {0, 0, 0, 0, 0, 0};
 
     template <typename Tp>
@@ -153,6 +155,13 @@ int shift_for(double bound) {
     int e = 0;
     std::frexp(bound, &e);  // bound < 2^e
     return std::min(62 - e, 1000);
+}
+
+// element keying without the cap region reads its samples from a per-plan
+// table (K sample_table_stride(N) words) instead of drawing them per pair
+bool uses_sample_table(const nlfem_plan* pl) {
+    return pl->keying == NLFEM_KEY_ELEMENT && pl->strategy == NLFEM_FULLCAPS &&
+           pl->cap_sampling != NLFEM_CAPS_OUTSIDE_UI && pl->mc > 0;
 }
 
 nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, const nlfem_params* prm) {
@@ -435,6 +444,12 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     ALLOC(pl->fc_val_int, double, pl->nnz_fc + 1);
     if (pl->global_r) ALLOC(pl->rglob, unsigned long long, 8 * VT + 8);
     if (pl->global_rows) ALLOC(pl->racc, unsigned long long, 3 * (pl->nnz_ff + pl->nnz_fc) + 3);
+    if (uses_sample_table(pl)) {
+        pl->stab_stride = sample_table_stride(pl->mc);
+        ALLOC(pl->stab, unsigned long long, K * pl->stab_stride + 8);
+        HIPCHK(launch_sample_table(K, pl->mc, pl->stab_stride, (uint32_t)(pl->seed & 0xFFFFFFFFull),
+                                   (uint32_t)(pl->seed >> 32), pl->stab, s));
+    }
     // fixed-point scales (each sum stays below 2^62 in units of its coarse word):
     //  T0_k, R_k(v) <= B_R = sum over the pair list of f_m S0 <= 4 max_pairs max|E|
     //    (S0 <= 2 |E_m| for one pair: subtets plus a Monte Carlo count of at most N)
@@ -516,6 +531,8 @@ IntegrateArgs make_args(nlfem_plan* pl, const double* f_qp) {
     a.gacc = pl->gacc;
     a.gstride = pl->K;
     a.rglob = pl->rglob;
+    a.stab = pl->stab;
+    a.stab_stride = pl->stab_stride;
     return a;
 }
 

@@ -124,6 +124,10 @@ struct IntegrateArgs {
     // R sums in global memory, [sum |Ve|][8] words (coarse k = 0..3, fine k = 0..3)
     // at 8 * (ve_off + i): for local vertex sets too large for LDS; nullptr: in LDS
     unsigned long long* rglob;
+    // element keying: the per-plan sample table, row m at m * stab_stride
+    // (stab_stride = sample_table_stride(N) words), or nullptr
+    const unsigned long long* stab;
+    int64_t stab_stride;
 };
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s);
 // persistent: grid workgroups pull (mesh, outer position) items from a device
@@ -135,6 +139,15 @@ hipError_t launch_integrate_batch(const IntegrateArgs* descs, const int2* items,
 hipError_t launch_integrate_items(const IntegrateArgs* descs, const int2* items, int64_t n_items, int umax, bool fp32,
                                   bool vr, int keying, int block, hipStream_t s);
 size_t integrate_lds_bytes(int umax);
+// per-plan sample table of element keying: for every element m its N samples
+// (counters (m, floor(s / 2), 0, 1)) packed one 64-bit word each, rows padded
+// to a multiple of eight words plus one block of eight (read ahead by the
+// sample loop)
+inline int64_t sample_table_stride(int N) { return ((int64_t)N + 7) / 8 * 8 + 8; }
+// (stride: the row length in words the caller allocated, at least
+// sample_table_stride(N))
+hipError_t launch_sample_table(int64_t K, int N, int64_t stride, uint32_t key0, uint32_t key1,
+                               unsigned long long* tab, hipStream_t s);
 // LDS of the integration with its R sums in global memory (independent of umax)
 size_t integrate_global_lds_bytes();
 // adds the exact-g defect of the T_Omega_I inner integrals to the load terms

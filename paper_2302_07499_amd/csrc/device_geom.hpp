@@ -251,6 +251,18 @@ __device__ __forceinline__ void lambda_u(const uint32_t* w, int h, uint32_t* L) 
     L[3] = 2097152u - hi;
 }
 
+// A sample of the per-plan element-keyed table as one 64-bit word:
+// L_1 | L_2 << 21 | L_3 << 42 (L_1, L_2 < 2^21, L_3 <= 2^21; L_0 follows from
+// their sum 2^21).
+__device__ __forceinline__ unsigned long long pack_lambda(const uint32_t* L) {
+    return (unsigned long long)L[1] | ((unsigned long long)L[2] << 21) | ((unsigned long long)L[3] << 42);
+}
+__device__ __forceinline__ void unpack_lambda(uint32_t lo, uint32_t hi, uint32_t* L) {
+    L[1] = lo & 0x1FFFFFu;
+    L[2] = __builtin_amdgcn_alignbit(hi, lo, 21) & 0x1FFFFFu;
+    L[3] = hi >> 10;
+}
+
 // ---------------------------------------------------------------------------
 // Cut-pair geometry in the inner tet's barycentric space.  Everything below
 // indexes its local arrays with compile-time constants only (runtime vertex
@@ -778,12 +790,46 @@ __device__ inline void region_fold(const CornerGeom* cr, int j, double vol, int 
 // sub-tet's coordinates mu map to E_m's as lambda = sum_r mu_r row(T_j, r).
 // Every lane runs the same sample loop (lanes of other classes in the wave
 // do not serialise it).
-// (cr: the cap region, used with VR)
+// (cr: the cap region, used with VR; trow: with element keying and no cap
+// region, element m's row of the per-plan sample table, the same samples
+// that mc_philox<1> gives, or nullptr to draw them)
 template <typename T, bool VR = false, int KEY = 0>
 __device__ inline void cut_mc(const double* X, double vol, const double* p, double d2, const CutGeom& g, int N,
                               uint32_t key0, uint32_t key1, uint32_t q, uint32_t m, double* S,
-                              const CornerGeom* cr) {
+                              const CornerGeom* cr, const unsigned long long* trow = nullptr) {
     double pl[8];
+    if constexpr (!VR && KEY == 1) {
+        if (trow) {
+            const BallForm bf = whole_frame(X, p, g, pl);
+            McSums acc;
+            // blocks of eight samples (64 bytes per lane), the next block in
+            // flight while one is tested; the row holds one padding block
+            // past its last sample, so the read-ahead needs no branch
+            const uint4* r4 = (const uint4*)trow;
+            uint4 c[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] = r4[i];
+            for (int s = 0; s < N; s += 8) {
+                uint4 nx[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) nx[i] = r4[(s >> 1) + 4 + i];
+#pragma unroll
+                for (int h = 0; h < 8; ++h) {
+                    if (s + h < N) {
+                        const uint4 v = c[h >> 1];
+                        uint32_t L[4];
+                        if (h & 1) unpack_lambda(v.z, v.w, L);
+                        else unpack_lambda(v.x, v.y, L);
+                        acc.add(bf, pl, d2, L);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) c[i] = nx[i];
+            }
+            acc.finish<T>(vol / (double)N, S);
+            return;
+        }
+    }
     if constexpr (!VR) {
         const BallForm bf = whole_frame(X, p, g, pl);
         McSums acc;

@@ -249,7 +249,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
                 cut_det<T>(X, volm, P[k], d2, cg, D, g, VR ? &cr : nullptr);
                 if (a.caps) {
                     cut_mc<T, VR, KEY>(X, volm, P[k], d2, cg, a.mc_samples, a.key0, a.key1, (uint32_t)(4 * n + k),
-                                       (uint32_t)m, S, &cr);
+                                       (uint32_t)m, S, &cr, a.stab ? a.stab + (int64_t)m * a.stab_stride : nullptr);
                 } else {
                     for (int i = 0; i < 15; ++i) S[i] = 0.0;  // nocaps: the subdivision T_I only
                 }
@@ -327,11 +327,28 @@ __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate_global
 
 // VR: the caps of cut pairs with n_in >= 1 are sampled on E_m minus U_I;
 // KEY: pair (0) or element (1) keying of the Monte Carlo samples
+#ifndef NLFEM_XCD_CHUNK
+#define NLFEM_XCD_CHUNK 64
+#endif
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b mod 8).
+// Runs of C consecutive outer tets (neighbours in the mesh order, so their
+// balls share inner tets) go to one XCD and its L2: workgroup b takes outer
+// position ((b / 8) / C) 8 C + (b mod 8) C + (b / 8) mod C; the tail past the
+// last whole group of 8 C keeps its own position.
+__device__ __forceinline__ int64_t xcd_outer_pos(int64_t b, int64_t G) {
+    constexpr int64_t C = NLFEM_XCD_CHUNK;
+    if constexpr (C <= 1) return b;
+    const int64_t full = G / (8 * C) * (8 * C);
+    if (b >= full) return b;
+    const int64_t x = b & 7, local = b >> 3;
+    return (local / C) * (8 * C) + x * C + local % C;
+}
+
 template <typename T, bool VR, int KEY>
 __global__ __launch_bounds__(256, NLFEM_INTEGRATE_WAVES) void k_integrate(IntegrateArgs a) {
     extern __shared__ unsigned long long smem64[];
     __shared__ double P[4][3];
-    integrate_any<T, 256, VR, KEY>(a, (int64_t)blockIdx.x, smem64, P);
+    integrate_any<T, 256, VR, KEY>(a, xcd_outer_pos((int64_t)blockIdx.x, (int64_t)gridDim.x), smem64, P);
 }
 
 // descriptors of a batch are read-only for the whole launch: read through the
@@ -539,6 +556,44 @@ size_t integrate_global_lds_bytes() { return 64 + 8 * 256 * sizeof(unsigned long
             }                                                   \
         }                                                       \
     } while (0)
+
+// The element-keyed samples of every element (mc_philox<1>, two per call),
+// packed; the padding words past N are zero and never used.
+__global__ __launch_bounds__(256) void k_sample_table(int64_t K, int N, int64_t stride, uint32_t key0, uint32_t key1,
+                                                      unsigned long long* tab) {
+    const int64_t half = stride >> 1;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= K * half) return;
+    const int64_t m = t / half;
+    const int j = (int)(t - m * half);
+    unsigned long long out[2] = {0ull, 0ull};
+    if (2 * j < N) {
+        uint32_t w[4];
+        mc_philox<1>(0u, (uint32_t)m, (uint32_t)j, key0, key1, w);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (2 * j + h < N) {
+                uint32_t L[4];
+                lambda_u(w, h, L);
+                out[h] = pack_lambda(L);
+            }
+        }
+    }
+    ulonglong2 v;
+    v.x = out[0];
+    v.y = out[1];
+    *(ulonglong2*)(tab + m * stride + 2 * j) = v;
+}
+
+hipError_t launch_sample_table(int64_t K, int N, int64_t stride, uint32_t key0, uint32_t key1,
+                               unsigned long long* tab, hipStream_t s) {
+    if (K <= 0 || N <= 0) return hipSuccess;
+    // rows of `stride` words: the N samples, the padding the sample loop reads ahead
+    if (stride < sample_table_stride(N) || (stride & 1)) return hipErrorInvalidValue;
+    const int64_t n = K * (stride >> 1);
+    k_sample_table<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(K, N, stride, key0, key1, tab);
+    return hipGetLastError();
+}
 
 hipError_t launch_integrate(const IntegrateArgs& a, bool fp32, hipStream_t s) {
     if (a.n_outer <= 0) return hipSuccess;

@@ -101,7 +101,11 @@ size_t estimate_footprint(const Request& r) {
     const double P = n_outer * ppo, C = n_outer * cpo, VT = n_outer * vpo, nnz = nf * row;
     const double mesh = V * 40.0 + K * 420.0;
     const double classify = C * 6.0 + P * 12.0 + n_outer * 64.0;
-    const double retained = P * 6.0 + VT * 44.0 + n_outer * 200.0 + nnz * 20.0 + nf * 64.0;
+    // the element-keyed sample table (8 bytes per sample and element) stays with the plan
+    const bool table = r.prm.keying == NLFEM_KEY_ELEMENT && r.prm.strategy == NLFEM_FULLCAPS &&
+                       r.prm.cap_sampling != NLFEM_CAPS_OUTSIDE_UI;
+    const double stab = table ? (double)K * 8.0 * (double)sample_table_stride(r.prm.mc_samples) : 0.0;
+    const double retained = P * 6.0 + VT * 44.0 + n_outer * 200.0 + nnz * 20.0 + nf * 64.0 + stab;
     const double pattern = retained + VT * 24.0;
     const double numeric = retained + nnz * 12.0 + nf * 48.0;
     const double est = (mesh + std::max(classify, std::max(pattern, numeric))) * 1.25 + (double)(8 << 20);

@@ -467,9 +467,12 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
         const double bG = 4.0 * apsi * vmax * vmax * (double)std::max<int64_t>(pl->max_inner, 1);
         const double bC = apsi * vmax * bR * 0.5 + bG + bW * vmax;
         const double bRow = bC * 8.0 * (double)std::max<int64_t>(pl->max_vt, 1);
-        pl->fx_shift = shift_for(bR);
-        pl->w_shift = shift_for(bW);
-        pl->g_shift = shift_for(bG);
+        // a single term must also stay below 2^51 units (the integer split of
+        // the integration kernel): at most 4 max|E| for T0 and R, |psi| max|E|
+        // for the inside weight, 2 |psi| max|E|^2 for the cut part of G_m
+        pl->fx_shift = std::min(shift_for(bR), shift_for(4.0 * vmax * 2048.0));
+        pl->w_shift = std::min(shift_for(bW), shift_for(apsi * vmax * 2048.0));
+        pl->g_shift = std::min(shift_for(bG), shift_for(2.0 * apsi * vmax * vmax * 2048.0));
         pl->row_shift = shift_for(bRow);
     }
     pl->times[0] = total.stop();

@@ -634,11 +634,14 @@ struct McSums {
         double h1 = fma(l3, pl[7], fma(l2, pl[6], fma(l1, pl[5], pl[4])));
         bool inU = (h0 >= 0.0) && (h1 >= 0.0);
         bool acc = (rr < d2) && !inU;
-        const uint32_t x1 = acc ? L[1] : 0u, x2 = acc ? L[2] : 0u, x3 = acc ? L[3] : 0u;
-        icnt += acc ? 1u : 0u;
-        ia1 += x1; ia2 += x2; ia3 += x3;
-        B11 += (uint64_t)x1 * x1; B12 += (uint64_t)x1 * x2; B13 += (uint64_t)x1 * x3;
-        B22 += (uint64_t)x2 * x2; B23 += (uint64_t)x2 * x3; B33 += (uint64_t)x3 * x3;
+        // the sums under the lane mask (a branch, not selects)
+        if (acc) {
+            const uint32_t x1 = L[1], x2 = L[2], x3 = L[3];
+            icnt += 1u;
+            ia1 += x1; ia2 += x2; ia3 += x3;
+            B11 += (uint64_t)x1 * x1; B12 += (uint64_t)x1 * x2; B13 += (uint64_t)x1 * x3;
+            B22 += (uint64_t)x2 * x2; B23 += (uint64_t)x2 * x3; B33 += (uint64_t)x3 * x3;
+        }
     }
     // moments of the accepted samples' coordinates, times scale, to S[15]
     template <typename T>

@@ -36,18 +36,26 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t 
     return lo;
 }
 
-// Non-negative x is added to a two-word fixed-point sum: the coarse word
-// counts units of 2^-s, the fine word the remainder in units of 2^-(s+48).
-// Integer sums are order-independent, so the result is deterministic, and the
-// fine word keeps small contributions (thin cut slivers) relatively exact.
+// x is added to a two-word fixed-point sum: the coarse word counts units of
+// 2^-s, the fine word the remainder in units of 2^-(s+48), both two's
+// complement.  The pair (h, l) of one term is the integer nearest to
+// x 2^(s+48) split at bit 48: h the integer nearest to x 2^s, l the integer
+// nearest to the remainder times 2^48 (|l| <= 2^47).  Integer sums are
+// order-independent, so the result is deterministic, and the fine word keeps
+// small contributions (thin cut slivers) relatively exact.
 constexpr int FX_LO_BITS = 48;
+// Adding 1.5 2^52 to |v| < 2^51 rounds v to an integer (to nearest, ties to
+// even) held in the low mantissa bits, which the bit difference reads out.
+constexpr double kRoundMagic = 6755399441055744.0;
 
+// needs |x 2^s| < 2^51 (the plan's scales keep every single term below it)
 __device__ __forceinline__ void fx_split(double x, double fx, unsigned long long& hi, unsigned long long& lo) {
-    const double xs = x * fx;  // exact: fx is a power of two
-    const double h = floor(xs);
-    const double r = xs - h;   // exact, in [0, 1)
-    hi = (unsigned long long)h;
-    lo = (unsigned long long)__double2ull_rn(r * 281474976710656.0);  // r * 2^48
+    const double xs = x * fx;                    // exact: fx is a power of two
+    const double t = xs + kRoundMagic;           // kRoundMagic + nearest integer to xs
+    const double r = xs - (t - kRoundMagic);     // exact, |r| <= 1/2
+    const double u = fma(r, 281474976710656.0, kRoundMagic);  // nearest integer to r 2^48, |.| <= 2^47
+    hi = (unsigned long long)(__double_as_longlong(t) - __double_as_longlong(kRoundMagic));
+    lo = (unsigned long long)(__double_as_longlong(u) - __double_as_longlong(kRoundMagic));
 }
 
 __device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long long* lo, double x, double fx) {
@@ -57,21 +65,18 @@ __device__ __forceinline__ void fx_add(unsigned long long* hi, unsigned long lon
     atomicAdd(lo, l);
 }
 
-// carry-normalised: the fine word is reduced below 2^48 first, so both
-// conversions are exact for totals below 2^53 coarse units
+// carry-normalised: the fine word is reduced to [0, 2^48) first (its carry,
+// an arithmetic shift, goes to the coarse word), so both conversions are
+// exact for totals below 2^53 coarse units
 __device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo, int shift) {
-    const unsigned long long h = hi + (lo >> FX_LO_BITS);
-    const double v = (double)(lo & ((1ull << FX_LO_BITS) - 1ull)) * 0x1p-48 + (double)h;
+    const unsigned long long h = hi + (unsigned long long)((long long)lo >> FX_LO_BITS);
+    const double v = (double)(lo & ((1ull << FX_LO_BITS) - 1ull)) * 0x1p-48 + (double)(long long)h;
     return ldexp(v, -shift);
 }
 
-// signed variant for global accumulators: the coarse word is two's complement
+// the same two-word sums in global memory (the G_m accumulators)
 __device__ __forceinline__ void fxs_add_global(unsigned long long* hi, unsigned long long* lo, double x, double fx) {
-    const double xs = x * fx;
-    const double h = floor(xs);
-    const double r = xs - h;
-    atomicAdd(hi, (unsigned long long)(long long)h);
-    atomicAdd(lo, (unsigned long long)__double2ull_rn(r * 281474976710656.0));
+    fx_add(hi, lo, x, fx);
 }
 
 // Cut (pair, outer point) items are taken in chunks of kChunk pairs.

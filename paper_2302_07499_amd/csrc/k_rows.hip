@@ -280,10 +280,11 @@ __device__ __forceinline__ double fx3_value(const unsigned long long* w, int str
     return neg ? -r : r;
 }
 
-// two-word value of the G accumulators (coarse word two's complement, fine
-// word non-negative), carry-normalised before conversion
+// two-word value of the G accumulators (both words two's complement),
+// carry-normalised before conversion: the fine word's carry by an arithmetic
+// shift, its remainder in [0, 2^48)
 __device__ __forceinline__ double fxs_value(unsigned long long hi, unsigned long long lo, int shift) {
-    const long long h = (long long)hi + (long long)(lo >> 48);
+    const long long h = (long long)hi + ((long long)lo >> 48);
     const double v = (double)(lo & kM48) * 0x1p-48 + (double)h;
     return ldexp(v, -shift);
 }

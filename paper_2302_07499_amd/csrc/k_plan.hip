@@ -377,8 +377,7 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
 
 // One wave per outer tet: the pending (candidate, point) cases are queued in
 // the wave's LDS slice across candidate chunks and tested in full rounds of
-// 64; each result replaces its pending byte (one atomic AND: CUT(0) = 2,
-// OUT = 0 both fit under the 0xFF mask).
+// 64; each result replaces its pending byte.
 constexpr int kQueue = 320;  // < 64 left over + 4 * 64 appended per chunk
 
 __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
@@ -402,8 +401,9 @@ __global__ __launch_bounds__(256) void k_classify_exact(const double* tetX, cons
         const double* Xg = tetX + 12 * (int64_t)cand_m[pos];
         double X[12];
         for (int e = 0; e < 12; ++e) X[e] = Xg[e];
-        const uint32_t res = (uint32_t)classify_exact(X, P[k], d2);
-        atomicAnd(&cand_code[pos], ~(0xFFu << (8 * k)) | (res << (8 * k)));
+        // byte k of the little-endian code word: a byte store, no atomic (the
+        // other bytes may be written by other lanes at the same time)
+        ((uint8_t*)cand_code)[4 * pos + k] = (uint8_t)classify_exact(X, P[k], d2);
     };
     const int64_t src = cand_off[oi], n = cand_n[oi];
     int nq = 0;

@@ -271,7 +271,9 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     }
     // ---- classification -------------------------------------------------
     Timer tcls(s);
-    TMP(t_cnt, (size_t)(5 * no + 5) * 8);
+    TMP(t_cnt, (size_t)(16 * no + 16) * 8);
+    TMP(t_cls, (size_t)(5 * no + 5) * 4);
+    TMP(t_cc, 64);
     TMP(t_tot, (size_t)(no + 1) * 8);
     TMP(t_cand_off, (size_t)(no + 2) * 8);
     ALLOC(pl->pair_off, int64_t, no + 2);
@@ -283,11 +285,15 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     TMP(t_cand_c, (size_t)(n_cand + 1) * 4);
     TMP(t_cand_n, (size_t)(no + 1) * 8);
     TMP(t_box, (size_t)(K + 1) * 32);
-    HIPCHK(launch_sorted_boxes(pl->tetX, cell_tets, K, (float4*)t_box.p, s));
-    HIPCHK(launch_classify(pl->tetX, pl->outer_ids, no, cell_start, cell_tets, (const float4*)t_box.p, g, prm->delta,
-                           prm->strategy, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), t_cnt.as<int64_t>(),
+    TMP(t_sx, (size_t)(K + 1) * 96);
+    HIPCHK(launch_sorted_boxes(pl->tetX, cell_tets, K, (float4*)t_box.p, t_sx.as<double>(), s));
+    HIPCHK(launch_classify(pl->tetX, pl->outer_ids, no, cell_start, cell_tets, (const float4*)t_box.p,
+                           t_sx.as<double>(), g, prm->delta, prm->strategy, t_cand_off.as<int64_t>(),
+                           t_cand_n.as<int64_t>(), t_cnt.as<int64_t>(), t_cls.as<uint32_t>(),
                            t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), s));
-    HIPCHK(launch_pair_totals(t_cnt.as<int64_t>(), no, t_tot.as<int64_t>(), s));
+    HIPCHK(hipMemsetAsync(t_cc.p, 0, 64, s));
+    HIPCHK(launch_pair_totals(t_cnt.as<int64_t>(), t_cls.as<uint32_t>(), no, t_tot.as<int64_t>(),
+                              t_cc.as<unsigned long long>(), s));
     HIPCHK(exclusive_scan_i64(t_tot.as<int64_t>(), pl->pair_off, no, t_scan2.p, s));
     HIPCHK(reduce_max_i64(t_tot.as<int64_t>(), no, (int64_t*)(small + 8), s));
     pl->P = read_i64(c, pl->pair_off + no);
@@ -299,12 +305,10 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
         return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^15 interacting tets for one outer tet");
     ALLOC(pl->pair_m, int32_t, P + 1);
     ALLOC(pl->pair_cls, uint16_t, P + 1);
-    HIPCHK(launch_pair_compact(no, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), pl->pair_off, prm->strategy,
-                               t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(), pl->pair_m, pl->pair_cls, s));
+    HIPCHK(launch_pair_compact(no, t_cand_off.as<int64_t>(), t_cand_n.as<int64_t>(), pl->pair_off,
+                               t_cnt.as<int64_t>(), prm->strategy, t_cand_m.as<int32_t>(), t_cand_c.as<uint32_t>(),
+                               pl->pair_m, pl->pair_cls, s));
     {
-        TMP(t_cc, 64);
-        HIPCHK(hipMemsetAsync(t_cc.p, 0, 64, s));
-        HIPCHK(launch_class_counts(pl->pair_cls, P, t_cc.as<unsigned long long>(), s));
         unsigned long long cc[6];
         HIPCHK(hipMemcpyAsync(cc, t_cc.p, sizeof cc, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

@@ -72,21 +72,25 @@ hipError_t launch_cell_start(const uint64_t* sorted_keys, int64_t K, int64_t n_c
 // ball query: candidate count per outer tet (upper bound of its pairs), the
 // tets' bounding boxes in cell order, then the classification of the
 // candidates (the cand_n[oi] hits of each region compacted at its start,
-// cand_code: one class byte per outer point; cnt[n_outer*5] = hits per
-// cut-count bucket), then the grouped compaction of the hits into the pair
+// cand_code: one class byte per outer point; the hits counted per cut mask
+// and per class), then the grouped compaction of the hits into the pair
 // arrays.
 hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                              const int64_t* cell_start, Grid g, double delta, int64_t* cand, hipStream_t s);
-hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box,
+// (box: [K][2] float corners, sX: [K][12] vertex blocks, both in cell order)
+hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box, double* sX,
                                hipStream_t s);
+// (cnt: [n_outer][16] hits per cut mask; cls: [n_outer][5] point-pair classes IN, CUT(0..3))
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
-                           const uint32_t* cell_tets, const float4* box, Grid g, double delta, int strategy,
-                           const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, int32_t* cand_m,
-                           uint32_t* cand_code, hipStream_t s);
+                           const uint32_t* cell_tets, const float4* box, const double* sX, Grid g, double delta,
+                           int strategy, const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, uint32_t* cls,
+                           int32_t* cand_m, uint32_t* cand_code, hipStream_t s);
 hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n, const int64_t* pair_off,
-                               int strategy, const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m,
-                               uint16_t* pair_cls, hipStream_t s);
-hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s);
+                               const int64_t* cnt, int strategy, const int32_t* cand_m, const uint32_t* cand_code,
+                               int32_t* pair_m, uint16_t* pair_cls, hipStream_t s);
+// pairs per outer tet into tot; class totals added to cls_tot[1..5] (zeroed by the caller)
+hipError_t launch_pair_totals(const int64_t* cnt, const uint32_t* cls, int64_t n_outer, int64_t* tot,
+                              unsigned long long* cls_tot, hipStream_t s);
 // local vertex sets Ve of the outer tets: count pass writes ucount[oi], fill
 // pass writes the sorted sets at ve_off
 hipError_t launch_pattern(bool fill, const int32_t* tets, int64_t n_outer, const int64_t* pair_off,

@@ -186,9 +186,11 @@ __device__ __forceinline__ void load_outer_points(const double* tetX, int n, dou
 
 // Bounding boxes of the tets in cell order (box[2j], box[2j+1] = lower and
 // upper corner of tet cell_tets[j]), in float rounded outward, so that the
-// classification can drop far candidates with one coalesced 32-byte read
-// instead of gathering their 96-byte vertex block.
-__global__ void k_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box) {
+// classification can drop far candidates with one coalesced 32-byte read;
+// and the tets' vertex blocks in the same order (sX[j] = tetX[cell_tets[j]]),
+// so that the candidates it keeps read theirs coalesced, without first
+// loading the tet id.
+__global__ void k_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box, double* sX) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= K) return;
     const double* X = tetX + 12 * (int64_t)cell_tets[j];
@@ -199,6 +201,7 @@ __global__ void k_sorted_boxes(const double* tetX, const uint32_t* cell_tets, in
     }
     box[2 * j] = make_float4(lo[0], lo[1], lo[2], 0.0f);
     box[2 * j + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    for (int i = 0; i < 12; ++i) sX[12 * j + i] = X[i];
 }
 
 // squared distance from p to a box, computed in double from the (outward
@@ -256,18 +259,20 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// classes of candidate j against the four points (one byte per point: IN,
-// CUT(n_in), kPending, or 0 = OUT); 0 if its box is beyond delta of all four
-__device__ __forceinline__ uint32_t classify_candidate(const double* tetX, const uint32_t* cell_tets,
-                                                       const float4* box, int64_t j, const double (*P)[3],
-                                                       double d2, double far2, int strategy, int& m) {
-    const float4 lo = box[2 * j], hi = box[2 * j + 1];
-    bool near = false;
-    for (int k = 0; k < 4; ++k) near = near || !(box_dist2(lo, hi, P[k]) > far2);
-    if (!near) return 0u;
-    m = (int)cell_tets[j];
+// classes of the near candidate j against the four points (one byte per
+// point: IN, CUT(n_in), kPending, or 0 = OUT)
+__device__ __forceinline__ uint32_t classify_candidate(const double* sX, int64_t j, const double (*P)[3], double d2,
+                                                       int strategy) {
     double X[12];
-    for (int i = 0; i < 12; ++i) X[i] = tetX[12 * (int64_t)m + i];
+    {
+        const double2* xs = (const double2*)(sX + 12 * j);  // 96-byte rows: 16-byte aligned
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const double2 v = xs[i];
+            X[2 * i] = v.x;
+            X[2 * i + 1] = v.y;
+        }
+    }
     uint32_t code = 0;
     for (int k = 0; k < 4; ++k) {
         int cl;
@@ -285,16 +290,20 @@ __device__ __forceinline__ uint32_t classify_candidate(const double* tetX, const
 
 // cell rows of one outer tet's candidate region kept in LDS (up to kMaxRows
 // at a time), so that the wave walks the region as one list in full 64-lane
-// chunks across rows
+// chunks across rows; the candidates whose box passes the ball test are
+// queued (kNearQ slots per wave) and classified in full rounds of 64
 constexpr int kMaxRows = 256;
+constexpr int kNearQ = 128;  // < 64 left over + 64 appended per chunk
 
 __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const int32_t* outer_ids, int64_t n_outer,
                                                        const int64_t* cell_start, const uint32_t* cell_tets,
-                                                       const float4* box, Grid g, double delta, int strategy,
+                                                       const float4* box, const double* sX, Grid g, double delta,
+                                                       int strategy,
                                                        const int64_t* cand_off, int64_t* cand_n, int32_t* cand_m,
                                                        uint32_t* cand_code) {
     __shared__ int64_t row_beg[4][kMaxRows];
     __shared__ int64_t row_pre[4][kMaxRows + 1];  // candidates before each row
+    __shared__ int64_t near_q[4][kNearQ];         // queued near candidates (cell order)
     // the wave index is uniform: in a scalar register, the outer tet and its points are too
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
@@ -302,11 +311,13 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
     double P[4][3];
     load_outer_points(tetX, outer_ids[oi], P);
     const double d2 = delta * delta;
-    // a box farther than this from a point is certainly OUT for it (the same
-    // bound the vertex-based test uses, so the classes are unchanged)
-    const double far2 = d2 * (1.0 + 1e-9);
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    // the ball around the points' centre that holds their four balls (radius
+    // delta + the largest distance to a point, enlarged by 1e-7): a box beyond
+    // it is beyond delta of every point, so one box test per candidate drops
+    // the far ones and the classes are unchanged
     const CandBall b = cand_ball(P, delta);
+    const double bR2 = b.R * b.R;
     int y0, y1, z0, z1;
     axis_range(b, 1, g, y0, y1);
     axis_range(b, 2, g, z0, z1);
@@ -324,6 +335,19 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
         }
         n_hit += __popcll(bal);
     };
+    // classify queue entry `lane` when it is below n (all lanes take part in emit)
+    int64_t* Q = near_q[wave];
+    auto classify_round = [&](int n) {
+        uint32_t code = 0;
+        int m = 0;
+        if (lane < n) {
+            const int64_t j = Q[lane];
+            m = (int)cell_tets[j];
+            code = classify_candidate(sX, j, P, d2, strategy);
+        }
+        emit(code, m);
+    };
+    int nq = 0;
     const int ny = y1 - y0 + 1;
     const int n_rows = (z1 >= z0 && y1 >= y0) ? ny * (z1 - z0 + 1) : 0;
     int64_t* RB = row_beg[wave];
@@ -362,16 +386,31 @@ __global__ __launch_bounds__(256) void k_classify_fast(const double* tetX, const
         int r = 0;  // this lane's row cursor: its candidate index only grows
         for (int64_t c0 = 0; c0 < run; c0 += 64) {
             const int64_t c = c0 + lane;
-            uint32_t code = 0;
-            int m = 0;
+            bool near = false;
+            int64_t j = 0;
             if (c < run) {
                 while (RP[r + 1] <= c) ++r;
-                code = classify_candidate(tetX, cell_tets, box, RB[r] + (c - RP[r]), P, d2, far2, strategy, m);
+                j = RB[r] + (c - RP[r]);
+                near = !(box_dist2(box[2 * j], box[2 * j + 1], b.c) > bR2);
             }
-            emit(code, m);
+            const uint64_t bal = __ballot(near);
+            if (near) Q[nq + __popcll(bal & lt)] = j;
+            nq += __popcll(bal);
+            wave_sync();
+            if (nq >= 64) {
+                classify_round(64);
+                // move the rest of the queue (fewer than 64) down
+                const int rest = nq - 64;
+                const int64_t keep = lane < rest ? Q[64 + lane] : 0;
+                wave_sync();
+                if (lane < rest) Q[lane] = keep;
+                wave_sync();
+                nq = rest;
+            }
         }
         wave_sync();  // the next batch of rows overwrites RB and RP
     }
+    if (nq > 0) classify_round(nq);
     if (lane == 0) cand_n[oi] = n_hit;
 }
 
@@ -466,34 +505,6 @@ __device__ __forceinline__ uint32_t strategy_code(uint32_t code, int strategy) {
     return out;
 }
 
-// Per outer tet: hits per "number of cut points" bucket (cnt[oi*5 + b]).
-__global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
-                                                    int strategy, const uint32_t* cand_code, int64_t* cnt) {
-    // the wave index is uniform: in a scalar register, the outer tet and its points are too
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
-    if (oi >= n_outer) return;
-    const int64_t src = cand_off[oi], n = cand_n[oi];
-    int64_t c[5] = {0, 0, 0, 0, 0};
-    for (int64_t j = 0; j < n; j += 64) {
-        const uint32_t code = (j + lane < n) ? strategy_code(cand_code[src + j + lane], strategy) : 0u;
-        int ncut = 0;
-        bool hit = false;
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t cl = (code >> (8 * k)) & 7u;
-            hit = hit || cl != (uint32_t)C_OUT;
-            ncut += cl >= (uint32_t)C_CUT0 ? 1 : 0;
-        }
-        for (int b = 0; b <= 4; ++b) c[b] += __popcll(__ballot(hit && ncut == b));
-    }
-    if (lane < 5) {
-        int64_t v = 0;
-        for (int b = 0; b <= 4; ++b)
-            if (b == lane) v = c[b];
-        cnt[oi * 5 + lane] = v;
-    }
-}
-
 // packed per-point class bytes -> 3-bit-per-point pair code
 __device__ __forceinline__ uint32_t code12(uint32_t code) {
     uint32_t c = 0;
@@ -510,14 +521,60 @@ __device__ __forceinline__ int cut_mask(uint32_t c12) {
     return mk;
 }
 
+// Per outer tet: its hits per cut mask (which outer points cut the tet,
+// cnt[16 oi + mask]) and per class over the four points (cls[5 oi + c - 1]
+// for IN, CUT(0..3)).
+__global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
+                                                    int strategy, const uint32_t* cand_code, int64_t* cnt,
+                                                    uint32_t* cls) {
+    // the wave index is uniform: in a scalar register, the outer tet and its points are too
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
+    if (oi >= n_outer) return;
+    const int64_t src = cand_off[oi], n = cand_n[oi];
+    int64_t c[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) c[b] = 0;
+    uint32_t q[5] = {0u, 0u, 0u, 0u, 0u};
+    for (int64_t j = 0; j < n; j += 64) {
+        const bool valid = j + lane < n;
+        const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
+        const int mk = cc ? cut_mask(cc) : -1;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) c[b] += __popcll(__ballot(mk == b));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t cl = (cc >> (3 * k)) & 7u;
+#pragma unroll
+            for (int t = 0; t < 5; ++t) q[t] += cl == (uint32_t)(t + 1) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+        for (int off = 32; off > 0; off >>= 1) q[t] += __shfl_xor(q[t], off, 64);
+    int64_t v = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+        if (b == lane) v = c[b];
+    if (lane < 16) cnt[oi * 16 + lane] = v;
+    if (lane < 5) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+            if (t == lane) w = q[t];
+        cls[oi * 5 + lane] = w;
+    }
+}
+
 // One wave per outer tet: the hits among its candidates, grouped by their cut
 // mask (more cut points first, then the larger mask) and in candidate order
 // within a group, to the final pair arrays.  Lanes of a wave then see the same
 // cut points, so the sample loops of a wave are not run for points that only
 // some lanes cut.
 __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n,
-                                                      const int64_t* pair_off, int strategy, const int32_t* cand_m,
-                                                      const uint32_t* cand_code, int32_t* pair_m, uint16_t* pair_cls) {
+                                                      const int64_t* pair_off, const int64_t* cnt, int strategy,
+                                                      const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m,
+                                                      uint16_t* pair_cls) {
     // the wave index is uniform: in a scalar register, the outer tet and its points are too
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t oi = (int64_t)blockIdx.x * 4 + wave;
@@ -526,14 +583,7 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     int64_t c[16];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) c[b] = 0;
-    for (int64_t j = 0; j < n; j += 64) {
-        const bool valid = j + lane < n;
-        const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
-        const int mk = cc ? cut_mask(cc) : -1;
-#pragma unroll
-        for (int b = 0; b < 16; ++b) c[b] += __popcll(__ballot(mk == b));
-    }
+    for (int b = 0; b < 16; ++b) c[b] = cnt[oi * 16 + b];  // from k_pair_count
     // group order: 15 | 14 13 11 7 | 12 10 9 6 5 3 | 8 4 2 1 | 0
     const int order[16] = {15, 14, 13, 11, 7, 12, 10, 9, 6, 5, 3, 8, 4, 2, 1, 0};
     int64_t base[16];
@@ -564,10 +614,27 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     }
 }
 
-__global__ void k_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_outer) return;
-    tot[i] = cnt[5 * i] + cnt[5 * i + 1] + cnt[5 * i + 2] + cnt[5 * i + 3] + cnt[5 * i + 4];
+// pairs per outer tet (the sum of its 16 mask buckets), and the class totals
+// of all pairs (one atomic per class and block into cls_tot[1..5])
+__global__ __launch_bounds__(256) void k_pair_totals(const int64_t* cnt, const uint32_t* cls, int64_t n_outer,
+                                                     int64_t* tot, unsigned long long* cls_tot) {
+    __shared__ unsigned long long red[5][256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long q[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
+    if (i < n_outer) {
+        int64_t t = 0;
+        for (int b = 0; b < 16; ++b) t += cnt[16 * i + b];
+        tot[i] = t;
+        for (int c = 0; c < 5; ++c) q[c] = cls[5 * i + c];
+    }
+    for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = q[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5 && red[threadIdx.x][0]) atomicAdd(&cls_tot[1 + threadIdx.x], red[threadIdx.x][0]);
 }
 
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
@@ -764,39 +831,41 @@ hipError_t launch_cand_count(const double* tetX, const int32_t* outer_ids, int64
     return hipGetLastError();
 }
 
-hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box,
+hipError_t launch_sorted_boxes(const double* tetX, const uint32_t* cell_tets, int64_t K, float4* box, double* sX,
                                hipStream_t s) {
     if (K <= 0) return hipSuccess;
-    k_sorted_boxes<<<blocks_for(K), 256, 0, s>>>(tetX, cell_tets, K, box);
+    k_sorted_boxes<<<blocks_for(K), 256, 0, s>>>(tetX, cell_tets, K, box, sX);
     return hipGetLastError();
 }
 
 hipError_t launch_classify(const double* tetX, const int32_t* outer_ids, int64_t n_outer, const int64_t* cell_start,
-                           const uint32_t* cell_tets, const float4* box, Grid g, double delta, int strategy,
-                           const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, int32_t* cand_m,
-                           uint32_t* cand_code, hipStream_t s) {
+                           const uint32_t* cell_tets, const float4* box, const double* sX, Grid g, double delta,
+                           int strategy, const int64_t* cand_off, int64_t* cand_n, int64_t* cnt, uint32_t* cls,
+                           int32_t* cand_m, uint32_t* cand_code, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
     k_classify_fast<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, cell_start, cell_tets, box,
-                                                                  g, delta, strategy, cand_off, cand_n, cand_m,
+                                                                  sX, g, delta, strategy, cand_off, cand_n, cand_m,
                                                                   cand_code);
     k_classify_exact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(tetX, outer_ids, n_outer, delta, cand_off, cand_n,
                                                                     cand_m, cand_code);
-    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, strategy, cand_code, cnt);
+    k_pair_count<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, strategy, cand_code, cnt,
+                                                               cls);
     return hipGetLastError();
 }
 
 hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const int64_t* cand_n, const int64_t* pair_off,
-                               int strategy, const int32_t* cand_m, const uint32_t* cand_code, int32_t* pair_m,
-                               uint16_t* pair_cls, hipStream_t s) {
+                               const int64_t* cnt, int strategy, const int32_t* cand_m, const uint32_t* cand_code,
+                               int32_t* pair_m, uint16_t* pair_cls, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, pair_off, strategy, cand_m,
-                                                                 cand_code, pair_m, pair_cls);
+    k_pair_compact<<<(unsigned)((n_outer + 3) / 4), 256, 0, s>>>(n_outer, cand_off, cand_n, pair_off, cnt, strategy,
+                                                                 cand_m, cand_code, pair_m, pair_cls);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_totals(const int64_t* cnt, int64_t n_outer, int64_t* tot, hipStream_t s) {
+hipError_t launch_pair_totals(const int64_t* cnt, const uint32_t* cls, int64_t n_outer, int64_t* tot,
+                              unsigned long long* cls_tot, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
-    k_pair_totals<<<blocks_for(n_outer), 256, 0, s>>>(cnt, n_outer, tot);
+    k_pair_totals<<<blocks_for(n_outer), 256, 0, s>>>(cnt, cls, n_outer, tot, cls_tot);
     return hipGetLastError();
 }
 

@@ -159,9 +159,62 @@ __global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, i
         for (int j = 0; j < 4; ++j) hset_insert(hs, mask, (uint32_t)rp.tets[4 * n + j], err);
     }
     __syncthreads();
-    for (int k = 2; k <= hash_cap; k <<= 1) {
+    if (!FILL) {
+        // the count pass needs no order: the filled slots, and the free ones among them
+        int nu = 0, nf = 0;
+        for (int i = t; i < hash_cap; i += 256) {
+            const uint32_t v = hs[i];
+            if (v != 0xFFFFFFFFu) {
+                ++nu;
+                nf += rp.free_id[v] >= 0 ? 1 : 0;
+            }
+        }
+        atomicAdd(&sU, nu);
+        atomicAdd(&sF, nf);
+        __syncthreads();
+        if (t == 0) {
+            n_ff[r] = sF;
+            n_fc[r] = sU - sF;
+        }
+        return;
+    }
+    // fill: the filled slots moved to the front, so that the bitonic sort runs
+    // over the first power of two that holds them instead of the whole table
+    // (tables of at most 256 kSlots entries; a larger one is sorted whole)
+    __shared__ int csum[256];
+    constexpr int kSlots = 32;
+    int n2 = hash_cap, U = -1;
+    if (hash_cap <= 256 * kSlots) {
+        uint32_t mine[kSlots];
+        int nm = 0;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            const int i = t + 256 * q;
+            mine[q] = i < hash_cap ? hs[i] : 0xFFFFFFFFu;
+            nm += mine[q] != 0xFFFFFFFFu ? 1 : 0;
+        }
+        csum[t] = nm;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int add = t >= off ? csum[t - off] : 0;
+            __syncthreads();
+            csum[t] += add;
+            __syncthreads();
+        }
+        U = csum[255];
+        n2 = 1;
+        while (n2 < U) n2 <<= 1;
+        int at = csum[t] - nm;
+        __syncthreads();  // every slot is read before the front is overwritten
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q)
+            if (mine[q] != 0xFFFFFFFFu) hs[at++] = mine[q];
+        for (int i = U + t; i < n2; i += 256) hs[i] = 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < hash_cap; i += 256) {
+            for (int i = t; i < n2; i += 256) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
                     const uint32_t a = hs[i], b = hs[ixj];
@@ -175,23 +228,13 @@ __global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, i
             __syncthreads();
         }
     }
-    for (int i = t; i < hash_cap; i += 256)
-        if (hs[i] != 0xFFFFFFFFu && (i == hash_cap - 1 || hs[i + 1] == 0xFFFFFFFFu)) sU = i + 1;
-    __syncthreads();
-    const int U = sU;
-    if (!FILL) {
-        int nf = 0;
-        for (int i = t; i < U; i += 256) nf += rp.free_id[hs[i]] >= 0 ? 1 : 0;
-        atomicAdd(&sF, nf);
+    if (U < 0) {  // the whole table was sorted: the filled slots end where EMPTY starts
+        for (int i = t; i < hash_cap; i += 256)
+            if (hs[i] != 0xFFFFFFFFu && (i == hash_cap - 1 || hs[i + 1] == 0xFFFFFFFFu)) sU = i + 1;
         __syncthreads();
-        if (t == 0) {
-            n_ff[r] = sF;
-            n_fc[r] = U - sF;
-        }
-        return;
+        U = sU;
     }
     // fill: ranks among free / constrained columns by a block scan over chunks
-    __shared__ int csum[256];
     const int64_t ab = ff_row_ptr[r] + fc_row_ptr[r];
     int run_f = 0;
     for (int base = 0; base < U; base += 256) {

@@ -53,7 +53,11 @@ typedef enum {
 typedef enum {
     NLFEM_FP64 = 0,       /* every step in IEEE double                                        */
     NLFEM_FP32_LOCAL = 1  /* per-pair subtet rule in float; classification, sample acceptance,
-                             the (exact, integer) sample sums and all global sums as in FP64  */
+                             the (exact, integer) sample sums and all global sums as in FP64.
+                             No faster than NLFEM_FP64 on gfx950: without packed FP32, a float
+                             FMA issues like a double one, and the sample test that dominates
+                             must decide acceptance as the FP64 form does; kept as the
+                             stated-accuracy form (about 1e-7 of the row scale)            */
 } nlfem_precision;
 
 /* Ball approximation strategy (Sec. 4.1: which elements, or element pieces,
@@ -84,9 +88,12 @@ typedef enum {
  * (outer point q = 4 n + k, element m) uses counter
  *   NLFEM_KEY_PAIR:    (q, m, j, 0) -- N samples of its own for every pair;
  *   NLFEM_KEY_ELEMENT: (m, j, 0, 1) -- N samples per element, the same points
- *                      of E_m for every outer point, so one sample stream
- *                      serves all outer points of an outer tet (correlated
- *                      across points, unbiased for each).                     */
+ *                      of E_m for every outer point (correlated across
+ *                      points, unbiased for each).  With the whole-element
+ *                      cap sampling the plan draws them once into a table
+ *                      of 8 bytes per sample and element (K x round8(N + 8)
+ *                      words of device memory held by the plan) that the
+ *                      integration reads instead of drawing per pair.        */
 typedef enum {
     NLFEM_KEY_PAIR = 0,
     NLFEM_KEY_ELEMENT = 1

@@ -11,7 +11,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -89,6 +91,9 @@ struct nlfem_plan {
 
 namespace {
 
+// threads that build the plans of a batch (each with its own stream)
+constexpr int kBuilders = 4;
+
 // scoped temporary device buffer
 struct Tmp {
     nlfem_ctx* c;
@@ -130,15 +135,23 @@ struct Timer {
         }                                                                                         \
     } while (0)
 
+// plan memory comes from the plan's context (pl->ctx), temporaries (TMP) and
+// the stream from the context c that builds it (the same one unless a batch
+// builds its plans on several threads)
 #define ALLOC(ptr, T, n)                                      \
     do {                                                      \
         ptr = pl->alloc<T>((size_t)(n));                      \
-        if (!ptr) return fail(c, NLFEM_E_OOM, c->err);        \
+        if (!ptr) return fail(c, NLFEM_E_OOM, owner_err(pl));  \
     } while (0)
 
 #define TMP(name, bytes)                                       \
     Tmp name(c, (bytes));                                      \
     if (!name.p) return fail(c, NLFEM_E_OOM, c->err)
+
+std::string owner_err(nlfem_plan* pl) {
+    std::lock_guard<std::recursive_mutex> lk(pl->ctx->mu);
+    return pl->ctx->err;
+}
 
 int64_t read_i64(nlfem_ctx* c, const int64_t* dev) {
     hipMemcpyAsync(c->pinned_i, dev, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
@@ -644,14 +657,46 @@ struct nlfem_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<const double*> cap_f, cap_g;
     double last_ms = 0.0;
+    std::mutex owned_mu;  // the plan builders allocate outputs concurrently
     void* alloc(size_t b) {
         void* p = dalloc(ctx, b);
-        if (p) owned.push_back(p);
+        if (p) {
+            std::lock_guard<std::mutex> lk(owned_mu);
+            owned.push_back(p);
+        }
         return p;
     }
 };
 
 namespace {
+
+// Per mesh of a batch, with context c (its stream): the output arrays, the
+// CSR pattern copied into them, and the pairs per outer tet read back (the
+// item costs of the longest-first order) into off.
+nlfem_status batch_mesh_out(nlfem_ctx* c, nlfem_batch* b, nlfem_plan* pl, int i, std::vector<int64_t>& off) {
+    hipStream_t s = c->stream;
+    nlfem_batch::Out& o = b->outs[(size_t)i];
+    const int64_t nf = pl->n_free;
+    o.ff_row_ptr = (int64_t*)b->alloc((size_t)(nf + 1) * 8);
+    o.ff_col = (int32_t*)b->alloc((size_t)(pl->nnz_ff + 1) * 4);
+    o.ff_val = (double*)b->alloc((size_t)(pl->nnz_ff + 1) * 8);
+    o.fc_row_ptr = (int64_t*)b->alloc((size_t)(nf + 1) * 8);
+    o.fc_col = (int32_t*)b->alloc((size_t)(pl->nnz_fc + 1) * 4);
+    o.fc_val = (double*)b->alloc((size_t)(pl->nnz_fc + 1) * 8);
+    o.rhs = (double*)b->alloc((size_t)(nf + 1) * 8);
+    o.f2v = (int32_t*)b->alloc((size_t)(nf + 1) * 4);
+    if (!o.ff_row_ptr || !o.ff_col || !o.ff_val || !o.fc_row_ptr || !o.fc_col || !o.fc_val || !o.rhs || !o.f2v)
+        return fail(c, NLFEM_E_OOM, owner_err(pl));
+    HIPCHK(launch_copy_i64(pl->ff_row_ptr, o.ff_row_ptr, nf + 1, s));
+    HIPCHK(launch_copy_i32(pl->ff_col, o.ff_col, pl->nnz_ff, s));
+    HIPCHK(launch_copy_i64(pl->fc_row_ptr, o.fc_row_ptr, nf + 1, s));
+    HIPCHK(launch_copy_i32(pl->fc_col, o.fc_col, pl->nnz_fc, s));
+    HIPCHK(launch_copy_i32(pl->free_to_vertex, o.f2v, nf, s));
+    off.resize((size_t)pl->n_outer + 1);
+    HIPCHK(hipMemcpyAsync(off.data(), pl->pair_off, off.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return NLFEM_OK;
+}
 
 void batch_free(nlfem_batch* b) {
     if (!b) return;
@@ -822,8 +867,21 @@ nlfem_status nlfem_trim(nlfem_ctx* c) {
     return NLFEM_OK;
 }
 
+namespace {
+nlfem_status plan_create_in(nlfem_ctx* owner, nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem_params* prm,
+                            nlfem_plan** out);
+}  // namespace
+
 nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem_params* prm, nlfem_plan** out) {
     if (!c) return NLFEM_E_INVALID_ARG;
+    return plan_create_in(c, c, mesh, prm, out);
+}
+
+namespace {
+// builds the plan with context c (its stream, temporaries and error text);
+// the plan's own memory belongs to owner
+nlfem_status plan_create_in(nlfem_ctx* owner, nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem_params* prm,
+                            nlfem_plan** out) {
     if (!out || !mesh || !prm) return fail(c, NLFEM_E_INVALID_ARG, "null argument");
     *out = nullptr;
     if (mesh->n_vertices < 0 || mesh->n_tets < 0) return fail(c, NLFEM_E_INVALID_ARG, "negative mesh size");
@@ -847,7 +905,7 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
         return fail(c, NLFEM_E_UNSUPPORTED, "mesh larger than 2^31 entities");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "hipSetDevice failed");
     nlfem_plan* pl = new nlfem_plan();
-    pl->ctx = c;
+    pl->ctx = owner;
     pl->delta = prm->delta;
     pl->psi = prm->psi;
     pl->mc = prm->mc_samples;
@@ -866,6 +924,7 @@ nlfem_status nlfem_plan_create(nlfem_ctx* c, const nlfem_mesh* mesh, const nlfem
     *out = pl;
     return NLFEM_OK;
 }
+}  // namespace
 
 nlfem_status nlfem_plan_info(const nlfem_plan* pl, int64_t* n_free, int64_t* nnz_ff, int64_t* nnz_fc,
                              int64_t pair_counts[5], size_t* workspace_bytes) {
@@ -1031,13 +1090,79 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
         b->n_cu = prop.multiProcessorCount;
         if (prop.maxSharedMemoryPerMultiProcessor > 0) lds_cu = prop.maxSharedMemoryPerMultiProcessor;
     }
-    for (int32_t i = 0; i < n; ++i) {
-        nlfem_plan* pl = nullptr;
-        nlfem_status st = nlfem_plan_create(c, &meshes[i], &params[i], &pl);
-        if (st != NLFEM_OK) {
-            return st;
+    std::vector<std::vector<int64_t>> offs;  // per mesh: its pair_off on the host
+    {
+        // The symbolic phases of the meshes are independent: kBuilders threads
+        // build them, each with a context of its own (stream, temporaries),
+        // taking meshes in turn; the plans' memory belongs to c.  c's cached
+        // blocks must be idle before other streams may take them.
+        const int nb = n >= 8 ? kBuilders : 1;
+        std::vector<nlfem_plan*> plans((size_t)n, nullptr);
+        b->outs.resize((size_t)n);
+        offs.resize((size_t)n);
+        if (nb == 1) {
+            for (int32_t i = 0; i < n; ++i) {
+                nlfem_status st = nlfem_plan_create(c, &meshes[i], &params[i], &plans[(size_t)i]);
+                if (st == NLFEM_OK) st = batch_mesh_out(c, b, plans[(size_t)i], i, offs[(size_t)i]);
+                if (st != NLFEM_OK) {
+                    for (nlfem_plan* pl : plans) nlfem_plan_destroy(pl);
+                    return st;
+                }
+            }
+        } else {
+            if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, NLFEM_E_DEVICE, "stream sync failed");
+            std::atomic<int> next{0};
+            std::atomic<bool> failed{false};
+            std::mutex emu;
+            nlfem_status first = NLFEM_OK;
+            std::string first_msg;
+            auto worker = [&]() {
+                nlfem_status st = NLFEM_OK;
+                std::string msg;
+                hipStream_t ws = nullptr;
+                nlfem_ctx* wc = nullptr;
+                if (hipSetDevice(c->device) != hipSuccess ||
+                    hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+                    (void)hipGetLastError();
+                    st = NLFEM_E_DEVICE;
+                    msg = "could not create a stream for a plan builder";
+                } else if ((st = nlfem_create(&wc, c->device, ws, c->budget)) != NLFEM_OK) {
+                    msg = "could not create a plan builder context";
+                }
+                while (st == NLFEM_OK && !failed.load()) {
+                    const int i = next.fetch_add(1);
+                    if (i >= n) break;
+                    st = plan_create_in(c, wc, &meshes[i], &params[i], &plans[(size_t)i]);
+                    if (st == NLFEM_OK) st = batch_mesh_out(wc, b, plans[(size_t)i], i, offs[(size_t)i]);
+                    if (st != NLFEM_OK) msg = wc->err;
+                }
+                if (wc) {
+                    // its temporaries are idle once its stream has drained: the
+                    // batch's context keeps them (freeing them here would make
+                    // every builder wait for the whole device)
+                    (void)hipStreamSynchronize(ws);
+                    if (!c->pool) adopt_cache(c, wc);
+                    nlfem_destroy(wc);
+                }
+                if (ws) (void)hipStreamDestroy(ws);
+                if (st != NLFEM_OK) {
+                    failed.store(true);
+                    std::lock_guard<std::mutex> lk(emu);
+                    if (first == NLFEM_OK) {
+                        first = st;
+                        first_msg = msg;
+                    }
+                }
+            };
+            std::vector<std::thread> th;
+            for (int w = 0; w < nb; ++w) th.emplace_back(worker);
+            for (auto& t : th) t.join();
+            if (first != NLFEM_OK) {
+                for (nlfem_plan* pl : plans) nlfem_plan_destroy(pl);
+                return fail(c, first, first_msg);
+            }
         }
-        b->plans.push_back(pl);
+        b->plans = plans;
     }
     hipStream_t s = c->stream;
     // resident 256-thread workgroups per CU that the LDS footprint allows,
@@ -1055,34 +1180,13 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
     }
     std::vector<std::vector<int2>> items(b->groups.size());
     std::vector<std::vector<int64_t>> cost(b->groups.size());
-    b->outs.resize(n);
     for (int32_t i = 0; i < n; ++i) {
         nlfem_plan* pl = b->plans[i];
-        nlfem_batch::Out& o = b->outs[i];
-        const int64_t nf = pl->n_free;
-        o.ff_row_ptr = (int64_t*)b->alloc((size_t)(nf + 1) * 8);
-        o.ff_col = (int32_t*)b->alloc((size_t)(pl->nnz_ff + 1) * 4);
-        o.ff_val = (double*)b->alloc((size_t)(pl->nnz_ff + 1) * 8);
-        o.fc_row_ptr = (int64_t*)b->alloc((size_t)(nf + 1) * 8);
-        o.fc_col = (int32_t*)b->alloc((size_t)(pl->nnz_fc + 1) * 4);
-        o.fc_val = (double*)b->alloc((size_t)(pl->nnz_fc + 1) * 8);
-        o.rhs = (double*)b->alloc((size_t)(nf + 1) * 8);
-        o.f2v = (int32_t*)b->alloc((size_t)(nf + 1) * 4);
-        if (!o.ff_row_ptr || !o.ff_col || !o.ff_val || !o.fc_row_ptr || !o.fc_col || !o.fc_val || !o.rhs || !o.f2v) {
-            return fail(c, NLFEM_E_OOM, c->err);
-        }
-        HIPCHK(launch_copy_i64(pl->ff_row_ptr, o.ff_row_ptr, nf + 1, s));
-        HIPCHK(launch_copy_i32(pl->ff_col, o.ff_col, pl->nnz_ff, s));
-        HIPCHK(launch_copy_i64(pl->fc_row_ptr, o.fc_row_ptr, nf + 1, s));
-        HIPCHK(launch_copy_i32(pl->fc_col, o.fc_col, pl->nnz_fc, s));
-        HIPCHK(launch_copy_i32(pl->free_to_vertex, o.f2v, nf, s));
         b->descs.push_back(make_args(pl, nullptr));
         const int g = gid[per_cu(pl->umax)];
         b->groups[g].umax = std::max(b->groups[g].umax, std::max(pl->umax, 1));
         b->groups[g].pairs += pl->P;
-        std::vector<int64_t> off(pl->n_outer + 1);
-        HIPCHK(hipMemcpyAsync(off.data(), pl->pair_off, off.size() * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        const std::vector<int64_t>& off = offs[(size_t)i];
         for (int64_t oi = 0; oi < pl->n_outer; ++oi) {
             items[g].push_back(make_int2(i, (int)oi));
             cost[g].push_back(off[oi + 1] - off[oi]);

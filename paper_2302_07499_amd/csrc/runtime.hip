@@ -97,12 +97,23 @@ nlfem_status fail(nlfem_ctx* c, nlfem_status s, const std::string& msg) {
 size_t round_up(size_t b) { return (b + 255) & ~(size_t)255; }
 
 void release_cache(nlfem_ctx* c) {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     for (auto& kv : c->cache) (void)hipFree(kv.second);
     c->cache.clear();
     c->cached = 0;
 }
 
+void adopt_cache(nlfem_ctx* to, nlfem_ctx* from) {
+    std::lock_guard<std::recursive_mutex> lt(to->mu);
+    std::lock_guard<std::recursive_mutex> lf(from->mu);
+    for (auto& kv : from->cache) to->cache.emplace(kv.first, kv.second);
+    to->cached += from->cached;
+    from->cache.clear();
+    from->cached = 0;
+}
+
 void drain_pending(nlfem_ctx* c) {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     if (!c->pool || c->pending.empty()) return;
     (void)hipStreamSynchronize(c->stream);
     for (auto& b : c->pending) {
@@ -113,6 +124,7 @@ void drain_pending(nlfem_ctx* c) {
 }
 
 void* dalloc(nlfem_ctx* c, size_t bytes) {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     bytes = round_up(bytes ? bytes : 1);
     if (c->pool) {
         if (c->budget && c->live + bytes > c->budget) {
@@ -173,6 +185,7 @@ void* dalloc(nlfem_ctx* c, size_t bytes) {
 
 void dfree(nlfem_ctx* c, void* p) {
     if (!p) return;
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
     auto it = c->sizes.find(p);
     if (it == c->sizes.end()) return;
     size_t sz = it->second;

@@ -45,6 +45,9 @@ struct Pool {
 // shared pool only after the context's stream has drained, since other
 // streams may take them next.
 struct nlfem_ctx {
+    // guards the allocator state below: the plans of a batch are built by
+    // several threads that allocate their plan memory from one context
+    std::recursive_mutex mu;
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0;  // 0 = unlimited
@@ -69,5 +72,8 @@ void* dalloc(nlfem_ctx* c, size_t bytes);
 void dfree(nlfem_ctx* c, void* p);
 // pool mode: waits for the context's stream, then returns freed blocks to the pool
 void drain_pending(nlfem_ctx* c);
+// moves the cached (free, idle) blocks of `from` into the cache of `to`; the
+// caller has drained from's stream (no pool mode on either side)
+void adopt_cache(nlfem_ctx* to, nlfem_ctx* from);
 
 }  // namespace nlfem

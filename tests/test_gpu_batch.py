@@ -149,3 +149,31 @@ def test_batched_workload_subset_vs_oracle(dev, orc):
         _say(f"batched mesh {i} n={pb.mesh.n} d/h={pb.info['delta_over_h']:.0f} fp32-local errors {e}")
         assert e["ff_abs"] <= 1e-5 and e["fc_abs"] <= 1e-5 and e["rhs"] <= 1e-5, (i, e)
     batch.destroy()
+
+
+def test_batch_parallel_build_error_and_recovery(dev):
+    """A batch of nine or more meshes builds its plans on several threads; a
+    mesh with an out-of-range vertex index fails the whole batch with
+    NLFEM_E_MESH (the plans already built are freed), and the context then
+    builds a good batch whose results equal the single-mesh assemblies."""
+    import dataclasses
+    import paper_2302_07499_amd as P
+    pbs = _mix("fp64", count=9, seed=13)
+    bad_tets = pbs[5].mesh.tets.copy()
+    bad_tets[2, 1] = pbs[5].mesh.n_vertices + 3
+    bad = dataclasses.replace(pbs[5], mesh=dataclasses.replace(pbs[5].mesh, tets=bad_tets))
+    before = P.nlfem_memory_in_use(dev.ctx)
+    with pytest.raises(P.NlfemError) as ei:
+        P.Batch(dev, pbs[:5] + [bad] + pbs[6:])
+    assert ei.value.status == P.NLFEM_E_MESH
+    assert P.nlfem_memory_in_use(dev.ctx) <= before + (64 << 20)
+    _say("parallel build error reported; building the good batch")
+    batch = P.Batch(dev, pbs)
+    batch.set_inputs([pb.f_qp for pb in pbs], [pb.g_nodal for pb in pbs])
+    batch.assemble()
+    for i, pb in enumerate(pbs):
+        g = batch.system_numpy(i)
+        e = _eager(dev, pb)
+        for k in ["ff_val", "fc_val", "rhs"]:
+            assert np.array_equal(g[k], e[k]), (i, k)
+    batch.destroy()

@@ -162,7 +162,6 @@ hipError_t launch_exact_g(const IntegrateArgs& a, const double* g_nodal, const d
 // out_S [slots][15], out_qm [slots][3] = (q, m, class)
 hipError_t launch_debug_pairs(const IntegrateArgs& a, bool fp32, int64_t o_lo, int64_t o_hi, double* out_S,
                               int32_t* out_qm, hipStream_t s);
-hipError_t launch_class_counts(const uint16_t* pair_cls, int64_t P, unsigned long long* counts, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_copy_i64(const int64_t* src, int64_t* dst, int64_t n, hipStream_t s);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s);

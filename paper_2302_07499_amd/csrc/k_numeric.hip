@@ -26,16 +26,6 @@ namespace nlfem {
 
 namespace {
 
-__device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int32_t v) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // x is added to a two-word fixed-point sum: the coarse word counts units of
 // 2^-s, the fine word the remainder in units of 2^-(s+48), both two's
 // complement.  The pair (h, l) of one term is the integer nearest to
@@ -84,7 +74,7 @@ constexpr int kChunk = 256;
 // LDS beyond R, T0 and the per-thread T0 words: the chunk's item prefix sums
 // (kChunk + 1 ints, padded to 8 bytes) and its pairs' local vertex positions
 // (kChunk x 4 u16), before Ve
-constexpr size_t kChunkLds = ((size_t)(kChunk + 1) * 4 + 7) / 8 * 8 + (size_t)kChunk * 8;
+constexpr size_t kChunkLds = ((size_t)(kChunk + 1) * 4 + 7) / 8 * 8 + (size_t)kChunk * 8 + (size_t)kChunk * 4 * 2;
 
 // One workgroup of BLOCK threads integrates one outer tet.  LDS: R [4][umax]
 // and T0 [4] as two-word fixed-point sums (coarse words, then fine words),
@@ -119,7 +109,8 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     unsigned long long* T0l = T0 + 4;           // fine   [4]
     unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
     int32_t* cs = (int32_t*)(T0p + 8 * BLOCK);  // [kChunk + 1] item prefix sums of the chunk
-    uint16_t* lvs = (uint16_t*)((char*)cs + (kChunkLds - (size_t)kChunk * 8));  // [kChunk][4]
+    uint16_t* lvs = (uint16_t*)((char*)cs + (kChunkLds - (size_t)kChunk * 16));  // [kChunk][4]
+    uint16_t* ipair = lvs + 4 * kChunk;  // [4 kChunk] the chunk position of the pair of each item
     int32_t* ve_lds = (int32_t*)((char*)cs + kChunkLds);
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
@@ -165,6 +156,8 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             if (lv[j] < U) fx_add(rco(k, lv[j]), rfi(k, lv[j]), fm * S[1 + j], fx);
     };
     const int64_t p0 = a.pair_off[oi], p1 = a.pair_off[oi + 1];
+    int ustep = 1;  // the largest power of two <= U (1 when U = 0)
+    while (2 * ustep <= U) ustep *= 2;
     for (int64_t c0 = p0; c0 < p1; c0 += kChunk) {
         const int nc = (int)(p1 - c0 < (int64_t)kChunk ? p1 - c0 : (int64_t)kChunk);
         // (a) whole pairs: inside points, cut-point counts, local vertex positions
@@ -174,11 +167,18 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
                 const int64_t p = c0 + i;
                 const int m = a.pair_m[p];
                 const uint32_t code = a.pair_cls[p];
-                int lv[4];
-                for (int j = 0; j < 4; ++j) {
-                    lv[j] = lower_bound_i32(ve, U, a.tets[4 * (int64_t)m + j]);
-                    lvs[4 * i + j] = (uint16_t)lv[j];
+                // the four positions by one lock-step binary search (Ve is sorted):
+                // lv[j] = the number of entries below vertex j, each step's four
+                // reads independent of each other
+                int lv[4] = {0, 0, 0, 0};
+                int32_t key[4];
+                for (int j = 0; j < 4; ++j) key[j] = a.tets[4 * (int64_t)m + j];
+                for (int step = ustep; step > 0; step >>= 1) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (lv[j] + step <= U && ve[lv[j] + step - 1] < key[j]) lv[j] += step;
                 }
+                for (int j = 0; j < 4; ++j) lvs[4 * i + j] = (uint16_t)lv[j];
                 const bool omega = a.region[m] != 0;
                 int n_in = 0;
 #pragma unroll 1
@@ -217,6 +217,10 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             if (t == 63) cs[kChunk] = incl;
         }
         __syncthreads();
+        // each pair lists its items' pair position, so that an item finds its pair in one read
+        for (int i = t; i < nc; i += BLOCK)
+            for (int q = cs[i]; q < cs[i + 1]; ++q) ipair[q] = (uint16_t)i;
+        __syncthreads();
         const int n_items = cs[kChunk];
         // (b) the chunk's cut (pair, point) items, one per lane
         for (int ib = 0; ib < n_items; ib += BLOCK) {
@@ -228,14 +232,7 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             int m = 0;
             bool omega = false;
             if (valid) {
-                // the pair: the last chunk position whose prefix is <= it
-                int lo = 0, hi = nc;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (cs[mid] <= it) lo = mid;
-                    else hi = mid;
-                }
-                pi = lo;
+                pi = ipair[it];
                 const int64_t p = c0 + pi;
                 m = a.pair_m[p];
                 const uint32_t code = a.pair_cls[p];
@@ -510,27 +507,6 @@ __global__ void k_copy_i32(const int32_t* a, int32_t* b, int64_t n) {
     if (i < n) b[i] = a[i];
 }
 
-// point-pair totals per class (counts[1..5] = IN, CUT(0..3)): counted in
-// registers, summed across the wave, one atomic per class and wave
-__global__ void k_class_counts(const uint16_t* pair_cls, int64_t P, unsigned long long* counts) {
-    unsigned c[5] = {0u, 0u, 0u, 0u, 0u};
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t code = pair_cls[p];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const unsigned cl = (code >> (3 * k)) & 7u;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) c[q] += (cl == (unsigned)(q + 1)) ? 1u : 0u;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-        for (int off = 32; off > 0; off >>= 1) c[q] += __shfl_xor(c[q], off, 64);
-    if ((threadIdx.x & 63) == 0)
-        for (int q = 0; q < 5; ++q)
-            if (c[q]) atomicAdd(&counts[1 + q], (unsigned long long)c[q]);
-}
-
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -698,12 +674,5 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_class_counts(const uint16_t* pair_cls, int64_t P, unsigned long long* counts, hipStream_t s) {
-    if (P <= 0) return hipSuccess;
-    int64_t b = (P + 255) / 256;
-    if (b > 2048) b = 2048;
-    k_class_counts<<<(unsigned)b, 256, 0, s>>>(pair_cls, P, counts);
-    return hipGetLastError();
-}
 
 }  // namespace nlfem

@@ -74,7 +74,8 @@ constexpr int kChunk = 256;
 // LDS beyond R, T0 and the per-thread T0 words: the chunk's item prefix sums
 // (kChunk + 1 ints, padded to 8 bytes) and its pairs' local vertex positions
 // (kChunk x 4 u16), before Ve
-constexpr size_t kChunkLds = ((size_t)(kChunk + 1) * 4 + 7) / 8 * 8 + (size_t)kChunk * 8 + (size_t)kChunk * 4 * 2;
+constexpr size_t kChunkLds =
+    ((size_t)(kChunk + 1) * 4 + 7) / 8 * 8 + (size_t)kChunk * 8 + (size_t)kChunk * 4 * 2 + (size_t)kChunk * 6;
 
 // One workgroup of BLOCK threads integrates one outer tet.  LDS: R [4][umax]
 // and T0 [4] as two-word fixed-point sums (coarse words, then fine words),
@@ -109,8 +110,10 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
     unsigned long long* T0l = T0 + 4;           // fine   [4]
     unsigned long long* T0p = T0l + 4;          // per thread [4][2][BLOCK]
     int32_t* cs = (int32_t*)(T0p + 8 * BLOCK);  // [kChunk + 1] item prefix sums of the chunk
-    uint16_t* lvs = (uint16_t*)((char*)cs + (kChunkLds - (size_t)kChunk * 16));  // [kChunk][4]
-    uint16_t* ipair = lvs + 4 * kChunk;  // [4 kChunk] the chunk position of the pair of each item
+    uint16_t* lvs = (uint16_t*)((char*)cs + (kChunkLds - (size_t)kChunk * 22));  // [kChunk][4]
+    uint16_t* ipair = lvs + 4 * kChunk;  // [4 kChunk] per item: its pair's chunk position (| point << 14)
+    int32_t* pm = (int32_t*)(ipair + 4 * kChunk);  // [kChunk] inner tet of each pair
+    uint16_t* pcl = (uint16_t*)(pm + kChunk);      // [kChunk] class code | T_Omega << 15
     int32_t* ve_lds = (int32_t*)((char*)cs + kChunkLds);
     const int n = a.outer_ids[oi];
     const int64_t vb = a.ve_off[oi];
@@ -180,6 +183,10 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
                 }
                 for (int j = 0; j < 4; ++j) lvs[4 * i + j] = (uint16_t)lv[j];
                 const bool omega = a.region[m] != 0;
+                if constexpr (KEY == 0) {
+                    pm[i] = m;
+                    pcl[i] = (uint16_t)(code | (omega ? 0x8000u : 0u));
+                }
                 int n_in = 0;
 #pragma unroll 1
                 for (int k = 0; k < 4; ++k) {
@@ -217,9 +224,18 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             if (t == 63) cs[kChunk] = incl;
         }
         __syncthreads();
-        // each pair lists its items' pair position, so that an item finds its pair in one read
-        for (int i = t; i < nc; i += BLOCK)
-            for (int q = cs[i]; q < cs[i + 1]; ++q) ipair[q] = (uint16_t)i;
+        // each pair lists its items (pair position, cut point), so that an item
+        // finds both in one read
+        for (int i = t; i < nc; i += BLOCK) {
+            if constexpr (KEY == 0) {
+                const uint32_t code = pcl[i];
+                int q = cs[i];
+                for (int kk = 0; kk < 4; ++kk)
+                    if (((code >> (3 * kk)) & 7u) >= (uint32_t)C_CUT0) ipair[q++] = (uint16_t)(i | (kk << 14));
+            } else {
+                for (int q = cs[i]; q < cs[i + 1]; ++q) ipair[q] = (uint16_t)i;
+            }
+        }
         __syncthreads();
         const int n_items = cs[kChunk];
         // (b) the chunk's cut (pair, point) items, one per lane
@@ -232,15 +248,28 @@ __device__ __forceinline__ void integrate_outer(const A& a, int64_t oi, unsigned
             int m = 0;
             bool omega = false;
             if (valid) {
-                pi = ipair[it];
-                const int64_t p = c0 + pi;
-                m = a.pair_m[p];
-                const uint32_t code = a.pair_cls[p];
-                unsigned cm = 0u;
-                for (int kk = 0; kk < 4; ++kk) cm |= (((code >> (3 * kk)) & 7u) >= (uint32_t)C_CUT0 ? 1u : 0u) << kk;
-                const int k = nth_bit(cm, it - cs[pi]);
+                // pair keying takes the pair's tet, class and the item's cut point
+                // from LDS; element keying reads them again (its table-fed sample
+                // loop measured faster with the register allocation this gives)
+                int k;
+                if constexpr (KEY == 0) {
+                    const uint32_t ik = ipair[it];
+                    pi = (int)(ik & 0x3FFFu);
+                    k = (int)(ik >> 14);
+                    m = pm[pi];
+                    omega = (pcl[pi] & 0x8000u) != 0;
+                } else {
+                    pi = ipair[it];
+                    const int64_t p = c0 + pi;
+                    m = a.pair_m[p];
+                    const uint32_t code = a.pair_cls[p];
+                    unsigned cm = 0u;
+                    for (int kk = 0; kk < 4; ++kk)
+                        cm |= (((code >> (3 * kk)) & 7u) >= (uint32_t)C_CUT0 ? 1u : 0u) << kk;
+                    k = nth_bit(cm, it - cs[pi]);
+                    omega = a.region[m] != 0;
+                }
                 const double volm = a.vol[m];
-                omega = a.region[m] != 0;
                 int lv[4];
                 for (int j = 0; j < 4; ++j) lv[j] = lvs[4 * pi + j];
                 const double* X = a.tetX + 12 * (int64_t)m;

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <string>
@@ -419,11 +420,15 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     TMP(t_nff, (size_t)(nf + 2) * 8);
     TMP(t_nfc, (size_t)(nf + 2) * 8);
     int row_cap = (int)std::max<int64_t>(512, next_pow2(4 * (int64_t)std::max(pl->umax, 1)));
+    std::unique_ptr<Tmp> t_rows;  // [nf][row_cap] each row's columns between the two passes
     while (true) {
         if ((size_t)row_cap * 4 + 2048 > c->lds_max) return fail(c, NLFEM_E_UNSUPPORTED, "matrix row too large for LDS");
+        t_rows.reset();
+        t_rows.reset(new Tmp(c, (size_t)std::max<int64_t>(nf, 1) * (size_t)row_cap * 4));
+        if (!t_rows->p) return fail(c, NLFEM_E_OOM, c->err);
         HIPCHK(launch_fill_i32((int32_t*)t_err.p, 16, 0, s));
         HIPCHK(launch_row_pattern(false, rp, nf, row_cap, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), nullptr, nullptr,
-                                  nullptr, nullptr, nullptr, t_err.as<unsigned>(), s));
+                                  nullptr, nullptr, nullptr, t_rows->as<uint32_t>(), t_err.as<unsigned>(), s));
         HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (!(errbits & ERR_HASH)) break;
@@ -450,8 +455,10 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     ALLOC(pl->fc_col, int32_t, pl->nnz_fc + 1);
     ALLOC(pl->all_cols, int32_t, pl->nnz_ff + pl->nnz_fc + 1);
     HIPCHK(launch_row_pattern(true, rp, nf, row_cap, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), pl->ff_row_ptr,
-                              pl->fc_row_ptr, pl->all_cols, pl->ff_col, pl->fc_col, t_err.as<unsigned>(), s));
+                              pl->fc_row_ptr, pl->all_cols, pl->ff_col, pl->fc_col, t_rows->as<uint32_t>(),
+                              t_err.as<unsigned>(), s));
     HIPCHK(hipStreamSynchronize(s));
+    t_rows.reset();
     pl->times[2] = tpat.stop();
     // ---- numeric workspace -------------------------------------------------
     ALLOC(pl->cblk, double, 4 * VT + 4);

@@ -208,9 +208,12 @@ hipError_t launch_inner_count(const int64_t* pair_off, int64_t n_outer, const in
 hipError_t launch_outer_pos(const int32_t* outer_ids, int64_t n_outer, int32_t* outer_pos, int64_t K, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// CSR pattern, count pass (fill = false: n_ff / n_fc per row, the columns
+// left unordered in rowbuf [n_rows][hash_cap]) then fill pass (fill = true,
+// the same rowbuf and counts)
 hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int64_t* n_ff,
                               int64_t* n_fc, const int64_t* ff_row_ptr, const int64_t* fc_row_ptr, int32_t* all_cols,
-                              int32_t* ff_col, int32_t* fc_col, unsigned* err, hipStream_t s);
+                              int32_t* ff_col, int32_t* fc_col, uint32_t* rowbuf, unsigned* err, hipStream_t s);
 hipError_t launch_g_finalize(int64_t K, const uint8_t* region, const int32_t* inner_cnt, const double* vol,
                              const unsigned long long* gacc, int g_shift, int w_shift, double* gvals, hipStream_t s);
 size_t row_assemble_lds_bytes(int max_row);  // dynamic part

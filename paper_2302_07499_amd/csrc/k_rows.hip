@@ -124,94 +124,14 @@ __device__ __forceinline__ void hset_insert(uint32_t* hs, uint32_t mask, uint32_
 // One block per free row: the sorted column set (vertex ids) of the row.
 // Count pass writes the numbers of free / constrained columns; fill pass
 // writes all columns (vertex ids) at all_off and the split ff/fc columns.
-template <bool FILL>
-__global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, int64_t* n_ff, int64_t* n_fc,
-                                                     const int64_t* ff_row_ptr, const int64_t* fc_row_ptr,
-                                                     int32_t* all_cols, int32_t* ff_col, int32_t* fc_col,
-                                                     unsigned* err) {
-    extern __shared__ uint32_t hs[];
-    __shared__ int sU, sF;
-    const int64_t r = blockIdx.x;
+// fill pass of a row: hs holds its U columns in its first n2 slots (n2 a
+// power of two >= U, the rest EMPTY); sorted by a bitonic network, then
+// written to the ff / fc rows with their ranks
+__device__ __forceinline__ void row_pattern_fill(const RowPlan& rp, int64_t r, int U, int n2, uint32_t* hs,
+                                                 const int64_t* ff_row_ptr, const int64_t* fc_row_ptr,
+                                                 int32_t* all_cols, int32_t* ff_col, int32_t* fc_col) {
     const int t = threadIdx.x;
-    const int32_t u = rp.free_to_vertex[r];
-    const uint32_t mask = (uint32_t)hash_cap - 1u;
-    for (int i = t; i < hash_cap; i += 256) hs[i] = 0xFFFFFFFFu;
-    if (t == 0) {
-        sU = 0;
-        sF = 0;
-    }
-    __syncthreads();
-    // direct: ball vertex sets of outer tets containing u; inner-element
-    // terms: vertices of T_Omega tets containing u that occur in some ball
-    for (int64_t e4 = rp.vt_off[u]; e4 < rp.vt_off[u + 1]; ++e4) {
-        const int64_t tl = rp.vt_val[e4];
-        const int64_t e = tl >> 2;
-        const int32_t oi = rp.outer_pos[e];
-        if (oi >= 0)
-            for (int64_t g = rp.ve_off[oi] + t; g < rp.ve_off[oi + 1]; g += 256)
-                hset_insert(hs, mask, (uint32_t)rp.ve_ids[g], err);
-        if (rp.region[e] && rp.inner_cnt[e] > 0 && t < 4) hset_insert(hs, mask, (uint32_t)rp.tets[4 * e + t], err);
-    }
-    // transposed: vertices of outer tets whose ball vertex set contains u
-    for (int64_t k = rp.inc_off[u] + t; k < rp.inc_off[u + 1]; k += 256) {
-        const int32_t oi = rp.ve_owner[rp.inc_val[k]];
-        const int64_t n = rp.outer_ids[oi];
-        for (int j = 0; j < 4; ++j) hset_insert(hs, mask, (uint32_t)rp.tets[4 * n + j], err);
-    }
-    __syncthreads();
-    if (!FILL) {
-        // the count pass needs no order: the filled slots, and the free ones among them
-        int nu = 0, nf = 0;
-        for (int i = t; i < hash_cap; i += 256) {
-            const uint32_t v = hs[i];
-            if (v != 0xFFFFFFFFu) {
-                ++nu;
-                nf += rp.free_id[v] >= 0 ? 1 : 0;
-            }
-        }
-        atomicAdd(&sU, nu);
-        atomicAdd(&sF, nf);
-        __syncthreads();
-        if (t == 0) {
-            n_ff[r] = sF;
-            n_fc[r] = sU - sF;
-        }
-        return;
-    }
-    // fill: the filled slots moved to the front, so that the bitonic sort runs
-    // over the first power of two that holds them instead of the whole table
-    // (tables of at most 256 kSlots entries; a larger one is sorted whole)
     __shared__ int csum[256];
-    constexpr int kSlots = 32;
-    int n2 = hash_cap, U = -1;
-    if (hash_cap <= 256 * kSlots) {
-        uint32_t mine[kSlots];
-        int nm = 0;
-#pragma unroll
-        for (int q = 0; q < kSlots; ++q) {
-            const int i = t + 256 * q;
-            mine[q] = i < hash_cap ? hs[i] : 0xFFFFFFFFu;
-            nm += mine[q] != 0xFFFFFFFFu ? 1 : 0;
-        }
-        csum[t] = nm;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const int add = t >= off ? csum[t - off] : 0;
-            __syncthreads();
-            csum[t] += add;
-            __syncthreads();
-        }
-        U = csum[255];
-        n2 = 1;
-        while (n2 < U) n2 <<= 1;
-        int at = csum[t] - nm;
-        __syncthreads();  // every slot is read before the front is overwritten
-#pragma unroll
-        for (int q = 0; q < kSlots; ++q)
-            if (mine[q] != 0xFFFFFFFFu) hs[at++] = mine[q];
-        for (int i = U + t; i < n2; i += 256) hs[i] = 0xFFFFFFFFu;
-    }
-    __syncthreads();
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = t; i < n2; i += 256) {
@@ -227,12 +147,6 @@ __global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, i
             }
             __syncthreads();
         }
-    }
-    if (U < 0) {  // the whole table was sorted: the filled slots end where EMPTY starts
-        for (int i = t; i < hash_cap; i += 256)
-            if (hs[i] != 0xFFFFFFFFu && (i == hash_cap - 1 || hs[i + 1] == 0xFFFFFFFFu)) sU = i + 1;
-        __syncthreads();
-        U = sU;
     }
     // fill: ranks among free / constrained columns by a block scan over chunks
     const int64_t ab = ff_row_ptr[r] + fc_row_ptr[r];
@@ -264,6 +178,74 @@ __global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, i
     }
 }
 
+
+// The count pass inserts the row's columns into an LDS hash set, counts them
+// (free / constrained) and leaves them, unordered, in rowbuf (row r at
+// r * hash_cap); the fill pass sorts them from there and writes the CSR rows.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, int64_t* n_ff, int64_t* n_fc,
+                                                     const int64_t* ff_row_ptr, const int64_t* fc_row_ptr,
+                                                     int32_t* all_cols, int32_t* ff_col, int32_t* fc_col,
+                                                     uint32_t* rowbuf, unsigned* err) {
+    extern __shared__ uint32_t hs[];
+    __shared__ int sU, sF;
+    const int64_t r = blockIdx.x;
+    const int t = threadIdx.x;
+    uint32_t* rb = rowbuf + r * (int64_t)hash_cap;
+    if constexpr (FILL) {
+        // the row's columns as the count pass left them, padded to a power of
+        // two with EMPTY for the sort
+        const int U = (int)(n_ff[r] + n_fc[r]);
+        int n2 = 1;
+        while (n2 < U) n2 <<= 1;
+        for (int i = t; i < n2; i += 256) hs[i] = i < U ? rb[i] : 0xFFFFFFFFu;
+        __syncthreads();
+        row_pattern_fill(rp, r, U, n2, hs, ff_row_ptr, fc_row_ptr, all_cols, ff_col, fc_col);
+        return;
+    }
+    const int32_t u = rp.free_to_vertex[r];
+    const uint32_t mask = (uint32_t)hash_cap - 1u;
+    for (int i = t; i < hash_cap; i += 256) hs[i] = 0xFFFFFFFFu;
+    if (t == 0) {
+        sU = 0;
+        sF = 0;
+    }
+    __syncthreads();
+    // direct: ball vertex sets of outer tets containing u; inner-element
+    // terms: vertices of T_Omega tets containing u that occur in some ball
+    for (int64_t e4 = rp.vt_off[u]; e4 < rp.vt_off[u + 1]; ++e4) {
+        const int64_t tl = rp.vt_val[e4];
+        const int64_t e = tl >> 2;
+        const int32_t oi = rp.outer_pos[e];
+        if (oi >= 0)
+            for (int64_t g = rp.ve_off[oi] + t; g < rp.ve_off[oi + 1]; g += 256)
+                hset_insert(hs, mask, (uint32_t)rp.ve_ids[g], err);
+        if (rp.region[e] && rp.inner_cnt[e] > 0 && t < 4) hset_insert(hs, mask, (uint32_t)rp.tets[4 * e + t], err);
+    }
+    // transposed: vertices of outer tets whose ball vertex set contains u
+    for (int64_t k = rp.inc_off[u] + t; k < rp.inc_off[u + 1]; k += 256) {
+        const int32_t oi = rp.ve_owner[rp.inc_val[k]];
+        const int64_t n = rp.outer_ids[oi];
+        for (int j = 0; j < 4; ++j) hset_insert(hs, mask, (uint32_t)rp.tets[4 * n + j], err);
+    }
+    __syncthreads();
+    // the filled slots to rowbuf in any order (the fill pass sorts them), and
+    // the free ones among them counted
+    int nf = 0;
+    for (int i = t; i < hash_cap; i += 256) {
+        const uint32_t v = hs[i];
+        if (v != 0xFFFFFFFFu) {
+            rb[atomicAdd(&sU, 1)] = v;
+            nf += rp.free_id[v] >= 0 ? 1 : 0;
+        }
+    }
+    atomicAdd(&sF, nf);
+    __syncthreads();
+    if (t == 0) {
+        n_ff[r] = sF;
+        n_fc[r] = sU - sF;
+    }
+}
 __device__ __forceinline__ int bsearch_cols(const int32_t* c, int n, int32_t v) {
     int lo = 0, hi = n;
     while (lo < hi) {
@@ -525,15 +507,15 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s) {
 
 hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int64_t* n_ff,
                               int64_t* n_fc, const int64_t* ff_row_ptr, const int64_t* fc_row_ptr, int32_t* all_cols,
-                              int32_t* ff_col, int32_t* fc_col, unsigned* err, hipStream_t s) {
+                              int32_t* ff_col, int32_t* fc_col, uint32_t* rowbuf, unsigned* err, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
     size_t sh = (size_t)hash_cap * 4;
     if (fill)
         k_row_pattern<true><<<(unsigned)n_rows, 256, sh, s>>>(rp, hash_cap, n_ff, n_fc, ff_row_ptr, fc_row_ptr, all_cols,
-                                                            ff_col, fc_col, err);
+                                                            ff_col, fc_col, rowbuf, err);
     else
         k_row_pattern<false><<<(unsigned)n_rows, 256, sh, s>>>(rp, hash_cap, n_ff, n_fc, ff_row_ptr, fc_row_ptr,
-                                                             all_cols, ff_col, fc_col, err);
+                                                             all_cols, ff_col, fc_col, rowbuf, err);
     return hipGetLastError();
 }
 

@@ -281,9 +281,10 @@ typedef struct nlfem_batch nlfem_batch;
  * follow mem_kind).  All params must use the same precision, cap sampling and
  * keying.  With 8 or more meshes the symbolic phases run on 4 host threads,
  * each with a stream of its own (the call waits for ctx's stream first and
- * returns when all are done); the plans' memory is ctx's either way.  If any
- * mesh fails, every plan built so far is freed and the first failure is
- * returned (message via nlfem_last_error).                                    */
+ * returns when all are done); the plans' memory is ctx's either way, and
+ * after a successful build ctx's cache keeps the threads' temporaries.  If
+ * any mesh fails, every plan built so far and the threads' temporaries are
+ * freed and the first failure is returned (message via nlfem_last_error).     */
 nlfem_status nlfem_batch_create(nlfem_ctx *ctx, int32_t n, const nlfem_mesh *meshes,
                                 const nlfem_params *params, nlfem_batch **batch);
 nlfem_status nlfem_batch_info(const nlfem_batch *batch, int32_t i, int64_t *n_free, int64_t *nnz_ff,

@@ -419,20 +419,31 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     RowPlan rp = make_row_plan(pl);
     TMP(t_nff, (size_t)(nf + 2) * 8);
     TMP(t_nfc, (size_t)(nf + 2) * 8);
+    // hash capacity per row (4 |Ve| slots at least), and the row buffer's
+    // stride: half the hash set first (the widest rows hold somewhat more
+    // than |Ve| columns), doubled (the count pass run again) if a row does
+    // not fit
     int row_cap = (int)std::max<int64_t>(512, next_pow2(4 * (int64_t)std::max(pl->umax, 1)));
-    std::unique_ptr<Tmp> t_rows;  // [nf][row_cap] each row's columns between the two passes
+    int row_stride = row_cap / 2;
+    std::unique_ptr<Tmp> t_rows;  // [nf][row_stride] each row's columns between the two passes
     while (true) {
         if ((size_t)row_cap * 4 + 2048 > c->lds_max) return fail(c, NLFEM_E_UNSUPPORTED, "matrix row too large for LDS");
         t_rows.reset();
-        t_rows.reset(new Tmp(c, (size_t)std::max<int64_t>(nf, 1) * (size_t)row_cap * 4));
+        t_rows.reset(new Tmp(c, (size_t)std::max<int64_t>(nf, 1) * (size_t)row_stride * 4));
         if (!t_rows->p) return fail(c, NLFEM_E_OOM, c->err);
         HIPCHK(launch_fill_i32((int32_t*)t_err.p, 16, 0, s));
-        HIPCHK(launch_row_pattern(false, rp, nf, row_cap, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), nullptr, nullptr,
-                                  nullptr, nullptr, nullptr, t_rows->as<uint32_t>(), t_err.as<unsigned>(), s));
+        HIPCHK(launch_row_pattern(false, rp, nf, row_cap, row_stride, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), nullptr,
+                                  nullptr, nullptr, nullptr, nullptr, t_rows->as<uint32_t>(), t_err.as<unsigned>(), s));
         HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (!(errbits & ERR_HASH)) break;
-        row_cap *= 2;
+        if (errbits & ERR_HASH) {
+            row_cap *= 2;
+            row_stride = std::max(row_stride, row_cap / 2);
+        } else if (errbits & ERR_ROWBUF) {
+            row_stride *= 2;  // at most row_cap: a row never holds more columns than its hash set
+        } else {
+            break;
+        }
     }
     ALLOC(pl->ff_row_ptr, int64_t, nf + 2);
     ALLOC(pl->fc_row_ptr, int64_t, nf + 2);
@@ -454,7 +465,7 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     ALLOC(pl->ff_col, int32_t, pl->nnz_ff + 1);
     ALLOC(pl->fc_col, int32_t, pl->nnz_fc + 1);
     ALLOC(pl->all_cols, int32_t, pl->nnz_ff + pl->nnz_fc + 1);
-    HIPCHK(launch_row_pattern(true, rp, nf, row_cap, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), pl->ff_row_ptr,
+    HIPCHK(launch_row_pattern(true, rp, nf, row_cap, row_stride, t_nff.as<int64_t>(), t_nfc.as<int64_t>(), pl->ff_row_ptr,
                               pl->fc_row_ptr, pl->all_cols, pl->ff_col, pl->fc_col, t_rows->as<uint32_t>(),
                               t_err.as<unsigned>(), s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1123,11 +1134,14 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
             std::mutex emu;
             nlfem_status first = NLFEM_OK;
             std::string first_msg;
-            auto worker = [&]() {
+            // each builder's context and stream, kept until all have ended
+            std::vector<nlfem_ctx*> wctx((size_t)nb, nullptr);
+            std::vector<hipStream_t> wstream((size_t)nb, nullptr);
+            auto worker = [&](int w) {
                 nlfem_status st = NLFEM_OK;
                 std::string msg;
-                hipStream_t ws = nullptr;
-                nlfem_ctx* wc = nullptr;
+                hipStream_t& ws = wstream[(size_t)w];
+                nlfem_ctx*& wc = wctx[(size_t)w];
                 if (hipSetDevice(c->device) != hipSuccess ||
                     hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
                     (void)hipGetLastError();
@@ -1143,15 +1157,8 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
                     if (st == NLFEM_OK) st = batch_mesh_out(wc, b, plans[(size_t)i], i, offs[(size_t)i]);
                     if (st != NLFEM_OK) msg = wc->err;
                 }
-                if (wc) {
-                    // its temporaries are idle once its stream has drained: the
-                    // batch's context keeps them (freeing them here would make
-                    // every builder wait for the whole device)
-                    (void)hipStreamSynchronize(ws);
-                    if (!c->pool) adopt_cache(c, wc);
-                    nlfem_destroy(wc);
-                }
-                if (ws) (void)hipStreamDestroy(ws);
+                // its temporaries are idle once its stream has drained
+                if (ws) (void)hipStreamSynchronize(ws);
                 if (st != NLFEM_OK) {
                     failed.store(true);
                     std::lock_guard<std::mutex> lk(emu);
@@ -1162,8 +1169,20 @@ nlfem_status nlfem_batch_create(nlfem_ctx* c, int32_t n, const nlfem_mesh* meshe
                 }
             };
             std::vector<std::thread> th;
-            for (int w = 0; w < nb; ++w) th.emplace_back(worker);
+            for (int w = 0; w < nb; ++w) th.emplace_back(worker, w);
             for (auto& t : th) t.join();
+            // after a build that succeeded, the batch's context keeps the
+            // builders' cached temporaries (freeing them while the builders
+            // ran would have made each wait for the whole device); after a
+            // failure they go back to the device with the builders' contexts
+            for (int w = 0; w < nb; ++w) {
+                nlfem_ctx* wc = wctx[(size_t)w];
+                if (wc) {
+                    if (first == NLFEM_OK && !c->pool) adopt_cache(c, wc);
+                    nlfem_destroy(wc);
+                }
+                if (wstream[(size_t)w]) (void)hipStreamDestroy(wstream[(size_t)w]);
+            }
             if (first != NLFEM_OK) {
                 for (nlfem_plan* pl : plans) nlfem_plan_destroy(pl);
                 return fail(c, first, first_msg);

@@ -32,7 +32,7 @@ struct Grid {
 };
 
 // Error bits raised by device validation.
-enum : unsigned { ERR_INDEX = 1u, ERR_VOLUME = 2u, ERR_REGION = 4u, ERR_HASH = 8u, ERR_FIXED = 16u };
+enum : unsigned { ERR_INDEX = 1u, ERR_VOLUME = 2u, ERR_REGION = 4u, ERR_HASH = 8u, ERR_FIXED = 16u, ERR_ROWBUF = 32u };
 
 // ---- launch wrappers (each returns the hipError_t of its launch) ----------
 // scans / sorts (k_sort.hip)
@@ -211,7 +211,7 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // CSR pattern, count pass (fill = false: n_ff / n_fc per row, the columns
 // left unordered in rowbuf [n_rows][hash_cap]) then fill pass (fill = true,
 // the same rowbuf and counts)
-hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int64_t* n_ff,
+hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int row_stride, int64_t* n_ff,
                               int64_t* n_fc, const int64_t* ff_row_ptr, const int64_t* fc_row_ptr, int32_t* all_cols,
                               int32_t* ff_col, int32_t* fc_col, uint32_t* rowbuf, unsigned* err, hipStream_t s);
 hipError_t launch_g_finalize(int64_t K, const uint8_t* region, const int32_t* inner_cnt, const double* vol,

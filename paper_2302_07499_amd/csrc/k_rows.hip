@@ -181,9 +181,11 @@ __device__ __forceinline__ void row_pattern_fill(const RowPlan& rp, int64_t r, i
 
 // The count pass inserts the row's columns into an LDS hash set, counts them
 // (free / constrained) and leaves them, unordered, in rowbuf (row r at
-// r * hash_cap); the fill pass sorts them from there and writes the CSR rows.
+// r * row_stride; a row with more columns than row_stride sets ERR_ROWBUF and
+// the host runs the pass again with a wider stride); the fill pass sorts them
+// from there (LDS: row_stride words, a power of two) and writes the CSR rows.
 template <bool FILL>
-__global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, int64_t* n_ff, int64_t* n_fc,
+__global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, int row_stride, int64_t* n_ff, int64_t* n_fc,
                                                      const int64_t* ff_row_ptr, const int64_t* fc_row_ptr,
                                                      int32_t* all_cols, int32_t* ff_col, int32_t* fc_col,
                                                      uint32_t* rowbuf, unsigned* err) {
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, i
     __shared__ int sU, sF;
     const int64_t r = blockIdx.x;
     const int t = threadIdx.x;
-    uint32_t* rb = rowbuf + r * (int64_t)hash_cap;
+    uint32_t* rb = rowbuf + r * (int64_t)row_stride;
     if constexpr (FILL) {
         // the row's columns as the count pass left them, padded to a power of
         // two with EMPTY for the sort
@@ -235,7 +237,9 @@ __global__ __launch_bounds__(256) void k_row_pattern(RowPlan rp, int hash_cap, i
     for (int i = t; i < hash_cap; i += 256) {
         const uint32_t v = hs[i];
         if (v != 0xFFFFFFFFu) {
-            rb[atomicAdd(&sU, 1)] = v;
+            const int q = atomicAdd(&sU, 1);
+            if (q < row_stride) rb[q] = v;
+            else atomicOr(err, ERR_ROWBUF);
             nf += rp.free_id[v] >= 0 ? 1 : 0;
         }
     }
@@ -505,17 +509,19 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int64_t* n_ff,
+hipError_t launch_row_pattern(bool fill, const RowPlan& rp, int64_t n_rows, int hash_cap, int row_stride, int64_t* n_ff,
                               int64_t* n_fc, const int64_t* ff_row_ptr, const int64_t* fc_row_ptr, int32_t* all_cols,
                               int32_t* ff_col, int32_t* fc_col, uint32_t* rowbuf, unsigned* err, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
-    size_t sh = (size_t)hash_cap * 4;
+    // the stride must be a power of two no larger than the hash set (the fill
+    // pass sorts a row in row_stride words of LDS)
+    if (row_stride <= 0 || row_stride > hash_cap || (row_stride & (row_stride - 1)) != 0) return hipErrorInvalidValue;
     if (fill)
-        k_row_pattern<true><<<(unsigned)n_rows, 256, sh, s>>>(rp, hash_cap, n_ff, n_fc, ff_row_ptr, fc_row_ptr, all_cols,
-                                                            ff_col, fc_col, rowbuf, err);
+        k_row_pattern<true><<<(unsigned)n_rows, 256, (size_t)row_stride * 4, s>>>(
+            rp, hash_cap, row_stride, n_ff, n_fc, ff_row_ptr, fc_row_ptr, all_cols, ff_col, fc_col, rowbuf, err);
     else
-        k_row_pattern<false><<<(unsigned)n_rows, 256, sh, s>>>(rp, hash_cap, n_ff, n_fc, ff_row_ptr, fc_row_ptr,
-                                                             all_cols, ff_col, fc_col, rowbuf, err);
+        k_row_pattern<false><<<(unsigned)n_rows, 256, (size_t)hash_cap * 4, s>>>(
+            rp, hash_cap, row_stride, n_ff, n_fc, ff_row_ptr, fc_row_ptr, all_cols, ff_col, fc_col, rowbuf, err);
     return hipGetLastError();
 }
 

@@ -106,10 +106,10 @@ size_t estimate_footprint(const Request& r) {
                        r.prm.cap_sampling != NLFEM_CAPS_OUTSIDE_UI;
     const double stab = table ? (double)K * 8.0 * (double)sample_table_stride(r.prm.mc_samples) : 0.0;
     const double retained = P * 6.0 + VT * 44.0 + n_outer * 200.0 + nnz * 20.0 + nf * 64.0 + stab;
-    // the CSR pattern keeps each row's columns between its two passes: a
-    // power-of-two slot of at least 4 |Ve| words per free row
+    // the CSR pattern keeps each row's columns between its two passes: half
+    // the row's hash set (a power of two of at least 4 |Ve| slots)
     const double rowcap = std::max(512.0, std::exp2(std::ceil(std::log2(4.0 * std::max(vpo, 1.0)))));
-    const double pattern = retained + VT * 24.0 + (double)nf * rowcap * 4.0;
+    const double pattern = retained + VT * 24.0 + (double)nf * (rowcap / 2.0) * 4.0;
     const double numeric = retained + nnz * 12.0 + nf * 48.0;
     const double est = (mesh + std::max(classify, std::max(pattern, numeric))) * 1.25 + (double)(8 << 20);
     return (size_t)std::min(est, 1e18);

@@ -506,8 +506,13 @@ def run_serving(P, mg, args, count, fractions):
     pairs = sum(sum(i["pair_counts"]) for i in infos)
     ok = [i for i in infos if i["state"] == 2]
     sat_rate = len(ok) / makespan
+    # the largest request (most point pairs) and its service time under the full queue
+    big = max(ok, key=lambda i: sum(i["pair_counts"])) if ok else None
     out["saturation"] = {"requests_per_s": round(sat_rate, 3), "pairs_per_s": round(pairs / makespan, 1),
-                         "makespan_s": round(makespan, 2), "failed": len(infos) - len(ok)}
+                         "makespan_s": round(makespan, 2), "failed": len(infos) - len(ok),
+                         "largest_request_pairs": int(sum(big["pair_counts"])) if big else 0,
+                         "largest_request_service_ms": round(1e3 * (big["latency_s"] - big["queue_s"]), 1)
+                         if big else None}
     est = np.array([i["est_bytes"] for i in infos], dtype=float)
     peak = np.array([max(i["peak_bytes"], 1) for i in infos], dtype=float)
     out["footprint_est_over_peak"] = {"min": round(float(np.min(est / peak)), 2),
@@ -529,10 +534,13 @@ def run_serving(P, mg, args, count, fractions):
         infos = collect(tickets)
         wall = time.perf_counter() - t0
         lat = [1e3 * i["latency_s"] for i in infos if i["state"] == 2]
+        # service time: admission to completion (plan, assembly, CG), without the queueing
+        svc = [1e3 * (i["latency_s"] - i["queue_s"]) for i in infos if i["state"] == 2]
         pairs = sum(sum(i["pair_counts"]) for i in infos)
         st = sv.stats()
         out[f"poisson_{frac:g}x"] = {
             "rate_per_s": round(rate, 3), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "service_p50_ms": pct(svc, 50), "service_p99_ms": pct(svc, 99),
             "mean_queue_ms": round(1e3 * float(np.mean([i["queue_s"] for i in infos])), 2),
             "requests_per_s": round(len(lat) / wall, 3), "pairs_per_s": round(pairs / wall, 1),
             "max_running": st["max_running"], "failed": len(infos) - len(lat)}

@@ -786,7 +786,9 @@ __device__ inline void region_fold(const CornerGeom* cr, int j, double vol, int 
 }
 
 // The Monte Carlo part of a cut pair, over samples 0 <= s < N (Philox
-// counters of mc_philox<KEY>, two samples per call): uniform on E_m, those in
+// counters of mc_philox<KEY>, two samples per call; the whole-element loop
+// makes two independent calls per iteration, and the sums are exact integers,
+// so the loop's shape does not change them): uniform on E_m, those in
 // U_I rejected; or, with the cap region on (VR, cr->n > 0), sub-tet j of n
 // takes the samples floor(j N / n) <= s < floor((j + 1) N / n), N_j of them
 // (N >= 3), with weight |T_j| / N_j and no U_I test, and its moments in the
@@ -836,14 +838,15 @@ __device__ inline void cut_mc(const double* X, double vol, const double* p, doub
     if constexpr (!VR) {
         const BallForm bf = whole_frame(X, p, g, pl);
         McSums acc;
-        for (int s = 0; s < N; s += 2) {
-            uint32_t w[4];
-            mc_philox<KEY>(q, m, (uint32_t)(s >> 1), key0, key1, w);
+        for (int s = 0; s < N; s += 4) {
+            uint32_t w[2][4];
+            mc_philox<KEY>(q, m, (uint32_t)(s >> 1), key0, key1, w[0]);
+            mc_philox<KEY>(q, m, (uint32_t)(s >> 1) + 1u, key0, key1, w[1]);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 4; ++h) {
                 if (s + h < N) {
                     uint32_t L[4];
-                    lambda_u(w, h, L);
+                    lambda_u(w[h >> 1], h & 1, L);
                     acc.add(bf, pl, d2, L);
                 }
             }

@@ -521,6 +521,15 @@ __device__ __forceinline__ int cut_mask(uint32_t c12) {
     return mk;
 }
 
+// the cut-mask buckets that some lane of the wave holds (bit b: mask b; mk < 0
+// for no hit), the same in every lane
+__device__ __forceinline__ uint32_t wave_buckets(int mk) {
+    uint32_t bits = mk >= 0 ? 1u << mk : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, off, 64);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)bits);
+}
+
 // Per outer tet: its hits per cut mask (which outer points cut the tet,
 // cnt[16 oi + mask]) and per class over the four points (cls[5 oi + c - 1]
 // for IN, CUT(0..3)).
@@ -540,8 +549,10 @@ __global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64
         const bool valid = j + lane < n;
         const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
         const int mk = cc ? cut_mask(cc) : -1;
+        const uint32_t held = wave_buckets(mk);
 #pragma unroll
-        for (int b = 0; b < 16; ++b) c[b] += __popcll(__ballot(mk == b));
+        for (int b = 0; b < 16; ++b)
+            if (held & (1u << b)) c[b] += __popcll(__ballot(mk == b));
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t cl = (cc >> (3 * k)) & 7u;
@@ -600,8 +611,11 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
         const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
         const int mk = cc ? cut_mask(cc) : -1;
         const int m = mk >= 0 ? cand_m[src + j + lane] : 0;
+        // only the buckets that some lane holds (a wave's candidates fall in a few)
+        const uint32_t held = wave_buckets(mk);
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
+            if (!(held & (1u << b))) continue;
             const bool mine = mk == b;
             const uint64_t mask = __ballot(mine);
             if (mine) {

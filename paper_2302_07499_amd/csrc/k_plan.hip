@@ -545,19 +545,29 @@ __global__ __launch_bounds__(256) void k_pair_count(int64_t n_outer, const int64
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
     uint32_t q[5] = {0u, 0u, 0u, 0u, 0u};
-    for (int64_t j = 0; j < n; j += 64) {
-        const bool valid = j + lane < n;
-        const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
-        const int mk = cc ? cut_mask(cc) : -1;
-        const uint32_t held = wave_buckets(mk);
+    // four rounds of 64 candidates per step, their loads issued together
+    for (int64_t j = 0; j < n; j += 4 * 64) {
+        uint32_t ccs[4];
 #pragma unroll
-        for (int b = 0; b < 16; ++b)
-            if (held & (1u << b)) c[b] += __popcll(__ballot(mk == b));
+        for (int u = 0; u < 4; ++u) {
+            const int64_t ix = j + 64 * u + lane;
+            ccs[u] = ix < n ? cand_code[src + ix] : 0u;
+        }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t cl = (cc >> (3 * k)) & 7u;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t ix = j + 64 * u + lane;
+            const uint32_t cc = ix < n ? code12(strategy_code(ccs[u], strategy)) : 0u;
+            const int mk = cc ? cut_mask(cc) : -1;
+            const uint32_t held = wave_buckets(mk);
 #pragma unroll
-            for (int t = 0; t < 5; ++t) q[t] += cl == (uint32_t)(t + 1) ? 1u : 0u;
+            for (int b = 0; b < 16; ++b)
+                if (held & (1u << b)) c[b] += __popcll(__ballot(mk == b));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t cl = (cc >> (3 * k)) & 7u;
+#pragma unroll
+                for (int t = 0; t < 5; ++t) q[t] += cl == (uint32_t)(t + 1) ? 1u : 0u;
+            }
         }
     }
 #pragma unroll
@@ -592,13 +602,15 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     if (oi >= n_outer) return;
     const int64_t src = cand_off[oi], n = cand_n[oi];
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    int64_t c[16];
+    // group sizes (from k_pair_count) and starts, within the outer tet's list
+    int c[16];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) c[b] = cnt[oi * 16 + b];  // from k_pair_count
+    for (int b = 0; b < 16; ++b) c[b] = (int)cnt[oi * 16 + b];
     // group order: 15 | 14 13 11 7 | 12 10 9 6 5 3 | 8 4 2 1 | 0
     const int order[16] = {15, 14, 13, 11, 7, 12, 10, 9, 6, 5, 3, 8, 4, 2, 1, 0};
-    int64_t base[16];
-    int64_t run = pair_off[oi];
+    const int64_t p0 = pair_off[oi];
+    int base[16];
+    int run = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         base[order[i]] = run;
@@ -606,24 +618,41 @@ __global__ __launch_bounds__(256) void k_pair_compact(int64_t n_outer, const int
     }
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
-    for (int64_t j = 0; j < n; j += 64) {
-        const bool valid = j + lane < n;
-        const uint32_t cc = valid ? code12(strategy_code(cand_code[src + j + lane], strategy)) : 0u;
-        const int mk = cc ? cut_mask(cc) : -1;
-        const int m = mk >= 0 ? cand_m[src + j + lane] : 0;
-        // only the buckets that some lane holds (a wave's candidates fall in a few)
-        const uint32_t held = wave_buckets(mk);
+    // four rounds of 64 candidates per step: their loads are issued together,
+    // then the rounds are placed in candidate order
+    for (int64_t j = 0; j < n; j += 4 * 64) {
+        uint32_t ccs[4];
+        int mks[4], ms[4];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            if (!(held & (1u << b))) continue;
-            const bool mine = mk == b;
-            const uint64_t mask = __ballot(mine);
-            if (mine) {
-                const int64_t pos = base[b] + c[b] + __popcll(mask & lt);
-                pair_m[pos] = m;
-                pair_cls[pos] = (uint16_t)cc;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t ix = j + 64 * u + lane;
+            ccs[u] = ix < n ? cand_code[src + ix] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t ix = j + 64 * u + lane;
+            ccs[u] = ix < n ? code12(strategy_code(ccs[u], strategy)) : 0u;
+            mks[u] = ccs[u] ? cut_mask(ccs[u]) : -1;
+            ms[u] = mks[u] >= 0 ? cand_m[src + ix] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t cc = ccs[u];
+            const int mk = mks[u], m = ms[u];
+            // only the buckets that some lane holds (a wave's candidates fall in a few)
+            const uint32_t held = wave_buckets(mk);
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                if (!(held & (1u << b))) continue;
+                const bool mine = mk == b;
+                const uint64_t mask = __ballot(mine);
+                if (mine) {
+                    const int64_t pos = p0 + base[b] + c[b] + __popcll(mask & lt);
+                    pair_m[pos] = m;
+                    pair_cls[pos] = (uint16_t)cc;
+                }
+                c[b] += __popcll(mask);
             }
-            c[b] += __popcll(mask);
         }
     }
 }

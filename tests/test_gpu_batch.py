@@ -9,6 +9,8 @@ import pytest
 import helpers as H
 import meshgen as mg
 
+FP32_TOL = 1e-6  # the form reaches about 1e-7 of the row scale on outer subsets (float subtet moments)
+
 pytestmark = pytest.mark.gpu
 
 
@@ -147,7 +149,7 @@ def test_batched_workload_subset_vs_oracle(dev, orc):
         H.pattern_equal(g, o)
         e = H.value_errors(g, o)
         _say(f"batched mesh {i} n={pb.mesh.n} d/h={pb.info['delta_over_h']:.0f} fp32-local errors {e}")
-        assert e["ff_abs"] <= 1e-5 and e["fc_abs"] <= 1e-5 and e["rhs"] <= 1e-5, (i, e)
+        assert e["ff_abs"] <= FP32_TOL and e["fc_abs"] <= FP32_TOL and e["rhs"] <= FP32_TOL, (i, e)
     batch.destroy()
 
 

@@ -2,7 +2,7 @@
 
 Bars: classification, pair lists and CSR pattern bit-exact; FP64 entries
 within 1e-12 of the row scale (and 1e-12 relative on entries above 1e-6 of
-it); FP32-local entries within 1e-5 of the row scale; CG solutions within
+it); FP32-local entries within 1e-6 of the row scale; CG solutions within
 1e-9 relative.
 """
 import os

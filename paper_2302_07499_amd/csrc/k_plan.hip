@@ -13,48 +13,70 @@ __device__ __forceinline__ unsigned long long ordered_bits(double x) {
 }
 
 // per tet: validate indices, gather coordinates (row-major [4][3]), volume
-// |det|/6, region, bounding-box minimum corner; global max extent and bbox.
+// |det|/6, region, bounding-box minimum corner; global max extent and bbox
+// (reduced over each wave first: one set of device-wide atomics per wave
+// instead of per tet, which all hit the same seven words).
 __global__ __launch_bounds__(256) void k_mesh_prep(MeshDev m, double* tetX, double* vol, uint8_t* region,
                                                    double* tet_min, unsigned long long* ext_bits,
                                                    unsigned long long* bbox_bits, unsigned* err) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m.K) return;
-    int32_t v[4];
-    bool ok = true;
-    for (int l = 0; l < 4; ++l) {
-        v[l] = m.tets[4 * e + l];
-        ok = ok && v[l] >= 0 && (int64_t)v[l] < m.V;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // ordered bits of the tet's box and extent; the identities for lanes without a valid tet
+    unsigned long long lo_b[3] = {~0ull, ~0ull, ~0ull}, hi_b[3] = {0ull, 0ull, 0ull}, ext_b = 0ull;
+    if (e < m.K) {
+        int32_t v[4];
+        bool ok = true;
+        for (int l = 0; l < 4; ++l) {
+            v[l] = m.tets[4 * e + l];
+            ok = ok && v[l] >= 0 && (int64_t)v[l] < m.V;
+        }
+        if (!ok) {
+            atomicOr(err, ERR_INDEX);
+            for (int i = 0; i < 12; ++i) tetX[12 * e + i] = 0.0;
+            vol[e] = 0.0;
+            region[e] = 0;
+            for (int i = 0; i < 3; ++i) tet_min[3 * e + i] = 0.0;
+        } else {
+            double X[12];
+            for (int l = 0; l < 4; ++l)
+                for (int i = 0; i < 3; ++i) X[3 * l + i] = m.coords[3 * (int64_t)v[l] + i];
+            for (int i = 0; i < 12; ++i) tetX[12 * e + i] = X[i];
+            double V6 = fabs(orient3(X, X + 3, X + 6, X + 9)) / 6.0;
+            vol[e] = V6;
+            if (!(V6 > 0.0)) atomicOr(err, ERR_VOLUME);
+            bool anyfree = false;
+            for (int l = 0; l < 4; ++l) anyfree = anyfree || (m.vfree[v[l]] != 0);
+            uint8_t rg = m.region_in ? (m.region_in[e] ? 1 : 0) : (anyfree ? 1 : 0);
+            if (!rg && anyfree) atomicOr(err, ERR_REGION);
+            region[e] = rg;
+            double ext = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                double lo = fmin(fmin(X[i], X[3 + i]), fmin(X[6 + i], X[9 + i]));
+                double hi = fmax(fmax(X[i], X[3 + i]), fmax(X[6 + i], X[9 + i]));
+                tet_min[3 * e + i] = lo;
+                ext = fmax(ext, hi - lo);
+                lo_b[i] = ordered_bits(lo);
+                hi_b[i] = ordered_bits(hi);
+            }
+            ext_b = ordered_bits(ext);
+        }
     }
-    if (!ok) {
-        atomicOr(err, ERR_INDEX);
-        for (int i = 0; i < 12; ++i) tetX[12 * e + i] = 0.0;
-        vol[e] = 0.0;
-        region[e] = 0;
-        for (int i = 0; i < 3; ++i) tet_min[3 * e + i] = 0.0;
-        return;
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const unsigned long long ol = __shfl_xor(lo_b[i], off, 64), oh = __shfl_xor(hi_b[i], off, 64);
+            lo_b[i] = ol < lo_b[i] ? ol : lo_b[i];
+            hi_b[i] = oh > hi_b[i] ? oh : hi_b[i];
+        }
+        const unsigned long long ox = __shfl_xor(ext_b, off, 64);
+        ext_b = ox > ext_b ? ox : ext_b;
     }
-    double X[12];
-    for (int l = 0; l < 4; ++l)
-        for (int i = 0; i < 3; ++i) X[3 * l + i] = m.coords[3 * (int64_t)v[l] + i];
-    for (int i = 0; i < 12; ++i) tetX[12 * e + i] = X[i];
-    double V6 = fabs(orient3(X, X + 3, X + 6, X + 9)) / 6.0;
-    vol[e] = V6;
-    if (!(V6 > 0.0)) atomicOr(err, ERR_VOLUME);
-    bool anyfree = false;
-    for (int l = 0; l < 4; ++l) anyfree = anyfree || (m.vfree[v[l]] != 0);
-    uint8_t rg = m.region_in ? (m.region_in[e] ? 1 : 0) : (anyfree ? 1 : 0);
-    if (!rg && anyfree) atomicOr(err, ERR_REGION);
-    region[e] = rg;
-    double ext = 0.0;
-    for (int i = 0; i < 3; ++i) {
-        double lo = fmin(fmin(X[i], X[3 + i]), fmin(X[6 + i], X[9 + i]));
-        double hi = fmax(fmax(X[i], X[3 + i]), fmax(X[6 + i], X[9 + i]));
-        tet_min[3 * e + i] = lo;
-        ext = fmax(ext, hi - lo);
-        atomicMin(&bbox_bits[i], ordered_bits(lo));
-        atomicMax(&bbox_bits[3 + i], ordered_bits(hi));
+    if ((threadIdx.x & 63) == 0 && ext_b != 0ull) {
+        for (int i = 0; i < 3; ++i) {
+            atomicMin(&bbox_bits[i], lo_b[i]);
+            atomicMax(&bbox_bits[3 + i], hi_b[i]);
+        }
+        atomicMax(ext_bits, ext_b);
     }
-    atomicMax(ext_bits, ordered_bits(ext));
 }
 
 __global__ void k_init_bits(unsigned long long* ext_bits, unsigned long long* bbox_bits) {

@@ -154,7 +154,10 @@ void nlfem_rule_constants(double *alpha, double *beta);
  * ball exactly in FP64 (IN / CUT(n_in) / OUT; Def. "simplex's dividing
  * strategy"), and builds the local vertex set of every outer tet, the
  * vertex-keyed lists that gather each matrix row, and the CSR pattern of the
- * free rows.  Mesh and mask are read during the call only.
+ * free rows.  Mesh and mask are read during the call only.  The call's
+ * temporaries (the largest: the CSR pattern's row buffer, at least
+ * 8 |Ve|max bytes per free row, |Ve|max the largest local vertex set) go back
+ * to the context's cache when it returns; nlfem_trim releases them.
  * Horizons whose local vertex sets or matrix rows do not fit in LDS (in 3D
  * about delta > 5h) keep those fixed-point sums in device memory instead
  * (slower, the same results); the environment variable NLFEM_GLOBAL_SUMS=1

@@ -161,7 +161,9 @@ void nlfem_rule_constants(double *alpha, double *beta);
  * Horizons whose local vertex sets or matrix rows do not fit in LDS (in 3D
  * about delta > 5h) keep those fixed-point sums in device memory instead
  * (slower, the same results); the environment variable NLFEM_GLOBAL_SUMS=1
- * forces that form for any plan (for checks).  Batches need the LDS form.  */
+ * forces that form for any plan (for checks).  Batches need the LDS form.
+ * NLFEM_ROW_STRIDE=<words> (a power of two, for checks) starts the CSR
+ * pattern's row buffer that narrow, so that its overflow retry runs.        */
 nlfem_status nlfem_plan_create(nlfem_ctx *ctx, const nlfem_mesh *mesh, const nlfem_params *params,
                                nlfem_plan **plan);
 

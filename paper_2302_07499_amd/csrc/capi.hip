@@ -425,6 +425,12 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     // not fit
     int row_cap = (int)std::max<int64_t>(512, next_pow2(4 * (int64_t)std::max(pl->umax, 1)));
     int row_stride = row_cap / 2;
+    // NLFEM_ROW_STRIDE=<words> (a power of two, for checks) starts narrower, so
+    // that the overflow retry runs
+    if (const char* rs = std::getenv("NLFEM_ROW_STRIDE")) {
+        const long v = std::strtol(rs, nullptr, 10);
+        if (v >= 1 && v <= row_cap / 2 && (v & (v - 1)) == 0) row_stride = (int)v;
+    }
     std::unique_ptr<Tmp> t_rows;  // [nf][row_stride] each row's columns between the two passes
     while (true) {
         if ((size_t)row_cap * 4 + 2048 > c->lds_max) return fail(c, NLFEM_E_UNSUPPORTED, "matrix row too large for LDS");

@@ -127,6 +127,22 @@ def test_plain_cg_device_poll_and_plan_form(dev, plain):
         assert not ok3 and it3 == cap and rr3 > 1e-10
 
 
+def test_row_buffer_overflow_retry(dev, plain):
+    """A row buffer far too narrow for the CSR rows (16 words a row, set by
+    NLFEM_ROW_STRIDE) makes the count pass report the overflow and run again
+    with wider strides; the pattern and values are bitwise those of the
+    plain plan."""
+    pb, plan, s, g, o = plain
+    os.environ["NLFEM_ROW_STRIDE"] = "16"
+    try:
+        plan2, s2, g2 = _gpu_system(dev, mg.plain_problem())
+    finally:
+        del os.environ["NLFEM_ROW_STRIDE"]
+    for k in ["ff_row_ptr", "ff_col", "fc_row_ptr", "fc_col", "ff_val", "fc_val", "rhs"]:
+        assert np.array_equal(g[k], g2[k]), k
+    plan2.destroy()
+
+
 def test_cg_breakdown_on_indefinite_matrix(dev):
     """An indefinite matrix makes p.Ap <= 0: the solve stops at once with
     NLFEM_E_NOT_CONVERGED and a breakdown message instead of running to the cap."""

@@ -152,9 +152,10 @@ __global__ void k_cell_start(const uint64_t* skeys, int64_t K, int64_t n_cells, 
 // corner t lies within one cell side below y on every axis.  A cell row
 // (cy, cz) is visited only if the slab of possible y over that row comes
 // closer than R to c, and then only over the x cells that can hold t.  Cell
-// boundaries are widened by 1e-6 cells and one guard cell on each end of a
-// range absorbs rounding of the cell index, so the candidate set contains
-// every tet that the exact test can find.
+// boundaries and the x ranges are widened by 1e-6 cells (the rounding of a
+// cell index, on either side, is below 1e-13 cells; R carries 1e-7 relative
+// for the rounding of the chord) and the row ranges by one guard row, so the
+// candidate set contains every tet that the exact test can find.
 struct CandBall {
     double c[3];
     double R;
@@ -195,8 +196,8 @@ __device__ __forceinline__ bool row_range(const CandBall& b, const Grid& g, int 
     const double rem = b.R * b.R - (dy * dy + dz * dz);
     if (!(rem > 0.0)) return false;
     const double hw = sqrt(rem);
-    x0 = clampi(floor((b.c[0] - hw - g.cs - g.ox) / g.cs) - 1.0, g.nx);
-    x1 = clampi(floor((b.c[0] + hw - g.ox) / g.cs) + 1.0, g.nx);
+    x0 = clampi(floor((b.c[0] - hw - g.cs - g.ox) / g.cs - 1e-6), g.nx);
+    x1 = clampi(floor((b.c[0] + hw - g.ox) / g.cs + 1e-6), g.nx);
     return true;
 }
 

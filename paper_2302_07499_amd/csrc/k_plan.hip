@@ -153,9 +153,10 @@ __global__ void k_cell_start(const uint64_t* skeys, int64_t K, int64_t n_cells, 
 // (cy, cz) is visited only if the slab of possible y over that row comes
 // closer than R to c, and then only over the x cells that can hold t.  Cell
 // boundaries and the x ranges are widened by 1e-6 cells (the rounding of a
-// cell index, on either side, is below 1e-13 cells; R carries 1e-7 relative
-// for the rounding of the chord) and the row ranges by one guard row, so the
-// candidate set contains every tet that the exact test can find.
+// cell index, on either side, is below 1e-8 cells: a few roundings of at most
+// 2^-53 of a value below 2^24 cells; R carries 1e-7 relative for the rounding
+// of the chord) and the row ranges by one guard row, so the candidate set
+// contains every tet that the exact test can find.
 struct CandBall {
     double c[3];
     double R;

@@ -104,3 +104,33 @@ def test_sanitizer_build_reports_a_heap_overflow(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode != 0
     assert "AddressSanitizer" in r.stderr and "heap-buffer-overflow" in r.stderr
+
+
+def test_hip_host_sanitizer_flags_report_undefined_behaviour(tmp_path):
+    """The flags tests/native/build_host_sanitized.py gives hipcc (the
+    sanitizer behind -Xarch_host, host code only) on a host-only program with
+    a signed overflow: the run must fail with an UndefinedBehaviorSanitizer
+    report, so the clean GPU run of the library's host code means something."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("build_host_sanitized",
+                                                  os.path.join(HERE, "native", "build_host_sanitized.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    if not os.path.exists(mod.libbuild.HIPCC):
+        pytest.skip("no hipcc")
+    src = tmp_path / "overflow.hip"
+    src.write_text("#include <hip/hip_runtime.h>\n"
+                   "#include <climits>\n"
+                   "int main(int argc, char **argv) {\n"
+                   "    int v = INT_MAX - 1 + argc;\n"
+                   "    v += argc;\n"
+                   "    return v == 7;\n"
+                   "}\n")
+    exe = str(tmp_path / "overflow")
+    r = subprocess.run([mod.libbuild.HIPCC, *mod.libbuild.FLAGS, *mod.HOST_SAN, "-o", exe, str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60,
+                       env=dict(os.environ, UBSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode != 0
+    assert "runtime error" in r.stderr and "overflow" in r.stderr, r.stderr[-2000:]

@@ -78,7 +78,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
+        # NLFEM_ORACLE_LIB: a copy of the oracle built elsewhere (the mutation
+        # tests point it at copies with a planted mistake)
+        L = C.CDLL(os.environ.get("NLFEM_ORACLE_LIB") or _LIB)
         P = C.c_void_p
         L.or_rule_constants.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.or_philox4x32_10.argtypes = [P, P, P]

@@ -163,7 +163,9 @@ void nlfem_rule_constants(double *alpha, double *beta);
  * (slower, the same results); the environment variable NLFEM_GLOBAL_SUMS=1
  * forces that form for any plan (for checks).  Batches need the LDS form.
  * NLFEM_ROW_STRIDE=<words> (a power of two, for checks) starts the CSR
- * pattern's row buffer that narrow, so that its overflow retry runs.        */
+ * pattern's row buffer that narrow, so that its overflow retry runs, and
+ * NLFEM_VE_STRIDE=<entries> sets the local vertex sets' hand-off buffer, so
+ * that sets longer than it take the fill pass.                               */
 nlfem_status nlfem_plan_create(nlfem_ctx *ctx, const nlfem_mesh *mesh, const nlfem_params *params,
                                nlfem_plan **plan);
 

@@ -347,17 +347,33 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     // ---- local vertex sets ---------------------------------------------------
     TMP(t_ucount, (size_t)(no + 1) * 8);
     int hash_cap = (int)std::max<int64_t>(256, next_pow2(2 * (pl->max_pairs + 16)));
+    // the count pass leaves each set in a hand-off buffer of vstride entries
+    // per outer tet (a set holds fewer vertices than half its outer tet's
+    // pairs on the measured workloads), if that takes at most 2 GiB; a longer
+    // set, or no buffer, leaves the sets to the fill pass.  NLFEM_VE_STRIDE
+    // (a power of two, for checks) sets the stride.
+    int vstride = (int)next_pow2(std::max<int64_t>(64, (pl->max_pairs + 1) / 2));
+    if (const char* vs = std::getenv("NLFEM_VE_STRIDE")) {
+        const long v = std::strtol(vs, nullptr, 10);
+        if (v >= 1 && v <= (1 << 24) && (v & (v - 1)) == 0) vstride = (int)v;
+    }
+    std::unique_ptr<Tmp> t_vbuf;
+    if ((size_t)std::max<int64_t>(no, 1) * (size_t)vstride * 4 <= ((size_t)2 << 30)) {
+        t_vbuf.reset(new Tmp(c, (size_t)std::max<int64_t>(no, 1) * (size_t)vstride * 4));
+        if (!t_vbuf->p) t_vbuf.reset();  // no room: the fill pass builds the sets
+    }
     while (true) {
         if ((size_t)hash_cap * 4 > c->lds_max)
             return fail(c, NLFEM_E_UNSUPPORTED, "local vertex set too large for LDS");
         HIPCHK(launch_fill_i32((int32_t*)t_err.p, 16, 0, s));
         HIPCHK(launch_pattern(false, pl->tets, no, pl->pair_off, pl->pair_m, hash_cap, t_ucount.as<int64_t>(), nullptr,
-                              nullptr, t_err.as<unsigned>(), s));
+                              nullptr, t_vbuf ? t_vbuf->as<int32_t>() : nullptr, vstride, t_err.as<unsigned>(), s));
         HIPCHK(hipMemcpyAsync(&errbits, t_err.p, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (!(errbits & ERR_HASH)) break;
         hash_cap *= 2;
     }
+    const bool ve_handoff = t_vbuf && !(errbits & ERR_VEBUF);
     ALLOC(pl->ve_off, int64_t, no + 2);
     HIPCHK(exclusive_scan_i64(t_ucount.as<int64_t>(), pl->ve_off, no, t_scan2.p, s));
     HIPCHK(reduce_max_i64(t_ucount.as<int64_t>(), no, (int64_t*)(small + 8), s));
@@ -374,8 +390,12 @@ nlfem_status build_plan(nlfem_ctx* c, nlfem_plan* pl, const nlfem_mesh* mesh, co
     if (VT >= (int64_t)0xFFFFFFFFll || 4 * K >= (int64_t)0xFFFFFFFFll)
         return fail(c, NLFEM_E_UNSUPPORTED, "more than 2^32 local vertex set entries");
     ALLOC(pl->ve_ids, int32_t, VT + 1);
-    HIPCHK(launch_pattern(true, pl->tets, no, pl->pair_off, pl->pair_m, hash_cap, t_ucount.as<int64_t>(), pl->ve_off,
-                          pl->ve_ids, t_err.as<unsigned>(), s));
+    if (ve_handoff)
+        HIPCHK(launch_ve_copy(no, pl->ve_off, t_vbuf->as<int32_t>(), vstride, pl->ve_ids, s));
+    else
+        HIPCHK(launch_pattern(true, pl->tets, no, pl->pair_off, pl->pair_m, hash_cap, t_ucount.as<int64_t>(),
+                              pl->ve_off, pl->ve_ids, nullptr, 0, t_err.as<unsigned>(), s));
+    t_vbuf.reset();
     // ---- vertex -> tets and vertex -> local vertex set entries -------------
     ALLOC(pl->vt_off, int64_t, V + 2);
     ALLOC(pl->vt_val, uint32_t, 4 * K + 1);

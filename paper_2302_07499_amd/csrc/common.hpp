@@ -32,7 +32,8 @@ struct Grid {
 };
 
 // Error bits raised by device validation.
-enum : unsigned { ERR_INDEX = 1u, ERR_VOLUME = 2u, ERR_REGION = 4u, ERR_HASH = 8u, ERR_FIXED = 16u, ERR_ROWBUF = 32u };
+enum : unsigned { ERR_INDEX = 1u, ERR_VOLUME = 2u, ERR_REGION = 4u, ERR_HASH = 8u, ERR_FIXED = 16u, ERR_ROWBUF = 32u,
+                  ERR_VEBUF = 64u };
 
 // ---- launch wrappers (each returns the hipError_t of its launch) ----------
 // scans / sorts (k_sort.hip)
@@ -91,11 +92,16 @@ hipError_t launch_pair_compact(int64_t n_outer, const int64_t* cand_off, const i
 // pairs per outer tet into tot; class totals added to cls_tot[1..5] (zeroed by the caller)
 hipError_t launch_pair_totals(const int64_t* cnt, const uint32_t* cls, int64_t n_outer, int64_t* tot,
                               unsigned long long* cls_tot, hipStream_t s);
-// local vertex sets Ve of the outer tets: count pass writes ucount[oi], fill
-// pass writes the sorted sets at ve_off
+// local vertex sets Ve of the outer tets: count pass writes ucount[oi] (and,
+// given vbuf, the sorted sets there, vstride entries per outer tet, ERR_VEBUF
+// for a longer set), fill pass writes the sorted sets at ve_off
 hipError_t launch_pattern(bool fill, const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
                           const int32_t* pair_m, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
-                          unsigned* err, hipStream_t s);
+                          int32_t* vbuf, int vstride, unsigned* err, hipStream_t s);
+// local vertex sets from the count pass's hand-off buffer (vstride entries per
+// outer tet) to ve_ids at ve_off
+hipError_t launch_ve_copy(int64_t n_outer, const int64_t* ve_off, const int32_t* vbuf, int vstride, int32_t* ve_ids,
+                          hipStream_t s);
 
 // numeric kernels (k_numeric.hip)
 struct IntegrateArgs {

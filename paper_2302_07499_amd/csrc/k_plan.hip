@@ -718,13 +718,17 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 // (spatially ordered meshes: always), the set is a bitmap over that range,
 // read out in ascending order through a block prefix sum of word popcounts;
 // otherwise an LDS hash set sorted by a bitonic network.  The count pass
-// writes |Ve|, the fill pass the set itself at ve_off.
+// writes |Ve| and, given a hand-off buffer (vbuf, vstride entries per outer
+// tet), the set itself there, for k_ve_copy to move to ve_off; a set longer
+// than vstride sets ERR_VEBUF and the fill pass builds the sets again at
+// ve_off instead.
 constexpr int kBitmapWords = 2048;
 
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
                                                  const int32_t* pair_m, int hash_cap, int64_t* ucount,
-                                                 const int64_t* ve_off, int32_t* ve_ids, unsigned* err) {
+                                                 const int64_t* ve_off, int32_t* ve_ids, int32_t* vbuf, int vstride,
+                                                 unsigned* err) {
     extern __shared__ uint32_t hs[];
     __shared__ int sU, sLo, sHi;
     __shared__ int wsum[256];
@@ -777,17 +781,25 @@ __global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, int64_t n_
             wsum[t] += add;
             __syncthreads();
         }
-        if (!FILL) {
-            if (t == 0) ucount[oi] = wsum[255];
-            return;
+        const int U = wsum[255];
+        int32_t* out;
+        if (FILL) {
+            out = ve_ids + ve_off[oi];
+        } else {
+            if (t == 0) ucount[oi] = U;
+            if (!vbuf) return;
+            if (U > vstride) {
+                if (t == 0) atomicOr(err, ERR_VEBUF);
+                return;
+            }
+            out = vbuf + oi * (int64_t)vstride;
         }
         int pos = wsum[t] - c;
-        const int64_t vb = ve_off[oi];
         for (int w = w0; w < w1; ++w) {
             uint32_t bits = hs[w];
             while (bits) {
                 const int bb = __ffs(bits) - 1;
-                ve_ids[vb + pos++] = vlo + 32 * w + bb;
+                out[pos++] = vlo + 32 * w + bb;
                 bits &= bits - 1u;
             }
         }
@@ -834,12 +846,28 @@ __global__ __launch_bounds__(256) void k_pattern(const int32_t* tets, int64_t n_
         if (hs[i] != EMPTY && (i == hash_cap - 1 || hs[i + 1] == EMPTY)) sU = i + 1;
     __syncthreads();
     const int U = sU;
-    if (!FILL) {
+    int32_t* out;
+    if (FILL) {
+        out = ve_ids + ve_off[oi];
+    } else {
         if (t == 0) ucount[oi] = U;
-        return;
+        if (!vbuf) return;
+        if (U > vstride) {
+            if (t == 0) atomicOr(err, ERR_VEBUF);
+            return;
+        }
+        out = vbuf + oi * (int64_t)vstride;
     }
-    const int64_t vb = ve_off[oi];
-    for (int i = t; i < U; i += 256) ve_ids[vb + i] = (int32_t)hs[i];
+    for (int i = t; i < U; i += 256) out[i] = (int32_t)hs[i];
+}
+
+// the sets the count pass left in the hand-off buffer, to their place at ve_off
+__global__ __launch_bounds__(256) void k_ve_copy(const int64_t* ve_off, const int32_t* vbuf, int vstride,
+                                                 int32_t* ve_ids) {
+    const int64_t oi = blockIdx.x;
+    const int64_t b = ve_off[oi], U = ve_off[oi + 1] - b;
+    const int32_t* src = vbuf + oi * (int64_t)vstride;
+    for (int64_t i = threadIdx.x; i < U; i += 256) ve_ids[b + i] = src[i];
 }
 
 inline unsigned blocks_for(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -938,15 +966,23 @@ hipError_t launch_pair_totals(const int64_t* cnt, const uint32_t* cls, int64_t n
 
 hipError_t launch_pattern(bool fill, const int32_t* tets, int64_t n_outer, const int64_t* pair_off,
                           const int32_t* pair_m, int hash_cap, int64_t* ucount, const int64_t* ve_off, int32_t* ve_ids,
-                          unsigned* err, hipStream_t s) {
+                          int32_t* vbuf, int vstride, unsigned* err, hipStream_t s) {
     if (n_outer <= 0) return hipSuccess;
+    if (vbuf && vstride <= 0) return hipErrorInvalidValue;
     size_t sh = (size_t)(hash_cap > kBitmapWords ? hash_cap : kBitmapWords) * sizeof(uint32_t);
     if (fill)
         k_pattern<true><<<(unsigned)n_outer, 256, sh, s>>>(tets, n_outer, pair_off, pair_m, hash_cap, ucount, ve_off,
-                                                          ve_ids, err);
+                                                          ve_ids, nullptr, 0, err);
     else
         k_pattern<false><<<(unsigned)n_outer, 256, sh, s>>>(tets, n_outer, pair_off, pair_m, hash_cap, ucount,
-                                                           ve_off, ve_ids, err);
+                                                           ve_off, ve_ids, vbuf, vstride, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ve_copy(int64_t n_outer, const int64_t* ve_off, const int32_t* vbuf, int vstride, int32_t* ve_ids,
+                          hipStream_t s) {
+    if (n_outer <= 0) return hipSuccess;
+    k_ve_copy<<<(unsigned)n_outer, 256, 0, s>>>(ve_off, vbuf, vstride, ve_ids);
     return hipGetLastError();
 }
 

@@ -109,7 +109,12 @@ size_t estimate_footprint(const Request& r) {
     // the CSR pattern keeps each row's columns between its two passes: half
     // the row's hash set (a power of two of at least 4 |Ve| slots)
     const double rowcap = std::max(512.0, std::exp2(std::ceil(std::log2(4.0 * std::max(vpo, 1.0)))));
-    const double pattern = retained + VT * 24.0 + (double)nf * (rowcap / 2.0) * 4.0;
+    // the local vertex sets pass through a hand-off buffer of a power of two
+    // of at least half the pairs per outer tet, per outer tet (when that
+    // stays within 2 GiB), before the CSR pattern's row buffer exists
+    const double vstride = std::max(64.0, std::exp2(std::ceil(std::log2(std::max(ppo * 0.5, 1.0)))));
+    const double vbuf = n_outer * vstride * 4.0 <= 2147483648.0 ? n_outer * vstride * 4.0 : 0.0;
+    const double pattern = retained + VT * 24.0 + std::max((double)nf * (rowcap / 2.0) * 4.0, vbuf);
     const double numeric = retained + nnz * 12.0 + nf * 48.0;
     const double est = (mesh + std::max(classify, std::max(pattern, numeric))) * 1.25 + (double)(8 << 20);
     return (size_t)std::min(est, 1e18);

@@ -143,6 +143,21 @@ def test_row_buffer_overflow_retry(dev, plain):
     plan2.destroy()
 
 
+def test_local_vertex_set_handoff_fallback(dev, plain):
+    """Local vertex sets longer than the count pass's hand-off buffer (16
+    entries a set, set by NLFEM_VE_STRIDE) are built again by the fill pass;
+    the plain plan takes the hand-off; pattern and values bitwise equal."""
+    pb, plan, s, g, o = plain
+    os.environ["NLFEM_VE_STRIDE"] = "16"
+    try:
+        plan2, s2, g2 = _gpu_system(dev, mg.plain_problem())
+    finally:
+        del os.environ["NLFEM_VE_STRIDE"]
+    for k in ["ff_row_ptr", "ff_col", "fc_row_ptr", "fc_col", "ff_val", "fc_val", "rhs"]:
+        assert np.array_equal(g[k], g2[k]), k
+    plan2.destroy()
+
+
 def test_cg_breakdown_on_indefinite_matrix(dev):
     """An indefinite matrix makes p.Ap <= 0: the solve stops at once with
     NLFEM_E_NOT_CONVERGED and a breakdown message instead of running to the cap."""
